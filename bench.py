@@ -1,0 +1,211 @@
+"""Throughput of the fused inpaint path on one MI355X.
+
+One step = one whole inpaint of a 2048x2048 synthetic image (80% random loss
+plus five elliptic blotches) with N = 32 orientations, beta = 1, T = 4 and
+400 Crank-Nicolson steps, FP32 FFTs and solve with FP64-precomputed
+propagators: orient -> lift + row FFT -> column FFT -> per-mode propagation ->
+inverse column FFT -> inverse row FFT + max projection.  Inputs are resident
+in device memory before timing starts; the propagator table is computed in the
+first (cold, untimed) call and reused, as the method allows.
+
+Prints one JSON line (the metric is lifted voxel-steps per second:
+M^2 * N * n_steps per inpaint).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--no-cpu-baseline]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "lifted voxel-steps/s (px·N·steps) + ms per 2048² N=32 inpaint at stated rel-L2"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(M: int, N: int, real: int = 4) -> dict:
+    """Bytes each kernel of one inpaint must move (each input read once, each output written once).
+
+    V is the half-spectrum volume N (M/2+1) M complex values; the propagator
+    table holds (M/4+1)^2 frequency classes of (N/2)(N/2+1) values.
+    """
+    K = M // 2 + 1
+    c = 2 * real
+    V = N * K * M * c
+    MM = M * M
+    Q = M // 4 + 1
+    h = N // 2
+    table = Q * Q * h * (h + 1) * real
+    return {
+        "orient_row_fwd": MM * real + MM + K * M * c,
+        "orient_col": 3 * K * M * c,
+        "orient_row_inv": 2 * K * M * c + MM,
+        "lift_row_fwd": MM * real + 2 * MM + V,
+        "col_fft_fwd": 2 * V,
+        "solve": 2 * V + table,
+        "col_fft_inv": 2 * V,
+        "row_inv_max": V + MM * real,
+        "fill_max": MM * real,
+        "decode_max": 2 * MM * real,
+    }
+
+
+def cpu_baseline(case, crop: int) -> dict:
+    """The FP64 oracle on a crop of the same workload, timed on the host cores."""
+    import oracle as O
+    from oracle import se2n_oracle
+
+    f = case["f"][:crop, :crop].astype(np.float32).astype(np.float64)
+    m = case["mask"][:crop, :crop]
+    t0 = time.perf_counter()
+    O.inpaint(f, m, case["N"], case["T"], case["beta"], case["n_steps"], sigma=case["sigma"])
+    dt = time.perf_counter() - t0
+    vs = crop * crop * case["N"] * case["n_steps"]
+    return {
+        "value": vs / dt,
+        "unit": "voxel-steps/s",
+        "cores": se2n_oracle.num_threads(),
+        "kind": "oracle",
+        "sample": f"FP64 oracle inpaint of the {crop}x{crop} top-left crop of the 2048^2 image, "
+                  f"N={case['N']}, T={case['T']}, {case['n_steps']} CN steps ({dt:.1f} s)",
+    }
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--beta", type=float, default=1.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-crop", type=int, default=512)
+    ap.add_argument("--no-fp64-check", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path is single-GPU (the multi-GPU split is a design "
+              "note, not built); run with --gpus 1", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1304_2062_amd import se2n, synth
+
+    case = synth.make_case("large")
+    case["beta"] = args.beta
+    M, N, T, n, beta, sigma = case["M"], case["N"], case["T"], case["n_steps"], case["beta"], case["sigma"]
+    dev = torch.device("cuda", 0)
+    torch.cuda.set_device(dev)
+    f = torch.from_numpy(case["f"].astype(np.float32)).to(dev)
+    mask = torch.from_numpy(case["mask"]).to(dev)
+    out = torch.empty((M, M), dtype=torch.float32, device=dev)
+    rmap = torch.empty((M, M), dtype=torch.uint8, device=dev)
+    plan = se2n.Plan(M, N, torch.float32)
+    plan.workspace()
+
+    def step():
+        plan.inpaint(f, mask, T, beta, n, sigma=sigma, out=out, rmap_out=rmap)
+
+    # cold call: includes the FP64 propagator precompute and its allocation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    plan.profile(True)
+    step()
+    torch.cuda.synchronize()
+    cold_ms = (time.perf_counter() - t0) * 1e3
+    cold_stats = plan.profile_stats()
+    plan.profile(False)
+    print(f"[bench] cold inpaint {cold_ms:.2f} ms (precompute "
+          f"{cold_stats.get('precompute', (0, 0.0))[1]:.2f} ms)", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ms_per_step = dt / args.steps * 1e3
+    voxel_steps = M * M * N * n
+    value = voxel_steps / (ms_per_step / 1e3)
+    print(f"[bench] warm inpaint {ms_per_step:.3f} ms -> {value:.3e} voxel-steps/s", file=sys.stderr, flush=True)
+
+    # per-kernel durations over the same number of steps, events on the launch stream
+    plan.profile(True)
+    for _ in range(args.steps):
+        step()
+    stats = plan.profile_stats()
+    plan.profile(False)
+    alg = algorithmic_bytes(M, N, 4)
+    kernels = {}
+    for name, (launches, total) in stats.items():
+        avg = total / launches
+        entry = {"launches": launches, "avg_ms": round(avg, 5)}
+        if name in alg:
+            gbs = alg[name] / (avg / 1e3) / 1e9
+            entry.update({"bytes": alg[name], "GB_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[name] = entry
+    dom = max((k for k in kernels if k in alg), key=lambda k: kernels[k]["avg_ms"] * kernels[k]["launches"])
+    achieved = kernels[dom]["GB_s"]
+    roofline = {"kernel": dom, "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None}
+    for k, v in sorted(kernels.items(), key=lambda kv: -kv[1]["avg_ms"] * kv[1]["launches"]):
+        print(f"[bench]   {k:16s} {v['avg_ms']:.4f} ms x{v['launches'] // args.steps}"
+              + (f"  {v['GB_s']:.0f} GB/s" if "GB_s" in v else ""), file=sys.stderr, flush=True)
+
+    # accuracy of the FP32 path against the FP64 GPU path on the same orientation map
+    rel = None
+    if not args.no_fp64_check:
+        p64 = se2n.Plan(M, N, torch.float64)
+        out64, _ = p64.inpaint(f.double(), mask, T, beta, n, sigma=sigma, rmap_in=rmap)
+        torch.cuda.synchronize()
+        rel = float(torch.linalg.norm(out.double() - out64) / torch.linalg.norm(out64))
+        p64.close()
+        print(f"[bench] FP32 vs FP64 rel-L2 {rel:.3e}", file=sys.stderr, flush=True)
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(case, args.cpu_crop)
+        print(f"[bench] cpu baseline {cpu['value']:.3e} voxel-steps/s on {cpu['cores']} threads",
+              file=sys.stderr, flush=True)
+
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "voxel-steps/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_per_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": "2048x2048 inpaint, N=32, beta=%g, T=4, 400 CN steps, 80%% loss + 5 blotches, "
+                        "FP32 with FP64 propagator precompute" % beta,
+            "M": M, "N": N, "beta": beta, "T": T, "n_steps": n, "sigma": sigma, "seed": case["seed"],
+        },
+        "rel_l2_vs_fp64": rel,
+        "cold_ms": cold_ms,
+        "precompute_ms": cold_stats.get("precompute", (0, None))[1],
+        "roofline": roofline,
+        "kernels": kernels,
+        "cpu_baseline": cpu,
+    }
+    plan.close()
+    print(json.dumps(line))
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

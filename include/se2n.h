@@ -1,0 +1,173 @@
+/*
+ * se2n.h - C ABI of the MI355X (gfx950) library for the semi-discrete SE(2,N)
+ * hypoelliptic diffusion of Boscain, Chertovskih, Gauthier and Remizov
+ * ("Hypoelliptic diffusion and human vision: a semi-discrete new twist").
+ *
+ * The calls follow the paper's statement of the problem: an image f on an
+ * M x M periodic grid with a set B of missing pixels is lifted to N discrete
+ * orientations, diffused by the semi-discrete operator, and projected back to
+ * the plane.
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - Every data pointer is DEVICE memory owned by the caller, contiguous,
+ *   row-major.  Images are [M][M] indexed [y][x] (x fastest); orientation
+ *   volumes are [N][M][M] indexed [r][y][x].
+ * - Real data (f, psi, out) has the plan's dtype: float for SE2N_F32, double
+ *   for SE2N_F64.  Masks and orientation maps are uint8.
+ * - mask[y][x] = 1 marks a missing pixel (the paper's bad set B), 0 a known one.
+ * - Orientation r stands for the angle e_r = 2*pi*r/N.
+ * - Every call only enqueues work on `stream` (a hipStream_t; NULL is the
+ *   default stream) and returns; nothing is synchronised.  Device faults
+ *   surface at the caller's next synchronisation.
+ * - Every call returns SE2N_OK (0) or a negative se2n_status.  All argument
+ *   checks happen on the host before anything is enqueued; a failed call
+ *   enqueues nothing and leaves a message in se2n_last_error().  The library
+ *   never aborts the process.
+ * - A plan may be used from one host thread / one stream at a time.
+ *
+ * Time scale: the library integrates d psi/dt = D psi with D the totally
+ * discrete operator of equation (FTE) (without its factor 1/2), i.e. per
+ * spatial frequency A_{k,l} = beta*L - M*diag_r((a^r_{k,l})^2).  This is the
+ * weighted operator Delta^(N) of Sec. "The weighting of the metric"; a time T_p
+ * in the paper's (FTE) clock is T = T_p/2 here, and alpha = beta (2 pi/N)^2.
+ */
+#ifndef SE2N_H
+#define SE2N_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SE2N_OK = 0,
+    SE2N_EINVAL = -1,       /* bad argument: size, pointer, parameter range  */
+    SE2N_EUNSUPPORTED = -2, /* valid for the paper, not supported by this build */
+    SE2N_ENOMEM = -3,       /* device allocation of a library-owned buffer failed */
+    SE2N_EHIP = -4,         /* a HIP runtime call or kernel launch failed */
+    SE2N_ESTATE = -5        /* plan destroyed or used inconsistently */
+} se2n_status;
+
+typedef enum { SE2N_F32 = 0, SE2N_F64 = 1 } se2n_dtype;
+
+/* Time integration of each decoupled N x N system (proof of Theorem 2):
+ * SE2N_CN    Crank-Nicolson with tau = T/n_steps (remark 2 after Theorem 2):
+ *            psi(T) = R(tau A)^n psi(0), R(z) = (1 + z/2)/(1 - z/2);
+ * SE2N_EXACT the exponential e^{T A} of equation (soleq). */
+typedef enum { SE2N_CN = 0, SE2N_EXACT = 1 } se2n_scheme;
+
+/* Projection to the plane (Sec. "A final inpainting algorithm ..."):
+ * maximum over orientations (the paper's preferred choice) or the mean. */
+typedef enum { SE2N_PROJ_MAX = 0, SE2N_PROJ_MEAN = 1 } se2n_proj;
+
+typedef struct se2n_plan_s *se2n_plan;
+
+/* Create a plan for M x M images and N orientations.
+ * M: 16 <= M <= 4096, M = 2^a 3^b with a >= 3 (the FFTs are mixed radix 2/3
+ *    and rows are processed in groups of 8).
+ * N: even, 4 <= N <= 64 (even N lets each per-mode system split into two
+ *    N/2 blocks, because the potential cos/sin^2 is pi-periodic, Sec. "The
+ *    weighting of the metric", remark about projectivization).
+ * The plan owns twiddle tables (allocated here) and a cache of per-frequency
+ * propagators (allocated on first use).  *out is set on success only.
+ * Errors: SE2N_EINVAL (null out, bad M or N, bad dtype), SE2N_ENOMEM, SE2N_EHIP. */
+int se2n_plan_create(se2n_plan *out, int M, int N, se2n_dtype dtype);
+
+/* Free every buffer the plan owns.  Waits for the device first (hipDeviceSynchronize).
+ * Passing NULL is SE2N_EINVAL. */
+int se2n_plan_destroy(se2n_plan plan);
+
+/* Bytes of device workspace that se2n_diffuse and se2n_inpaint need: the
+ * half-spectrum volume [N][M/2+1][M] of complex values plus small scratch.
+ * Returns 0 for a NULL plan. */
+size_t se2n_workspace_bytes(se2n_plan plan);
+
+/* Fill the propagator cache for (T, beta, n_steps, scheme) now instead of on
+ * the first diffusion (Remark 3 after Theorem 2: the matrices A_{k,l} are
+ * universal once M, N and beta are fixed, so their propagators are computed
+ * once).  The propagators are computed in FP64 on the device and stored in
+ * the plan's dtype.
+ * T >= 0, beta >= 0, n_steps >= 1 (ignored by SE2N_EXACT).
+ * Errors: SE2N_EINVAL, SE2N_ENOMEM, SE2N_EHIP. */
+int se2n_precompute(se2n_plan plan, double T, double beta, int n_steps,
+                    se2n_scheme scheme, void *stream);
+
+/* Orientation map of the corrupted image (Sec. "A final inpainting algorithm
+ * ...": Gaussian smoothing and gradient at the level of the FFT, nearest angle;
+ * the gradient is taken on the corrupted image as the paper does).
+ *   f      [M][M] real, mask [M][M] uint8 (1 = missing)
+ *   sigma  Gaussian width in pixels, > 0, applied as the Fourier multiplier
+ *          exp(-2 pi^2 sigma^2 (kbar^2 + lbar^2) / M^2)
+ *   rmap   [M][M] uint8 out: r = floor(theta N/(2 pi) + 1/2) mod N with
+ *          theta = atan2(g_y, g_x) + pi/2 the level-line direction of the
+ *          smoothed central-difference gradient (g_x, g_y).
+ *   workspace: at least se2n_workspace_bytes(plan) bytes.
+ * Errors: SE2N_EINVAL (null pointer, sigma <= 0), SE2N_EHIP. */
+int se2n_orient(se2n_plan plan, const void *f, const uint8_t *mask, double sigma,
+                uint8_t *rmap, void *workspace, void *stream);
+
+/* Lift: psi[r][y][x] = f[y][x]*(1-mask[y][x]) if rmap[y][x] == r, else 0.
+ *   psi [N][M][M] real out.  rmap values must be < N (not checked on device:
+ *   a larger value lifts the pixel to no orientation).
+ * Errors: SE2N_EINVAL, SE2N_EHIP. */
+int se2n_lift(se2n_plan plan, const void *f, const uint8_t *mask, const uint8_t *rmap,
+              void *psi, void *stream);
+
+/* Diffuse an orientation volume in place to time T (Theorem 2: FFT over
+ * (Z/MZ)^2 of every slice, the M^2 decoupled N-dimensional systems, inverse
+ * FFT).  psi [N][M][M] real, in/out.  workspace: se2n_workspace_bytes bytes.
+ * Parameters as in se2n_precompute; the propagators are taken from the cache
+ * or computed (FP64) on the stream first.
+ * Errors: SE2N_EINVAL, SE2N_ENOMEM, SE2N_EHIP. */
+int se2n_diffuse(se2n_plan plan, void *psi, double T, double beta, int n_steps,
+                 se2n_scheme scheme, void *workspace, void *stream);
+
+/* Project a volume to the plane: out[y][x] = max_r psi[r][y][x] or the mean.
+ * Errors: SE2N_EINVAL, SE2N_EHIP. */
+int se2n_project(se2n_plan plan, const void *psi, se2n_proj mode, void *out, void *stream);
+
+/* The whole path, fused so that the lifted volume never exists in real
+ * space: orient -> lift + row FFT -> column FFT -> per-mode propagation ->
+ * inverse column FFT -> inverse row FFT + projection.
+ *   rmap_in  optional [M][M] uint8: if non-NULL it is used instead of
+ *            computing the orientation map (values must be < N).
+ *   rmap_out optional [M][M] uint8: receives the orientation map used.
+ *   out      [M][M] real.
+ * Errors: as se2n_orient and se2n_diffuse. */
+int se2n_inpaint(se2n_plan plan, const void *f, const uint8_t *mask, double sigma,
+                 double T, double beta, int n_steps, se2n_scheme scheme, se2n_proj mode,
+                 const uint8_t *rmap_in, uint8_t *rmap_out, void *out, void *workspace,
+                 void *stream);
+
+/* Kernel timing.  While enabled, every kernel the plan launches is bracketed
+ * by two hipEvents recorded on the launch stream; se2n_profile_stats waits
+ * for the recorded events and returns, per kernel name, the number of
+ * launches and their summed duration.  Enabling (or disabling) clears the
+ * statistics.  Timing adds two event records per launch; leave it off in
+ * production.
+ * se2n_profile_stats: out may be NULL to query the count only; at most
+ * `capacity` entries are written; *count receives the number of kernels.
+ * Errors: SE2N_EINVAL, SE2N_EHIP. */
+typedef struct {
+    char name[32];
+    int launches;
+    double total_ms;
+} se2n_kernel_stat;
+
+int se2n_profile(se2n_plan plan, int enable);
+int se2n_profile_stats(se2n_plan plan, se2n_kernel_stat *out, int capacity, int *count);
+
+/* Message describing the last failure on the calling thread ("" if none). */
+const char *se2n_last_error(void);
+
+/* Library version string. */
+const char *se2n_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SE2N_H */

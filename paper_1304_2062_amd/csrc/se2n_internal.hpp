@@ -1,0 +1,88 @@
+// Internal declarations shared by the kernels and the host runtime.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "se2n_fft.hpp"
+
+namespace se2n {
+
+// Elements of an LDS transform batch that each thread stages in registers.
+template <class R>
+__host__ __device__ constexpr int ept() { return sizeof(R) == 4 ? 16 : 8; }
+
+enum { SRC_LIFT = 0, SRC_VOLUME = 1, SRC_IMAGE = 2 };
+enum { DST_MAX = 0, DST_SUM = 1, DST_VOLUME = 2, DST_ORIENT = 3 };
+
+// Order-preserving map of a real value to an unsigned integer, so that a
+// maximum over workgroups can be taken with integer atomics.  0 is below the
+// image of every real value.
+template <class R>
+struct Enc;
+template <>
+struct Enc<float> {
+    using U = unsigned int;
+    __device__ static U encode(float v) {
+        const U u = __float_as_uint(v);
+        return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+    }
+    __device__ static float decode(U e) {
+        return __uint_as_float((e & 0x80000000u) ? (e ^ 0x80000000u) : ~e);
+    }
+};
+template <>
+struct Enc<double> {
+    using U = unsigned long long;
+    __device__ static U encode(double v) {
+        const U u = (U)__double_as_longlong(v);
+        return (u & 0x8000000000000000ull) ? ~u : (u | 0x8000000000000000ull);
+    }
+    __device__ static double decode(U e) {
+        return __longlong_as_double((long long)((e & 0x8000000000000000ull) ? (e ^ 0x8000000000000000ull) : ~e));
+    }
+};
+
+// Launch geometry of one plan (chosen on the host from M and the dtype).
+struct LaunchGeom {
+    int rows;         // image rows per row-pass workgroup
+    int row_threads;  // threads of a row-pass workgroup
+    int row_slices;   // orientation slices per row-pass workgroup (forward)
+    int inv_slices;   // orientation slices per row-pass workgroup (inverse, max projection)
+    int cols;         // columns per column-pass workgroup
+    int col_threads;
+    int ocols;        // columns per orientation column workgroup
+    int ocol_threads;
+};
+
+template <class R>
+hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_t* rmap, const R* vol,
+                          C2<R>* spec, int M, int nslices, const LaunchGeom& g, const FftPlan& planH,
+                          const C2<R>* tw, hipStream_t st);
+template <class R>
+hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
+                          const FftPlan& planM, const C2<R>* tw, hipStream_t st);
+template <class R>
+hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftPlan& planM,
+                             const C2<R>* tw, double sigma, hipStream_t st);
+template <class R>
+hipError_t launch_solve(C2<R>* spec, const R* P, int M, int N, hipStream_t st);
+template <class R>
+hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U* enc, uint8_t* rmap,
+                          int M, int nslices, int N, R out_scale, const LaunchGeom& g,
+                          int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st);
+template <class R>
+hipError_t launch_fill_enc(typename Enc<R>::U* enc, long n, hipStream_t st);
+template <class R>
+hipError_t launch_decode_enc(const typename Enc<R>::U* enc, R* out, long n, hipStream_t st);
+template <class R>
+hipError_t launch_lift(const R* f, const uint8_t* mask, const uint8_t* rmap, R* psi, int M, int N,
+                       hipStream_t st);
+template <class R>
+hipError_t launch_project(const R* psi, R* out, int M, int N, bool mean, hipStream_t st);
+template <class R>
+hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
+                             hipStream_t st);
+
+}  // namespace se2n

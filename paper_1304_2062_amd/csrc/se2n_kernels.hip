@@ -1,0 +1,639 @@
+// gfx950 kernels of the semi-discrete SE(2,N) diffusion.
+//
+// Spectral layout.  The half spectrum of an orientation volume is stored
+// "column major": spec[r][kx][ky], kx in [0, M/2], ky in [0, M) contiguous.
+// Every column (r, kx) is M contiguous complex values, so the column FFTs
+// and the per-mode solve read and write whole cache lines; the row passes
+// move 8 (float) or 4 (double) rows at a time so that each (r, kx) segment
+// they touch is 64 contiguous bytes.
+//
+// Pass structure of one diffusion (Theorem 2 of the paper: FFT over (Z/MZ)^2,
+// M^2 decoupled N-dimensional systems, inverse FFT):
+//   k_row_fwd   lift (or read the real volume) + real-to-complex FFT along x
+//   k_col_fft   complex FFT along y, forward
+//   k_solve     psi_hat(kx,ky) <- P(kx,ky) psi_hat(kx,ky), P the per-mode propagator
+//   k_col_fft   complex FFT along y, inverse
+//   k_row_inv   complex-to-real FFT along x + projection (or write the volume)
+// The 1/M^2 of the inverse transform is folded into the stored propagators.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "se2n_fft.hpp"
+#include "se2n_internal.hpp"
+
+namespace se2n {
+
+// ---------------------------------------------------------------------------
+// Row pass, forward: lift + R2C along x, written transposed.
+// ---------------------------------------------------------------------------
+// A real row x[0..M) is transformed as the half-length complex sequence
+// z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
+//   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
+// grid: (M/ROWS row blocks, slice groups); block: nthr threads; LDS ROWS*H.
+template <class R, int SRC>
+__global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
+                          const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
+                          C2<R>* __restrict__ spec, int M, int nslices, int slices_per_group,
+                          int rows, FftPlan planH, const C2<R>* __restrict__ tw) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int y0 = blockIdx.x * rows;
+    const int s_begin = blockIdx.y * slices_per_group;
+    const int s_end = min(nslices, s_begin + slices_per_group);
+    const int nel = rows * H;
+
+    // Lift sources are read once per block and kept in registers.
+    constexpr int EPT = ept<R>();
+    R fc0[EPT], fc1[EPT];
+    uint8_t rm0[EPT], rm1[EPT];
+    if (SRC != SRC_VOLUME) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * nthr;
+            fc0[i] = R(0);
+            fc1[i] = R(0);
+            rm0[i] = 0xff;
+            rm1[i] = 0xff;
+            if (e < nel) {
+                const int row = e / H;
+                const int n = e - row * H;
+                const size_t p = (size_t)(y0 + row) * M + 2 * n;
+                const C2<R> fv = *reinterpret_cast<const C2<R>*>(f + p);
+                const uint16_t mv = *reinterpret_cast<const uint16_t*>(mask + p);
+                fc0[i] = (mv & 0xff) ? R(0) : fv.x;
+                fc1[i] = (mv >> 8) ? R(0) : fv.y;
+                if (SRC == SRC_LIFT) {
+                    const uint16_t rv = *reinterpret_cast<const uint16_t*>(rmap + p);
+                    rm0[i] = (uint8_t)(rv & 0xff);
+                    rm1[i] = (uint8_t)(rv >> 8);
+                }
+            }
+        }
+    }
+
+    for (int s = s_begin; s < s_end; ++s) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * nthr;
+            if (e < nel) {
+                C2<R> z;
+                if (SRC == SRC_VOLUME) {
+                    const int row = e / H;
+                    const int n = e - row * H;
+                    z = *reinterpret_cast<const C2<R>*>(vol + ((size_t)s * M + y0 + row) * M + 2 * n);
+                } else if (SRC == SRC_LIFT) {
+                    z.x = (rm0[i] == s) ? fc0[i] : R(0);
+                    z.y = (rm1[i] == s) ? fc1[i] : R(0);
+                } else {
+                    z.x = fc0[i];
+                    z.y = fc1[i];
+                }
+                buf[e] = z;
+            }
+        }
+        __syncthreads();
+        fft_lds<R, false, EPT>(buf, planH, rows, H, tw, M, tid, nthr);
+        // unpack the real transform and write (r, kx, y0..y0+rows) segments
+        const int nout = rows * K;
+        C2<R>* out = spec + (size_t)s * K * M + y0;
+        for (int e = tid; e < nout; e += nthr) {
+            const int kx = e / rows;
+            const int row = e - kx * rows;
+            const C2<R> z1 = buf[row * H + (kx == H ? 0 : kx)];
+            const C2<R> z2 = buf[row * H + (kx == 0 ? 0 : H - kx)];
+            const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
+            // (z1 - conj z2)/(2i)
+            const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
+            const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
+            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw[kx], od));
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: FFT along y of `cols_per_block` contiguous columns of length M.
+// ---------------------------------------------------------------------------
+template <class R, bool INV>
+__global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M, int cols_per_block,
+                          FftPlan planM, const C2<R>* __restrict__ tw) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    constexpr int EPT = ept<R>();
+    const long c0 = (long)blockIdx.x * cols_per_block;
+    const int ncb = (int)min((long)cols_per_block, ncols - c0);
+    const int nel = ncb * M;
+    C2<R>* base = spec + c0 * M;
+    for (int e = tid; e < nel; e += nthr) buf[e] = base[e];
+    __syncthreads();
+    fft_lds<R, INV, EPT>(buf, planM, ncb, M, tw, M, tid, nthr);
+    for (int e = tid; e < nel; e += nthr) base[e] = buf[e];
+}
+
+// ---------------------------------------------------------------------------
+// Orientation: column FFT of the corrupted image's row spectrum F[kx][ky]
+// (slice 0), multiplication by the smoothed central-difference symbols and
+// inverse column FFTs.  Writes G_x into slice 0 and G_y into slice 1.
+//   G_x = F * i sqrt(M) s_kx g(kx) g(ky) / M^2,  G_y likewise with s_ky,
+//   s_k = sin(2 pi k/M), g(k) = exp(-2 pi^2 sigma^2 kbar^2 / M^2).
+// (The 1/M^2 only keeps magnitudes moderate; the angle ignores it.)
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block, FftPlan planM,
+                             const C2<R>* __restrict__ tw, R neg_two_pi2_sigma2_over_M2, R scale) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    constexpr int EPT = ept<R>();
+    const int c0 = blockIdx.x * cols_per_block;
+    const int ncb = min(cols_per_block, K - c0);
+    const int nel = ncb * M;
+    C2<R>* gx = spec + (size_t)c0 * M;
+    C2<R>* gy = spec + ((size_t)K + c0) * M;
+    for (int e = tid; e < nel; e += nthr) buf[e] = gx[e];
+    __syncthreads();
+    fft_lds<R, false, EPT>(buf, planM, ncb, M, tw, M, tid, nthr);
+    C2<R>* buf2 = buf + nel;
+    for (int e = tid; e < nel; e += nthr) {
+        const int col = e / M;
+        const int ky = e - col * M;
+        const int kx = c0 + col;
+        const R skx = -tw[kx].y;
+        const R sky = -tw[ky].y;
+        const R kxb = (R)kx;                            // kx <= M/2; (M/2)^2 = (-M/2)^2
+        const R kyb = (R)(ky < H ? ky : ky - M);
+        const R g = exp(neg_two_pi2_sigma2_over_M2 * (kxb * kxb + kyb * kyb)) * scale;
+        const C2<R> F = buf[e];
+        const C2<R> iF = cmk<R>(-F.y, F.x);
+        buf[e] = cmk<R>(iF.x * skx * g, iF.y * skx * g);
+        buf2[e] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
+    }
+    __syncthreads();
+    fft_lds<R, true, EPT>(buf, planM, 2 * ncb, M, tw, M, tid, nthr);
+    for (int e = tid; e < nel; e += nthr) {
+        gx[e] = buf[e];
+        gy[e] = buf2[e];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, inverse: C2R along x from the transposed half spectrum, then
+// projection over the block's slices (max / sum), the real volume, or the
+// orientation binning (slices 0, 1 = g_x, g_y).
+// With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
+// the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
+// ---------------------------------------------------------------------------
+template <class R, int DST>
+__global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
+                          typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
+                          int M, int nslices, int slices_per_group, int rows, int N, R out_scale,
+                          FftPlan planH, const C2<R>* __restrict__ tw) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int S = H + 1;  // LDS row stride
+    const int tid = threadIdx.x;
+    const int nthr = blockDim.x;
+    const int y0 = blockIdx.x * rows;
+    const int s_begin = blockIdx.y * slices_per_group;
+    const int s_end = min(nslices, s_begin + slices_per_group);
+    const int nel = rows * H;
+
+    constexpr int EPT = ept<R>();
+    C2<R> acc[EPT], acc2[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const R init = (DST == DST_MAX) ? -INFINITY : R(0);
+        acc[i] = cmk<R>(init, init);
+        acc2[i] = cmk<R>(R(0), R(0));
+    }
+
+    for (int s = s_begin; s < s_end; ++s) {
+        const C2<R>* in = spec + (size_t)s * K * M + y0;
+        const int nin = rows * K;
+        for (int e = tid; e < nin; e += nthr) {
+            const int kx = e / rows;
+            const int row = e - kx * rows;
+            buf[row * S + kx] = in[(size_t)kx * M + row];
+        }
+        __syncthreads();
+        const int npair = H / 2 + 1;
+        for (int e = tid; e < rows * npair; e += nthr) {
+            const int row = e / npair;
+            const int k = e - row * npair;
+            const int kk = H - k;
+            const C2<R> a = buf[row * S + k];
+            const C2<R> b = buf[row * S + kk];
+            // Z[k]
+            const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);      // a + conj b
+            const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);      // a - conj b
+            const C2<R> wa = cconj<R>(tw[k]);
+            const C2<R> ta = cmul<R>(wa, da);
+            const C2<R> za = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
+            // Z[H-k]
+            const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
+            const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
+            const C2<R> wb = cconj<R>(tw[kk]);
+            const C2<R> tb = cmul<R>(wb, db);
+            const C2<R> zb = cmk<R>(sb.x - tb.y, sb.y + tb.x);
+            buf[row * S + k] = za;
+            if (kk != k) buf[row * S + kk] = zb;
+        }
+        __syncthreads();
+        fft_lds<R, true, EPT>(buf, planH, rows, S, tw, M, tid, nthr);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * nthr;
+            if (e < nel) {
+                const int row = e / H;
+                const int n = e - row * H;
+                const C2<R> z = buf[row * S + n];
+                if (DST == DST_VOLUME) {
+                    *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
+                        cmk<R>(z.x * out_scale, z.y * out_scale);
+                } else if (DST == DST_MAX) {
+                    acc[i].x = fmax(acc[i].x, z.x);
+                    acc[i].y = fmax(acc[i].y, z.y);
+                } else if (DST == DST_SUM) {
+                    acc[i].x += z.x;
+                    acc[i].y += z.y;
+                } else {  // DST_ORIENT
+                    if (s == 0) acc[i] = z;
+                    else acc2[i] = z;
+                }
+            }
+        }
+        __syncthreads();
+    }
+
+    if (DST == DST_VOLUME) return;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < nel) {
+            const int row = e / H;
+            const int n = e - row * H;
+            const size_t p = (size_t)(y0 + row) * M + 2 * n;
+            if (DST == DST_MAX) {
+                if (enc) {
+                    atomicMax(enc + p, Enc<R>::encode(acc[i].x));
+                    atomicMax(enc + p + 1, Enc<R>::encode(acc[i].y));
+                } else {
+                    *reinterpret_cast<C2<R>*>(out + p) = acc[i];
+                }
+            } else if (DST == DST_SUM) {
+                *reinterpret_cast<C2<R>*>(out + p) = cmk<R>(acc[i].x * out_scale, acc[i].y * out_scale);
+            } else {  // orientation bins of pixels 2n and 2n+1
+                const R two_pi = R(6.283185307179586476925);
+                const R half_pi = R(1.570796326794896619231);
+                R t0 = (atan2(acc2[i].x, acc[i].x) + half_pi) * (R)N / two_pi + R(0.5);
+                R t1 = (atan2(acc2[i].y, acc[i].y) + half_pi) * (R)N / two_pi + R(0.5);
+                int b0 = (int)floor(t0) % N;
+                int b1 = (int)floor(t1) % N;
+                if (b0 < 0) b0 += N;
+                if (b1 < 0) b1 += N;
+                const uint16_t packed = (uint16_t)((unsigned)b0 | ((unsigned)b1 << 8));
+                *reinterpret_cast<uint16_t*>(rmap + p) = packed;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Small elementwise kernels.
+// ---------------------------------------------------------------------------
+template <class R>
+__global__ void k_fill_enc(typename Enc<R>::U* __restrict__ enc, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) enc[i] = 0;
+}
+
+template <class R>
+__global__ void k_decode_enc(const typename Enc<R>::U* __restrict__ enc, R* __restrict__ out, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = Enc<R>::decode(enc[i]);
+}
+
+template <class R>
+__global__ void k_lift(const R* __restrict__ f, const uint8_t* __restrict__ mask,
+                       const uint8_t* __restrict__ rmap, R* __restrict__ psi, long MM, int N) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MM) return;
+    const R v = mask[i] ? R(0) : f[i];
+    const int r = rmap[i];
+    for (int s = 0; s < N; ++s) psi[(size_t)s * MM + i] = (s == r) ? v : R(0);
+}
+
+template <class R, bool MEAN>
+__global__ void k_project(const R* __restrict__ psi, R* __restrict__ out, long MM, int N) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= MM) return;
+    R a = psi[i];
+    for (int s = 1; s < N; ++s) {
+        const R v = psi[(size_t)s * MM + i];
+        a = MEAN ? a + v : fmax(a, v);
+    }
+    out[i] = MEAN ? a / (R)N : a;
+}
+
+// ---------------------------------------------------------------------------
+// Propagator precompute, FP64: one 64-thread workgroup per frequency class.
+// ---------------------------------------------------------------------------
+// For class (lx, ly) and each block (periodic +, antiperiodic -) of size
+// h = N/2:  A = beta L_h^{+-} - diag(pot_j), pot_j = M (cos e_j s_x + sin e_j s_y)^2.
+//   CN:    C = (I - tau A/2)^{-1} (I + tau A/2) by Gauss-Jordan (the left
+//          matrix is symmetric, diagonally dominant: no pivoting), P = C^n by
+//          binary powering.
+//   EXACT: P = e^{T A} by scaling and squaring of a degree-16 Taylor sum.
+__device__ void lds_matmul(const double* A, const double* B, double* Cm, int h, int tid) {
+    for (int idx = tid; idx < h * h; idx += 64) {
+        const int i = idx / h;
+        const int j = idx - i * h;
+        double s = 0.0;
+        for (int k = 0; k < h; ++k) s += A[i * h + k] * B[k * h + j];
+        Cm[idx] = s;
+    }
+    __syncthreads();
+}
+
+__device__ void lds_copy(const double* A, double* B, int n, int tid) {
+    for (int idx = tid; idx < n; idx += 64) B[idx] = A[idx];
+    __syncthreads();
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q,
+                                                   double beta, double T, int nsteps, int scheme,
+                                                   double scale) {
+    extern __shared__ double sm[];
+    const int h = N / 2;
+    const int hh = h * h;
+    double* A = sm;          // generator block
+    double* Bs = A + hh;     // base / result of the solve
+    double* Rs = Bs + hh;    // running product
+    double* Ts = Rs + hh;    // temporary
+    double* W = Ts + hh;     // h x 2h augmented matrix
+    double* pot = W + 2 * hh;
+    const int tid = threadIdx.x;
+    const int lx = blockIdx.x / Q;
+    const int ly = blockIdx.x - lx * Q;
+    const double two_pi = 6.283185307179586476925;
+    const double sx = sin(two_pi * lx / M);
+    const double sy = sin(two_pi * ly / M);
+    for (int j = tid; j < h; j += 64) {
+        const double e = two_pi * j / N;
+        const double a = cos(e) * sx + sin(e) * sy;
+        pot[j] = (double)M * a * a;
+    }
+    __syncthreads();
+    const int Eh = h * (h + 1) / 2;
+    const int E = 2 * Eh;
+    for (int blk = 0; blk < 2; ++blk) {
+        const double wrap = blk == 0 ? 1.0 : -1.0;
+        for (int idx = tid; idx < hh; idx += 64) {
+            const int i = idx / h;
+            const int j = idx - i * h;
+            double v = (i == j) ? (-2.0 * beta - pot[i]) : 0.0;
+            // neighbours i+1 and i-1 with wrap-around sign
+            if (j == (i + 1) % h) v += (i + 1 < h) ? beta : wrap * beta;
+            if (j == (i + h - 1) % h) v += (i >= 1) ? beta : wrap * beta;
+            A[idx] = v;
+        }
+        __syncthreads();
+        if (scheme == 0) {
+            const double tau = T / nsteps;
+            for (int idx = tid; idx < 2 * hh; idx += 64) {
+                const int i = idx / (2 * h);
+                const int j = idx - i * 2 * h;
+                const double a = A[i * h + (j % h)];
+                const double id = (i == (j % h)) ? 1.0 : 0.0;
+                W[idx] = (j < h) ? (id - 0.5 * tau * a) : (id + 0.5 * tau * a);
+            }
+            __syncthreads();
+            for (int piv = 0; piv < h; ++piv) {
+                const double inv = 1.0 / W[piv * 2 * h + piv];
+                __syncthreads();  // every thread has read the pivot
+                for (int j = tid; j < 2 * h; j += 64) W[piv * 2 * h + j] *= inv;
+                for (int i = tid; i < h; i += 64) Ts[i] = W[i * 2 * h + piv];
+                __syncthreads();
+                for (int idx = tid; idx < 2 * hh; idx += 64) {
+                    const int i = idx / (2 * h);
+                    const int j = idx - i * 2 * h;
+                    if (i != piv) W[idx] -= Ts[i] * W[piv * 2 * h + j];
+                }
+                __syncthreads();
+            }
+            for (int idx = tid; idx < hh; idx += 64) {
+                const int i = idx / h;
+                const int j = idx - i * h;
+                Bs[idx] = W[i * 2 * h + h + j];
+                Rs[idx] = (i == j) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            int n = nsteps;
+            while (n > 0) {
+                if (n & 1) {
+                    lds_matmul(Rs, Bs, Ts, h, tid);
+                    lds_copy(Ts, Rs, hh, tid);
+                }
+                n >>= 1;
+                if (n) {
+                    lds_matmul(Bs, Bs, Ts, h, tid);
+                    lds_copy(Ts, Bs, hh, tid);
+                }
+            }
+        } else {
+            // X = T A / 2^s with ||X||_inf <= 1/2
+            double nrm = 0.0;
+            for (int i = 0; i < h; ++i) {
+                double rs = 0.0;
+                for (int j = 0; j < h; ++j) rs += fabs(A[i * h + j]);
+                nrm = fmax(nrm, rs);
+            }
+            nrm *= T;
+            __syncthreads();  // all norms read before A is scaled in place
+            int sq = 0;
+            while (nrm > 0.5) {
+                nrm *= 0.5;
+                ++sq;
+            }
+            const double xs = T * ldexp(1.0, -sq);
+            for (int idx = tid; idx < hh; idx += 64) {
+                A[idx] *= xs;
+                const int i = idx / h;
+                const int j = idx - i * h;
+                Rs[idx] = (i == j) ? 1.0 : 0.0;
+            }
+            __syncthreads();
+            // Horner: E = I + X (I + X/2 (I + X/3 (... (I + X/16))))
+            for (int k = 16; k >= 1; --k) {
+                lds_matmul(A, Rs, Ts, h, tid);
+                for (int idx = tid; idx < hh; idx += 64) {
+                    const int i = idx / h;
+                    const int j = idx - i * h;
+                    Rs[idx] = ((i == j) ? 1.0 : 0.0) + Ts[idx] / k;
+                }
+                __syncthreads();
+            }
+            for (int s = 0; s < sq; ++s) {
+                lds_matmul(Rs, Rs, Ts, h, tid);
+                lds_copy(Ts, Rs, hh, tid);
+            }
+        }
+        // packed upper triangle, symmetrised, scaled, stored as R
+        R* dst = Ptab + (size_t)lx * E * Q + ly;
+        for (int idx = tid; idx < hh; idx += 64) {
+            const int i = idx / h;
+            const int j = idx - i * h;
+            if (j >= i) {
+                const int e = blk * Eh + i * h - i * (i - 1) / 2 + (j - i);
+                const double v = 0.5 * (Rs[i * h + j] + Rs[j * h + i]) * scale;
+                dst[(size_t)e * Q] = (R)v;
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers (host side, called by the runtime with validated arguments).
+// ---------------------------------------------------------------------------
+template <class R>
+hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_t* rmap, const R* vol,
+                          C2<R>* spec, int M, int nslices, const LaunchGeom& g, const FftPlan& planH,
+                          const C2<R>* tw, hipStream_t st) {
+    const int groups = (nslices + g.row_slices - 1) / g.row_slices;
+    dim3 grid(M / g.rows, groups);
+    const size_t lds = (size_t)g.rows * (M / 2) * sizeof(C2<R>);
+    if (src == SRC_LIFT)
+        hipLaunchKernelGGL((k_row_fwd<R, SRC_LIFT>), grid, dim3(g.row_threads), lds, st, f, mask, rmap,
+                           vol, spec, M, nslices, g.row_slices, g.rows, planH, tw);
+    else if (src == SRC_VOLUME)
+        hipLaunchKernelGGL((k_row_fwd<R, SRC_VOLUME>), grid, dim3(g.row_threads), lds, st, f, mask,
+                           rmap, vol, spec, M, nslices, g.row_slices, g.rows, planH, tw);
+    else
+        hipLaunchKernelGGL((k_row_fwd<R, SRC_IMAGE>), grid, dim3(g.row_threads), lds, st, f, mask,
+                           rmap, vol, spec, M, nslices, g.row_slices, g.rows, planH, tw);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
+                          const FftPlan& planM, const C2<R>* tw, hipStream_t st) {
+    dim3 grid((unsigned)((ncols + g.cols - 1) / g.cols));
+    const size_t lds = (size_t)g.cols * M * sizeof(C2<R>);
+    if (inverse)
+        hipLaunchKernelGGL((k_col_fft<R, true>), grid, dim3(g.col_threads), lds, st, spec, ncols, M,
+                           g.cols, planM, tw);
+    else
+        hipLaunchKernelGGL((k_col_fft<R, false>), grid, dim3(g.col_threads), lds, st, spec, ncols, M,
+                           g.cols, planM, tw);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftPlan& planM,
+                             const C2<R>* tw, double sigma, hipStream_t st) {
+    const int K = M / 2 + 1;
+    dim3 grid((K + g.ocols - 1) / g.ocols);
+    const size_t lds = 2 * (size_t)g.ocols * M * sizeof(C2<R>);
+    const double c = -2.0 * 9.869604401089358619 * sigma * sigma / ((double)M * M);
+    const double scale = sqrt((double)M) / ((double)M * M);
+    hipLaunchKernelGGL((k_col_orient<R>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols, planM,
+                       tw, (R)c, (R)scale);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U* enc, uint8_t* rmap,
+                          int M, int nslices, int N, R out_scale, const LaunchGeom& g,
+                          int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st) {
+    const int groups = (nslices + slices_per_group - 1) / slices_per_group;
+    dim3 grid(M / g.rows, groups);
+    const size_t lds = (size_t)g.rows * (M / 2 + 1) * sizeof(C2<R>);
+#define SE2N_ROWINV(D)                                                                               \
+    hipLaunchKernelGGL((k_row_inv<R, D>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap, M, \
+                       nslices, slices_per_group, g.rows, N, out_scale, planH, tw)
+    if (dst == DST_MAX) SE2N_ROWINV(DST_MAX);
+    else if (dst == DST_SUM) SE2N_ROWINV(DST_SUM);
+    else if (dst == DST_VOLUME) SE2N_ROWINV(DST_VOLUME);
+    else SE2N_ROWINV(DST_ORIENT);
+#undef SE2N_ROWINV
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_fill_enc(typename Enc<R>::U* enc, long n, hipStream_t st) {
+    hipLaunchKernelGGL((k_fill_enc<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, enc, n);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_decode_enc(const typename Enc<R>::U* enc, R* out, long n, hipStream_t st) {
+    hipLaunchKernelGGL((k_decode_enc<R>), dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, enc, out, n);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_lift(const R* f, const uint8_t* mask, const uint8_t* rmap, R* psi, int M, int N,
+                       hipStream_t st) {
+    const long MM = (long)M * M;
+    hipLaunchKernelGGL((k_lift<R>), dim3((unsigned)((MM + 255) / 256)), dim3(256), 0, st, f, mask, rmap,
+                       psi, MM, N);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_project(const R* psi, R* out, int M, int N, bool mean, hipStream_t st) {
+    const long MM = (long)M * M;
+    dim3 grid((unsigned)((MM + 255) / 256));
+    if (mean) hipLaunchKernelGGL((k_project<R, true>), grid, dim3(256), 0, st, psi, out, MM, N);
+    else hipLaunchKernelGGL((k_project<R, false>), grid, dim3(256), 0, st, psi, out, MM, N);
+    return hipGetLastError();
+}
+
+template <class R>
+hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
+                             hipStream_t st) {
+    const int Q = M / 4 + 1;
+    const int h = N / 2;
+    const size_t lds = (size_t)(6 * h * h + h) * sizeof(double);
+    const double scale = 1.0 / (2.0 * (double)M * (double)M);
+    hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q, beta,
+                       T, nsteps, scheme, scale);
+    return hipGetLastError();
+}
+
+#define SE2N_INSTANTIATE(R)                                                                             \
+    template hipError_t launch_row_fwd<R>(int, const R*, const uint8_t*, const uint8_t*, const R*,     \
+                                          C2<R>*, int, int, const LaunchGeom&, const FftPlan&,         \
+                                          const C2<R>*, hipStream_t);                                  \
+    template hipError_t launch_col_fft<R>(bool, C2<R>*, long, int, const LaunchGeom&, const FftPlan&,  \
+                                          const C2<R>*, hipStream_t);                                  \
+    template hipError_t launch_col_orient<R>(C2<R>*, int, const LaunchGeom&, const FftPlan&,           \
+                                             const C2<R>*, double, hipStream_t);                       \
+    template hipError_t launch_row_inv<R>(int, const C2<R>*, R*, typename Enc<R>::U*, uint8_t*, int,   \
+                                          int, int, R, const LaunchGeom&, int, const FftPlan&,         \
+                                          const C2<R>*, hipStream_t);                                  \
+    template hipError_t launch_fill_enc<R>(typename Enc<R>::U*, long, hipStream_t);                    \
+    template hipError_t launch_decode_enc<R>(const typename Enc<R>::U*, R*, long, hipStream_t);        \
+    template hipError_t launch_lift<R>(const R*, const uint8_t*, const uint8_t*, R*, int, int,         \
+                                       hipStream_t);                                                   \
+    template hipError_t launch_project<R>(const R*, R*, int, int, bool, hipStream_t);                  \
+    template hipError_t launch_precompute<R>(R*, int, int, double, double, int, int, hipStream_t);
+
+SE2N_INSTANTIATE(float)
+SE2N_INSTANTIATE(double)
+
+}  // namespace se2n

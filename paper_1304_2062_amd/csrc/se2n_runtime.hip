@@ -1,0 +1,586 @@
+// Host runtime of libse2n: plans, argument validation, the per-frequency
+// propagator cache, workspace layout and the C ABI of include/se2n.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <list>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/se2n.h"
+#include "se2n_internal.hpp"
+
+using namespace se2n;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+int fail(int code, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+    return fail(SE2N_EHIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SE2N_HIP(call, what)                          \
+    do {                                              \
+        hipError_t e_ = (call);                       \
+        if (e_ != hipSuccess) return hip_fail(e_, what); \
+    } while (0)
+
+bool is_2a3b(int M, int* twos, int* threes) {
+    int a = 0, b = 0, m = M;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    if (twos) *twos = a;
+    if (threes) *threes = b;
+    return m == 1;
+}
+
+// Radix sequence of a length-L transform, L = 2^a 3^b: radix 8 where possible,
+// then 4 (or 4,4 in place of 8,2), then radix 3.
+FftPlan make_fft_plan(int L) {
+    FftPlan p{};
+    p.L = L;
+    int a = 0, b = 0;
+    is_2a3b(L, &a, &b);
+    int n = 0;
+    int q = a / 3, r = a % 3;
+    if (r == 1 && q >= 1) {
+        for (int i = 0; i < q - 1; ++i) p.radix[n++] = 8;
+        p.radix[n++] = 4;
+        p.radix[n++] = 4;
+    } else {
+        for (int i = 0; i < q; ++i) p.radix[n++] = 8;
+        if (r == 1) p.radix[n++] = 2;
+        if (r == 2) p.radix[n++] = 4;
+    }
+    for (int i = 0; i < b; ++i) p.radix[n++] = 3;
+    p.nstages = n;
+    return p;
+}
+
+struct CacheKey {
+    double T, beta;
+    int n, scheme;
+    bool operator==(const CacheKey& o) const {
+        return std::memcmp(&T, &o.T, sizeof T) == 0 && std::memcmp(&beta, &o.beta, sizeof beta) == 0 &&
+               n == o.n && scheme == o.scheme;
+    }
+};
+
+struct CacheEntry {
+    CacheKey key;
+    void* dptr;
+    size_t bytes;
+};
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+}  // namespace
+
+struct se2n_plan_s {
+    int M = 0, N = 0;
+    se2n_dtype dt = SE2N_F32;
+    int device = 0;
+    void* tw = nullptr;  // w_M^m, m < M, in the plan dtype
+    FftPlan planH{}, planM{};
+    LaunchGeom geom{};
+    std::list<CacheEntry> cache;  // most recently used first
+    size_t cache_bytes = 0;
+    size_t cache_limit = (size_t)16 << 30;
+    std::mutex mu;
+    bool alive = true;
+    // kernel timing
+    bool prof_on = false;
+    struct ProfRec {
+        const char* name;
+        hipEvent_t a, b;
+    };
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    std::map<std::string, std::pair<int, double>> prof_acc;
+
+    size_t real_size() const { return dt == SE2N_F32 ? 4 : 8; }
+    size_t cplx_size() const { return 2 * real_size(); }
+    int K() const { return M / 2 + 1; }
+    size_t spec_bytes() const { return align256((size_t)N * K() * M * cplx_size()); }
+    size_t enc_bytes() const { return align256((size_t)M * M * real_size()); }
+    size_t rmap_bytes() const { return align256((size_t)M * M); }
+    size_t workspace() const { return spec_bytes() + enc_bytes() + rmap_bytes(); }
+    size_t table_bytes() const {
+        const size_t Q = (size_t)(M / 4 + 1);
+        const size_t h = (size_t)(N / 2);
+        return Q * Q * h * (h + 1) * real_size();
+    }
+};
+
+namespace {
+
+hipEvent_t prof_event(se2n_plan p) {
+    if (!p->prof_pool.empty()) {
+        hipEvent_t e = p->prof_pool.back();
+        p->prof_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+}
+
+// Brackets one launch with events on its stream while timing is enabled.
+struct ProfScope {
+    se2n_plan p;
+    const char* name;
+    hipStream_t st;
+    hipEvent_t a = nullptr;
+    ProfScope(se2n_plan p_, const char* name_, hipStream_t st_) : p(p_), name(name_), st(st_) {
+        if (p->prof_on) {
+            a = prof_event(p);
+            if (a) (void)hipEventRecord(a, st);
+        }
+    }
+    ~ProfScope() {
+        if (a) {
+            hipEvent_t b = prof_event(p);
+            if (b) {
+                (void)hipEventRecord(b, st);
+                p->prof_pending.push_back({name, a, b});
+            } else {
+                p->prof_pool.push_back(a);
+            }
+        }
+    }
+};
+
+#define SE2N_TIMED(plan, name, st, call, what) \
+    do {                                       \
+        ProfScope ps_(plan, name, st);         \
+        SE2N_HIP(call, what);                  \
+    } while (0)
+
+template <class R>
+LaunchGeom make_geom(int M, int N) {
+    constexpr int EPT = ept<R>();
+    const int target = sizeof(R) == 4 ? 4096 : 2048;  // complex elements per FFT workgroup
+    const int H = M / 2;
+    LaunchGeom g{};
+    int rows = 64 / (int)sizeof(C2<R>);  // 64-byte segments per (slice, kx)
+    while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
+    g.rows = rows;
+    g.row_threads = (rows * H + EPT - 1) / EPT;
+    const int row_blocks = M / rows;
+    int groups = (1024 + row_blocks - 1) / row_blocks;
+    if (groups > N) groups = N;
+    if (groups < 1) groups = 1;
+    g.row_slices = (N + groups - 1) / groups;
+    g.inv_slices = g.row_slices;
+    g.cols = target / M > 1 ? target / M : 1;
+    g.col_threads = (g.cols * M + EPT - 1) / EPT;
+    g.ocols = target / (2 * M) > 1 ? target / (2 * M) : 1;
+    g.ocol_threads = (2 * g.ocols * M + EPT - 1) / EPT;
+    return g;
+}
+
+int check_plan(se2n_plan p) {
+    if (!p) return fail(SE2N_EINVAL, "plan is NULL");
+    if (!p->alive) return fail(SE2N_ESTATE, "plan was destroyed");
+    return SE2N_OK;
+}
+
+int check_diffusion_params(double T, double beta, int n_steps, se2n_scheme scheme) {
+    if (!(T >= 0.0) || !std::isfinite(T)) return fail(SE2N_EINVAL, "T must be finite and >= 0 (got %g)", T);
+    if (!(beta >= 0.0) || !std::isfinite(beta))
+        return fail(SE2N_EINVAL, "beta must be finite and >= 0 (got %g)", beta);
+    if (scheme != SE2N_CN && scheme != SE2N_EXACT) return fail(SE2N_EINVAL, "unknown scheme %d", (int)scheme);
+    if (scheme == SE2N_CN && n_steps < 1) return fail(SE2N_EINVAL, "n_steps must be >= 1 (got %d)", n_steps);
+    return SE2N_OK;
+}
+
+// Look up (or compute on `st`) the propagator table for the given parameters.
+int get_propagators(se2n_plan p, double T, double beta, int n_steps, se2n_scheme scheme, hipStream_t st,
+                    const void** out) {
+    CacheKey key{T, beta, scheme == SE2N_CN ? n_steps : 0, (int)scheme};
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (auto it = p->cache.begin(); it != p->cache.end(); ++it) {
+        if (it->key == key) {
+            p->cache.splice(p->cache.begin(), p->cache, it);
+            *out = p->cache.front().dptr;
+            return SE2N_OK;
+        }
+    }
+    const size_t bytes = p->table_bytes();
+    // evict least recently used entries to stay under the limit
+    while (!p->cache.empty() && p->cache_bytes + bytes > p->cache_limit) {
+        SE2N_HIP(hipStreamSynchronize(st), "hipStreamSynchronize before cache eviction");
+        SE2N_HIP(hipFree(p->cache.back().dptr), "hipFree of an evicted propagator table");
+        p->cache_bytes -= p->cache.back().bytes;
+        p->cache.pop_back();
+    }
+    void* d = nullptr;
+    hipError_t e = hipMalloc(&d, bytes);
+    if (e != hipSuccess) return fail(SE2N_ENOMEM, "hipMalloc of %zu bytes for propagators: %s", bytes,
+                                     hipGetErrorString(e));
+    {
+        ProfScope ps(p, "precompute", st);
+        if (p->dt == SE2N_F32)
+            e = launch_precompute<float>((float*)d, p->M, p->N, beta, T, n_steps, (int)scheme, st);
+        else
+            e = launch_precompute<double>((double*)d, p->M, p->N, beta, T, n_steps, (int)scheme, st);
+    }
+    if (e != hipSuccess) {
+        (void)hipFree(d);
+        return hip_fail(e, "propagator precompute launch");
+    }
+    p->cache.push_front(CacheEntry{key, d, bytes});
+    p->cache_bytes += bytes;
+    *out = d;
+    return SE2N_OK;
+}
+
+template <class R>
+struct Ws {
+    C2<R>* spec;
+    typename Enc<R>::U* enc;
+    uint8_t* rmap;
+};
+
+template <class R>
+Ws<R> split_workspace(se2n_plan p, void* ws) {
+    char* b = (char*)ws;
+    Ws<R> w;
+    w.spec = (C2<R>*)b;
+    w.enc = (typename Enc<R>::U*)(b + p->spec_bytes());
+    w.rmap = (uint8_t*)(b + p->spec_bytes() + p->enc_bytes());
+    return w;
+}
+
+template <class R>
+int orient_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, uint8_t* rmap, C2<R>* spec,
+                hipStream_t st) {
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    const int M = p->M;
+    SE2N_TIMED(p, "orient_row_fwd", st,
+               launch_row_fwd<R>(SRC_IMAGE, f, mask, nullptr, nullptr, spec, M, 1, p->geom, p->planH, tw, st),
+               "orient row pass");
+    SE2N_TIMED(p, "orient_col", st, launch_col_orient<R>(spec, M, p->geom, p->planM, tw, sigma, st),
+               "orient column pass");
+    SE2N_TIMED(p, "orient_row_inv", st,
+               launch_row_inv<R>(DST_ORIENT, spec, nullptr, nullptr, rmap, M, 2, p->N, R(1), p->geom, 2,
+                                 p->planH, tw, st),
+               "orient inverse row pass");
+    return SE2N_OK;
+}
+
+// spec holds the forward half spectrum of all slices; propagate it in place.
+template <class R>
+int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    const long ncols = (long)p->N * p->K();
+    SE2N_TIMED(p, "col_fft_fwd", st, launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st),
+               "forward column FFT");
+    SE2N_TIMED(p, "solve", st, launch_solve<R>(spec, (const R*)P, p->M, p->N, st), "per-mode solve");
+    SE2N_TIMED(p, "col_fft_inv", st, launch_col_fft<R>(true, spec, ncols, p->M, p->geom, p->planM, tw, st),
+               "inverse column FFT");
+    return SE2N_OK;
+}
+
+template <class R>
+int project_spec(se2n_plan p, const C2<R>* spec, typename Enc<R>::U* enc, se2n_proj mode, R* out,
+                 hipStream_t st) {
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    const int M = p->M, N = p->N;
+    const long MM = (long)M * M;
+    if (mode == SE2N_PROJ_MEAN) {
+        SE2N_TIMED(p, "row_inv_mean", st,
+                   launch_row_inv<R>(DST_SUM, spec, out, nullptr, nullptr, M, N, N, R(1) / (R)N, p->geom, N,
+                                     p->planH, tw, st),
+                   "inverse row pass (mean)");
+        return SE2N_OK;
+    }
+    if (p->geom.inv_slices >= N) {
+        SE2N_TIMED(p, "row_inv_max", st,
+                   launch_row_inv<R>(DST_MAX, spec, out, nullptr, nullptr, M, N, N, R(1), p->geom, N, p->planH,
+                                     tw, st),
+                   "inverse row pass (max)");
+        return SE2N_OK;
+    }
+    SE2N_TIMED(p, "fill_max", st, launch_fill_enc<R>(enc, MM, st), "clear max buffer");
+    SE2N_TIMED(p, "row_inv_max", st,
+               launch_row_inv<R>(DST_MAX, spec, nullptr, enc, nullptr, M, N, N, R(1), p->geom,
+                                 p->geom.inv_slices, p->planH, tw, st),
+               "inverse row pass (max)");
+    SE2N_TIMED(p, "decode_max", st, launch_decode_enc<R>(enc, out, MM, st), "decode max buffer");
+    return SE2N_OK;
+}
+
+template <class R>
+int inpaint_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, double T, double beta,
+                 int n_steps, se2n_scheme scheme, se2n_proj mode, const uint8_t* rmap_in, uint8_t* rmap_out,
+                 R* out, void* workspace, hipStream_t st) {
+    const void* P = nullptr;
+    int rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
+    if (rc) return rc;
+    Ws<R> w = split_workspace<R>(p, workspace);
+    const uint8_t* rmap = rmap_in;
+    if (!rmap_in) {
+        uint8_t* dst = rmap_out ? rmap_out : w.rmap;
+        rc = orient_impl<R>(p, f, mask, sigma, dst, w.spec, st);
+        if (rc) return rc;
+        rmap = dst;
+    } else if (rmap_out && rmap_out != rmap_in) {
+        SE2N_HIP(hipMemcpyAsync(rmap_out, rmap_in, (size_t)p->M * p->M, hipMemcpyDeviceToDevice, st),
+                 "copy of rmap_in to rmap_out");
+    }
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    SE2N_TIMED(p, "lift_row_fwd", st,
+               launch_row_fwd<R>(SRC_LIFT, f, mask, rmap, nullptr, w.spec, p->M, p->N, p->geom, p->planH, tw, st),
+               "lift + row FFT");
+    rc = spectral_middle<R>(p, w.spec, P, st);
+    if (rc) return rc;
+    return project_spec<R>(p, w.spec, w.enc, mode, out, st);
+}
+
+template <class R>
+int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_scheme scheme, void* workspace,
+                 hipStream_t st) {
+    const void* P = nullptr;
+    int rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
+    if (rc) return rc;
+    Ws<R> w = split_workspace<R>(p, workspace);
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    SE2N_TIMED(p, "row_fwd", st,
+               launch_row_fwd<R>(SRC_VOLUME, nullptr, nullptr, nullptr, psi, w.spec, p->M, p->N, p->geom,
+                                 p->planH, tw, st),
+               "row FFT");
+    rc = spectral_middle<R>(p, w.spec, P, st);
+    if (rc) return rc;
+    SE2N_TIMED(p, "row_inv_volume", st,
+               launch_row_inv<R>(DST_VOLUME, w.spec, psi, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
+                                 p->geom.inv_slices, p->planH, tw, st),
+               "inverse row FFT");
+    return SE2N_OK;
+}
+
+template <class R>
+int make_twiddles(se2n_plan p) {
+    const int M = p->M;
+    std::vector<C2<R>> h(M);
+    for (int m = 0; m < M; ++m) {
+        // exp(-2 pi i m / M), evaluated in extended precision before rounding
+        const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)M;
+        h[m].x = (R)(double)cosl(a);
+        h[m].y = (R)(double)(-sinl(a));
+    }
+    SE2N_HIP(hipMalloc(&p->tw, (size_t)M * sizeof(C2<R>)), "hipMalloc twiddles");
+    SE2N_HIP(hipMemcpy(p->tw, h.data(), (size_t)M * sizeof(C2<R>), hipMemcpyHostToDevice), "twiddle upload");
+    return SE2N_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
+    g_last_error.clear();
+    if (!out) return fail(SE2N_EINVAL, "out is NULL");
+    int twos = 0;
+    if (M < 16 || M > 4096 || !is_2a3b(M, &twos, nullptr) || twos < 3)
+        return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 3 and 16 <= M <= 4096 (got %d)", M);
+    if (N < 4 || N > 64) return fail(SE2N_EINVAL, "N must lie in [4, 64] (got %d)", N);
+    if (N % 2) return fail(SE2N_EUNSUPPORTED, "odd N (%d) is not supported: N must be even", N);
+    if (dtype != SE2N_F32 && dtype != SE2N_F64) return fail(SE2N_EINVAL, "unknown dtype %d", (int)dtype);
+    se2n_plan p = new (std::nothrow) se2n_plan_s;
+    if (!p) return fail(SE2N_ENOMEM, "host allocation of the plan failed");
+    p->M = M;
+    p->N = N;
+    p->dt = dtype;
+    (void)hipGetDevice(&p->device);
+    p->planH = make_fft_plan(M / 2);
+    p->planM = make_fft_plan(M);
+    int rc;
+    if (dtype == SE2N_F32) {
+        p->geom = make_geom<float>(M, N);
+        rc = make_twiddles<float>(p);
+    } else {
+        p->geom = make_geom<double>(M, N);
+        rc = make_twiddles<double>(p);
+    }
+    if (rc) {
+        if (p->tw) (void)hipFree(p->tw);
+        delete p;
+        return rc;
+    }
+    *out = p;
+    return SE2N_OK;
+}
+
+int se2n_plan_destroy(se2n_plan p) {
+    g_last_error.clear();
+    if (!p) return fail(SE2N_EINVAL, "plan is NULL");
+    (void)hipDeviceSynchronize();
+    for (auto& e : p->cache) (void)hipFree(e.dptr);
+    for (auto& r : p->prof_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto e : p->prof_pool) (void)hipEventDestroy(e);
+    if (p->tw) (void)hipFree(p->tw);
+    p->alive = false;
+    delete p;
+    return SE2N_OK;
+}
+
+size_t se2n_workspace_bytes(se2n_plan p) {
+    if (!p || !p->alive) return 0;
+    return p->workspace();
+}
+
+int se2n_precompute(se2n_plan p, double T, double beta, int n_steps, se2n_scheme scheme, void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    rc = check_diffusion_params(T, beta, n_steps, scheme);
+    if (rc) return rc;
+    const void* P = nullptr;
+    return get_propagators(p, T, beta, n_steps, scheme, (hipStream_t)stream, &P);
+}
+
+int se2n_orient(se2n_plan p, const void* f, const uint8_t* mask, double sigma, uint8_t* rmap, void* workspace,
+                void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!f || !mask || !rmap || !workspace) return fail(SE2N_EINVAL, "null pointer argument");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dt == SE2N_F32)
+        return orient_impl<float>(p, (const float*)f, mask, sigma, rmap, split_workspace<float>(p, workspace).spec, st);
+    return orient_impl<double>(p, (const double*)f, mask, sigma, rmap, split_workspace<double>(p, workspace).spec,
+                               st);
+}
+
+int se2n_lift(se2n_plan p, const void* f, const uint8_t* mask, const uint8_t* rmap, void* psi, void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!f || !mask || !rmap || !psi) return fail(SE2N_EINVAL, "null pointer argument");
+    hipStream_t st = (hipStream_t)stream;
+    ProfScope ps(p, "lift", st);
+    hipError_t e = p->dt == SE2N_F32
+                       ? launch_lift<float>((const float*)f, mask, rmap, (float*)psi, p->M, p->N, st)
+                       : launch_lift<double>((const double*)f, mask, rmap, (double*)psi, p->M, p->N, st);
+    if (e != hipSuccess) return hip_fail(e, "lift launch");
+    return SE2N_OK;
+}
+
+int se2n_diffuse(se2n_plan p, void* psi, double T, double beta, int n_steps, se2n_scheme scheme, void* workspace,
+                 void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!psi || !workspace) return fail(SE2N_EINVAL, "null pointer argument");
+    rc = check_diffusion_params(T, beta, n_steps, scheme);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dt == SE2N_F32) return diffuse_impl<float>(p, (float*)psi, T, beta, n_steps, scheme, workspace, st);
+    return diffuse_impl<double>(p, (double*)psi, T, beta, n_steps, scheme, workspace, st);
+}
+
+int se2n_project(se2n_plan p, const void* psi, se2n_proj mode, void* out, void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!psi || !out) return fail(SE2N_EINVAL, "null pointer argument");
+    if (mode != SE2N_PROJ_MAX && mode != SE2N_PROJ_MEAN) return fail(SE2N_EINVAL, "unknown projection %d", (int)mode);
+    hipStream_t st = (hipStream_t)stream;
+    const bool mean = mode == SE2N_PROJ_MEAN;
+    ProfScope ps(p, "project", st);
+    hipError_t e = p->dt == SE2N_F32 ? launch_project<float>((const float*)psi, (float*)out, p->M, p->N, mean, st)
+                                     : launch_project<double>((const double*)psi, (double*)out, p->M, p->N, mean, st);
+    if (e != hipSuccess) return hip_fail(e, "project launch");
+    return SE2N_OK;
+}
+
+int se2n_inpaint(se2n_plan p, const void* f, const uint8_t* mask, double sigma, double T, double beta, int n_steps,
+                 se2n_scheme scheme, se2n_proj mode, const uint8_t* rmap_in, uint8_t* rmap_out, void* out,
+                 void* workspace, void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!f || !mask || !out || !workspace) return fail(SE2N_EINVAL, "null pointer argument");
+    if (!rmap_in && (!(sigma > 0.0) || !std::isfinite(sigma)))
+        return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
+    if (mode != SE2N_PROJ_MAX && mode != SE2N_PROJ_MEAN) return fail(SE2N_EINVAL, "unknown projection %d", (int)mode);
+    rc = check_diffusion_params(T, beta, n_steps, scheme);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dt == SE2N_F32)
+        return inpaint_impl<float>(p, (const float*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in,
+                                   rmap_out, (float*)out, workspace, st);
+    return inpaint_impl<double>(p, (const double*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in, rmap_out,
+                                (double*)out, workspace, st);
+}
+
+int se2n_profile(se2n_plan p, int enable) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    for (auto& r : p->prof_pending) {
+        SE2N_HIP(hipEventSynchronize(r.b), "hipEventSynchronize");
+        p->prof_pool.push_back(r.a);
+        p->prof_pool.push_back(r.b);
+    }
+    p->prof_pending.clear();
+    p->prof_acc.clear();
+    p->prof_on = enable != 0;
+    return SE2N_OK;
+}
+
+int se2n_profile_stats(se2n_plan p, se2n_kernel_stat* out, int capacity, int* count) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!count) return fail(SE2N_EINVAL, "count is NULL");
+    for (auto& r : p->prof_pending) {
+        SE2N_HIP(hipEventSynchronize(r.b), "hipEventSynchronize");
+        float ms = 0.f;
+        SE2N_HIP(hipEventElapsedTime(&ms, r.a, r.b), "hipEventElapsedTime");
+        auto& acc = p->prof_acc[r.name];
+        acc.first += 1;
+        acc.second += ms;
+        p->prof_pool.push_back(r.a);
+        p->prof_pool.push_back(r.b);
+    }
+    p->prof_pending.clear();
+    int i = 0;
+    for (auto& kv : p->prof_acc) {
+        if (out && i < capacity) {
+            std::snprintf(out[i].name, sizeof out[i].name, "%s", kv.first.c_str());
+            out[i].launches = kv.second.first;
+            out[i].total_ms = kv.second.second;
+        }
+        ++i;
+    }
+    *count = i;
+    return SE2N_OK;
+}
+
+const char* se2n_last_error(void) { return g_last_error.c_str(); }
+
+const char* se2n_version(void) { return "se2n 0.1 (gfx950)"; }
+
+}  // extern "C"

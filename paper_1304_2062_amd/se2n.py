@@ -1,0 +1,200 @@
+"""Python binding of libse2n (argument marshalling only).
+
+Every call hands device pointers of torch tensors and the current HIP stream
+to the C ABI declared in include/se2n.h; all arithmetic runs in the library's
+gfx950 kernels.  Importing this module fails when libse2n.so has not been
+built: there is no fallback implementation.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libse2n.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(
+        f"{LIB_PATH} is missing: build it with `python -m paper_1304_2062_amd.build` "
+        "(the HIP library is required; there is no CPU fallback)"
+    )
+
+_lib = ctypes.CDLL(LIB_PATH)
+
+_vp = ctypes.c_void_p
+_i = ctypes.c_int
+_d = ctypes.c_double
+
+_lib.se2n_plan_create.argtypes = [ctypes.POINTER(_vp), _i, _i, _i]
+_lib.se2n_plan_destroy.argtypes = [_vp]
+_lib.se2n_workspace_bytes.argtypes = [_vp]
+_lib.se2n_workspace_bytes.restype = ctypes.c_size_t
+_lib.se2n_precompute.argtypes = [_vp, _d, _d, _i, _i, _vp]
+_lib.se2n_orient.argtypes = [_vp, _vp, _vp, _d, _vp, _vp, _vp]
+_lib.se2n_lift.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
+_lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
+_lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
+_lib.se2n_inpaint.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]
+
+
+class KernelStat(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 32), ("launches", ctypes.c_int), ("total_ms", ctypes.c_double)]
+
+
+_lib.se2n_profile.argtypes = [_vp, _i]
+_lib.se2n_profile.restype = _i
+_lib.se2n_profile_stats.argtypes = [_vp, ctypes.POINTER(KernelStat), _i, ctypes.POINTER(_i)]
+_lib.se2n_profile_stats.restype = _i
+_lib.se2n_last_error.restype = ctypes.c_char_p
+_lib.se2n_version.restype = ctypes.c_char_p
+for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_lift",
+              "se2n_diffuse", "se2n_project", "se2n_inpaint"):
+    getattr(_lib, _name).restype = _i
+
+F32, F64 = 0, 1
+CN, EXACT = 0, 1
+PROJ_MAX, PROJ_MEAN = 0, 1
+
+_SCHEMES = {"cn": CN, "exact": EXACT}
+_PROJ = {"max": PROJ_MAX, "mean": PROJ_MEAN}
+
+
+class Se2nError(RuntimeError):
+    """A negative status returned by the library, with its message."""
+
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"se2n error {code}: {msg}")
+        self.code = code
+
+
+def _check(rc: int) -> None:
+    if rc != 0:
+        raise Se2nError(rc, _lib.se2n_last_error().decode())
+
+
+def version() -> str:
+    return _lib.se2n_version().decode()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else _vp(t.data_ptr())
+
+
+class Plan:
+    """A plan for M x M images and N orientations in float32 or float64."""
+
+    def __init__(self, M: int, N: int, dtype: torch.dtype = torch.float32, device: int | str | None = None):
+        if dtype not in (torch.float32, torch.float64):
+            raise ValueError("dtype must be torch.float32 or torch.float64")
+        self.M, self.N, self.dtype = int(M), int(N), dtype
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(_lib.se2n_plan_create(ctypes.byref(h), self.M, self.N, F32 if dtype == torch.float32 else F64))
+        self._h = h
+        self._ws = None
+
+    # -- helpers -----------------------------------------------------------
+    def _image(self, t: torch.Tensor, name: str, dtype=None) -> torch.Tensor:
+        dtype = self.dtype if dtype is None else dtype
+        if t.device != self.device or t.dtype != dtype or tuple(t.shape) != (self.M, self.M) or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous {dtype} tensor of shape ({self.M}, {self.M}) on {self.device}")
+        return t
+
+    def _volume(self, t: torch.Tensor, name: str) -> torch.Tensor:
+        if (t.device != self.device or t.dtype != self.dtype or tuple(t.shape) != (self.N, self.M, self.M)
+                or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous {self.dtype} tensor of shape "
+                             f"({self.N}, {self.M}, {self.M}) on {self.device}")
+        return t
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(_lib.se2n_workspace_bytes(self._h))
+
+    def workspace(self) -> torch.Tensor:
+        if self._ws is None:
+            self._ws = torch.empty(self.workspace_bytes, dtype=torch.uint8, device=self.device)
+        return self._ws
+
+    # -- the C ABI ---------------------------------------------------------
+    def precompute(self, T: float, beta: float, n_steps: int, scheme: str = "cn") -> None:
+        _check(_lib.se2n_precompute(self._h, float(T), float(beta), int(n_steps), _SCHEMES[scheme], _vp(_stream())))
+
+    def orient(self, f: torch.Tensor, mask: torch.Tensor, sigma: float = 2.0) -> torch.Tensor:
+        self._image(f, "f")
+        self._image(mask, "mask", torch.uint8)
+        rmap = torch.empty((self.M, self.M), dtype=torch.uint8, device=self.device)
+        _check(_lib.se2n_orient(self._h, _ptr(f), _ptr(mask), float(sigma), _ptr(rmap), _ptr(self.workspace()),
+                                _vp(_stream())))
+        return rmap
+
+    def lift(self, f: torch.Tensor, mask: torch.Tensor, rmap: torch.Tensor) -> torch.Tensor:
+        self._image(f, "f")
+        self._image(mask, "mask", torch.uint8)
+        self._image(rmap, "rmap", torch.uint8)
+        psi = torch.empty((self.N, self.M, self.M), dtype=self.dtype, device=self.device)
+        _check(_lib.se2n_lift(self._h, _ptr(f), _ptr(mask), _ptr(rmap), _ptr(psi), _vp(_stream())))
+        return psi
+
+    def diffuse(self, psi: torch.Tensor, T: float, beta: float, n_steps: int, scheme: str = "cn") -> torch.Tensor:
+        """In place; returns psi."""
+        self._volume(psi, "psi")
+        _check(_lib.se2n_diffuse(self._h, _ptr(psi), float(T), float(beta), int(n_steps), _SCHEMES[scheme],
+                                 _ptr(self.workspace()), _vp(_stream())))
+        return psi
+
+    def project(self, psi: torch.Tensor, mode: str = "max") -> torch.Tensor:
+        self._volume(psi, "psi")
+        out = torch.empty((self.M, self.M), dtype=self.dtype, device=self.device)
+        _check(_lib.se2n_project(self._h, _ptr(psi), _PROJ[mode], _ptr(out), _vp(_stream())))
+        return out
+
+    def inpaint(self, f: torch.Tensor, mask: torch.Tensor, T: float, beta: float, n_steps: int,
+                sigma: float = 2.0, scheme: str = "cn", proj: str = "max", rmap_in: torch.Tensor | None = None,
+                out: torch.Tensor | None = None, rmap_out: torch.Tensor | None = None):
+        """Fused orient -> lift -> diffuse -> project.  Returns (out, rmap)."""
+        self._image(f, "f")
+        self._image(mask, "mask", torch.uint8)
+        if rmap_in is not None:
+            self._image(rmap_in, "rmap_in", torch.uint8)
+        if out is None:
+            out = torch.empty((self.M, self.M), dtype=self.dtype, device=self.device)
+        self._image(out, "out")
+        if rmap_out is None:
+            rmap_out = torch.empty((self.M, self.M), dtype=torch.uint8, device=self.device)
+        self._image(rmap_out, "rmap_out", torch.uint8)
+        _check(_lib.se2n_inpaint(self._h, _ptr(f), _ptr(mask), float(sigma), float(T), float(beta), int(n_steps),
+                                 _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_in), _ptr(rmap_out), _ptr(out),
+                                 _ptr(self.workspace()), _vp(_stream())))
+        return out, rmap_out
+
+    def profile(self, enable: bool = True) -> None:
+        """Enable/disable per-kernel event timing (clears the statistics)."""
+        _check(_lib.se2n_profile(self._h, 1 if enable else 0))
+
+    def profile_stats(self) -> dict:
+        """{kernel name: (launches, total ms)} of the launches timed so far (synchronises)."""
+        n = _i(0)
+        _check(_lib.se2n_profile_stats(self._h, None, 0, ctypes.byref(n)))
+        arr = (KernelStat * max(n.value, 1))()
+        _check(_lib.se2n_profile_stats(self._h, arr, n.value, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _check(_lib.se2n_plan_destroy(self._h))
+            self._h = None
+            self._ws = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
