@@ -4,8 +4,9 @@
 //
 // Each stage reads every butterfly's inputs into registers, synchronises,
 // and writes the outputs back to the same LDS buffer, so a transform needs
-// no second buffer.  Twiddles come from one table of w_M^m = exp(-2 pi i m/M)
-// for the plan's side M; a transform of length L | M reads it with stride M/L.
+// no second buffer.  Twiddles come from an LDS copy of the quarter table
+// w_M^r, r <= M/4, of the plan's side M; a transform of length L | M reads it
+// with stride M/L.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -109,36 +110,73 @@ __device__ __forceinline__ void dft(C2<R>* v) {
     else dft8<R, INV>(v);
 }
 
-// Radix sequence of one transform length (host fills it, kernels read it by value).
-struct FftPlan {
-    int L;          // transform length
-    int nstages;    // number of stages
-    int radix[16];  // radix of each stage, 2/3/4/8
+// Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal (inv = 1/d
+// rounded to float): (n + 1/2) inv lies at least 1/(2d) away from an integer,
+// far more than the float rounding of the product.
+__device__ __forceinline__ int fdiv(int n, float inv) { return (int)(((float)n + 0.5f) * inv); }
+
+// One stage of a Stockham transform (filled on the host).
+struct FftStage {
+    int radix;      // 2, 3, 4 or 8
+    int nb;         // butterflies per transform = L / radix
+    int Ns;         // product of the radices of the earlier stages
+    int twstep;     // M / (Ns * radix): twiddle w_{Ns radix}^e = w_M^{e twstep}
+    float inv_nb;   // 1/nb
+    float inv_Ns;   // 1/Ns
 };
 
+// Radix sequence of one transform length.
+struct FftPlan {
+    int L;
+    int nstages;
+    FftStage st[12];
+};
+
+// w_M^m = exp(-2 pi i m / M) for m in [0, M) from the quarter table
+// q[r] = w_M^r, r in [0, M/4]: w_M^{a M/4 + r} = (-i)^a w_M^r.
+template <class R>
+__device__ __forceinline__ C2<R> tw_get(const C2<R>* q, int M4, int m) {
+    const int a = (m >= M4) + (m >= 2 * M4) + (m >= 3 * M4);
+    const C2<R> w = q[m - a * M4];
+    if (a == 0) return w;
+    if (a == 1) return cmk<R>(w.y, -w.x);
+    if (a == 2) return cmk<R>(-w.x, -w.y);
+    return cmk<R>(-w.y, w.x);
+}
+
+// Copy the quarter twiddle table into LDS (callers synchronise afterwards).
+template <class R>
+__device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restrict__ src, int M4, int tid,
+                                              int nthr) {
+    for (int i = tid; i <= M4; i += nthr) dst[i] = src[i];
+}
+
 // One Stockham stage, in place.  `nbatch` transforms of length L start at
-// buf + t*bstride.  Ns is the product of the radices of the earlier stages.
-// Butterfly j of a transform reads x[j + r L/RADIX], multiplies input r by
-// w_{Ns RADIX}^{r (j mod Ns)}, and writes output r to
-// (j / Ns) Ns RADIX + (j mod Ns) + r Ns.
+// buf + t*bstride.  Butterfly j of a transform reads x[j + r L/RADIX],
+// multiplies input r by w_{Ns RADIX}^{r (j mod Ns)}, and writes output r to
+// (j / Ns) Ns RADIX + (j mod Ns) + r Ns.  Every thread first reads all its
+// butterflies, the block synchronises, then every thread writes.
 // The caller guarantees nbatch*L <= EPT*nthr.
 template <class R, int RADIX, bool INV, int EPT>
-__device__ __forceinline__ void fft_stage(C2<R>* buf, int L, int Ns, int nbatch, int bstride,
-                                          const C2<R>* __restrict__ tw, int M, int tid, int nthr) {
+__device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nbatch, int bstride,
+                                          const C2<R>* twq, int M4, int tid, int nthr) {
     constexpr int MAXB = (EPT + RADIX - 1) / RADIX;
-    const int nb = L / RADIX;
-    const int total = nb * nbatch;
-    const int twstep = M / (Ns * RADIX);
+    const int total = s.nb * nbatch;
     C2<R> v[MAXB][RADIX];
+    int obase[MAXB], kk[MAXB];
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthr;
         if (b < total) {
-            const int t = b / nb;
-            const int j = b - t * nb;
-            const C2<R>* s = buf + t * bstride + j;
+            const int t = fdiv(b, s.inv_nb);
+            const int j = b - t * s.nb;
+            const int q = fdiv(j, s.inv_Ns);
+            const int k = j - q * s.Ns;
+            const int ib = t * bstride + j;
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[i][r] = s[r * nb];
+            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[ib + r * s.nb];
+            obase[i] = t * bstride + q * s.Ns * RADIX + k;
+            kk[i] = k;
         }
     }
     __syncthreads();
@@ -146,21 +184,18 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, int L, int Ns, int nbatch,
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthr;
         if (b < total) {
-            const int t = b / nb;
-            const int j = b - t * nb;
-            const int k = j % Ns;
-            if (Ns > 1) {
+            if (s.Ns > 1) {
+                const int e = kk[i] * s.twstep;
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) {
-                    C2<R> w = tw[r * k * twstep];
+                    C2<R> w = tw_get<R>(twq, M4, r * e);
                     if (INV) w.y = -w.y;
                     v[i][r] = cmul<R>(v[i][r], w);
                 }
             }
             dft<R, RADIX, INV>(v[i]);
-            C2<R>* d = buf + t * bstride + (j - k) * RADIX + k;
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) d[r * Ns] = v[i][r];
+            for (int r = 0; r < RADIX; ++r) buf[obase[i] + r * s.Ns] = v[i][r];
         }
     }
     __syncthreads();
@@ -168,18 +203,17 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, int L, int Ns, int nbatch,
 
 // Unnormalised transforms of `nbatch` sequences of length plan.L held in LDS.
 // Forward: X_k = sum_n x_n w_L^{nk}; inverse: the same with w_L^{-nk}.
+// twq is the LDS quarter twiddle table of the plan's side M (M4 = M/4).
 // Must be called by all nthr threads of the workgroup (it synchronises).
 template <class R, bool INV, int EPT>
-__device__ void fft_lds(C2<R>* buf, const FftPlan& plan, int nbatch, int bstride,
-                        const C2<R>* __restrict__ tw, int M, int tid, int nthr) {
-    int Ns = 1;
+__device__ void fft_lds(C2<R>* buf, const FftPlan& plan, int nbatch, int bstride, const C2<R>* twq, int M4,
+                        int tid, int nthr) {
     for (int s = 0; s < plan.nstages; ++s) {
-        const int rad = plan.radix[s];
-        if (rad == 8) fft_stage<R, 8, INV, EPT>(buf, plan.L, Ns, nbatch, bstride, tw, M, tid, nthr);
-        else if (rad == 4) fft_stage<R, 4, INV, EPT>(buf, plan.L, Ns, nbatch, bstride, tw, M, tid, nthr);
-        else if (rad == 3) fft_stage<R, 3, INV, EPT>(buf, plan.L, Ns, nbatch, bstride, tw, M, tid, nthr);
-        else fft_stage<R, 2, INV, EPT>(buf, plan.L, Ns, nbatch, bstride, tw, M, tid, nthr);
-        Ns *= rad;
+        const FftStage& st = plan.st[s];
+        if (st.radix == 8) fft_stage<R, 8, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else if (st.radix == 4) fft_stage<R, 4, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else if (st.radix == 3) fft_stage<R, 3, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else fft_stage<R, 2, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
     }
 }
 

@@ -9,10 +9,6 @@
 
 namespace se2n {
 
-// Elements of an LDS transform batch that each thread stages in registers.
-template <class R>
-__host__ __device__ constexpr int ept() { return sizeof(R) == 4 ? 16 : 8; }
-
 enum { SRC_LIFT = 0, SRC_VOLUME = 1, SRC_IMAGE = 2 };
 enum { DST_MAX = 0, DST_SUM = 1, DST_VOLUME = 2, DST_ORIENT = 3 };
 
@@ -45,15 +41,20 @@ struct Enc<double> {
 };
 
 // Launch geometry of one plan (chosen on the host from M and the dtype).
+// Each FFT workgroup holds its transforms in LDS; every thread stages at most
+// `ept` (8 or 16) complex elements of a stage in registers.
 struct LaunchGeom {
     int rows;         // image rows per row-pass workgroup
     int row_threads;  // threads of a row-pass workgroup
+    int row_ept;
     int row_slices;   // orientation slices per row-pass workgroup (forward)
     int inv_slices;   // orientation slices per row-pass workgroup (inverse, max projection)
     int cols;         // columns per column-pass workgroup
     int col_threads;
+    int col_ept;
     int ocols;        // columns per orientation column workgroup
     int ocol_threads;
+    int ocol_ept;
 };
 
 template <class R>

@@ -31,13 +31,15 @@ namespace se2n {
 // z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
 //   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
 // grid: (M/ROWS row blocks, slice groups); block: nthr threads; LDS ROWS*H.
-template <class R, int SRC>
+template <class R, int SRC, int EPT>
 __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
                           const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
                           C2<R>* __restrict__ spec, int M, int nslices, int slices_per_group,
-                          int rows, FftPlan planH, const C2<R>* __restrict__ tw) {
+                          int rows, FftPlan planH, const C2<R>* __restrict__ twg) {
     extern __shared__ unsigned char smem_raw[];
-    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int M4 = M >> 2;
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
     const int H = M >> 1;
     const int K = H + 1;
     const int tid = threadIdx.x;
@@ -47,8 +49,8 @@ __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ m
     const int s_end = min(nslices, s_begin + slices_per_group);
     const int nel = rows * H;
 
+    load_twiddles<R>(tw, twg, M4, tid, nthr);
     // Lift sources are read once per block and kept in registers.
-    constexpr int EPT = ept<R>();
     R fc0[EPT], fc1[EPT];
     uint8_t rm0[EPT], rm1[EPT];
     if (SRC != SRC_VOLUME) {
@@ -97,7 +99,7 @@ __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ m
             }
         }
         __syncthreads();
-        fft_lds<R, false, EPT>(buf, planH, rows, H, tw, M, tid, nthr);
+        fft_lds<R, false, EPT>(buf, planH, rows, H, tw, M4, tid, nthr);
         // unpack the real transform and write (r, kx, y0..y0+rows) segments
         const int nout = rows * K;
         C2<R>* out = spec + (size_t)s * K * M + y0;
@@ -110,7 +112,7 @@ __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ m
             // (z1 - conj z2)/(2i)
             const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
             const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
-            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw[kx], od));
+            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R>(tw, M4, kx), od));
         }
         __syncthreads();
     }
@@ -119,21 +121,23 @@ __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ m
 // ---------------------------------------------------------------------------
 // Column pass: FFT along y of `cols_per_block` contiguous columns of length M.
 // ---------------------------------------------------------------------------
-template <class R, bool INV>
+template <class R, bool INV, int EPT>
 __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M, int cols_per_block,
-                          FftPlan planM, const C2<R>* __restrict__ tw) {
+                          FftPlan planM, const C2<R>* __restrict__ twg) {
     extern __shared__ unsigned char smem_raw[];
-    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int M4 = M >> 2;
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    constexpr int EPT = ept<R>();
+    load_twiddles<R>(tw, twg, M4, tid, nthr);
     const long c0 = (long)blockIdx.x * cols_per_block;
     const int ncb = (int)min((long)cols_per_block, ncols - c0);
     const int nel = ncb * M;
     C2<R>* base = spec + c0 * M;
     for (int e = tid; e < nel; e += nthr) buf[e] = base[e];
     __syncthreads();
-    fft_lds<R, INV, EPT>(buf, planM, ncb, M, tw, M, tid, nthr);
+    fft_lds<R, INV, EPT>(buf, planM, ncb, M, tw, M4, tid, nthr);
     for (int e = tid; e < nel; e += nthr) base[e] = buf[e];
 }
 
@@ -145,16 +149,18 @@ __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M, int cols_
 //   s_k = sin(2 pi k/M), g(k) = exp(-2 pi^2 sigma^2 kbar^2 / M^2).
 // (The 1/M^2 only keeps magnitudes moderate; the angle ignores it.)
 // ---------------------------------------------------------------------------
-template <class R>
+template <class R, int EPT>
 __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block, FftPlan planM,
-                             const C2<R>* __restrict__ tw, R neg_two_pi2_sigma2_over_M2, R scale) {
+                             const C2<R>* __restrict__ twg, R neg_two_pi2_sigma2_over_M2, R scale) {
     extern __shared__ unsigned char smem_raw[];
-    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int M4 = M >> 2;
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
     const int H = M >> 1;
     const int K = H + 1;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    constexpr int EPT = ept<R>();
+    load_twiddles<R>(tw, twg, M4, tid, nthr);
     const int c0 = blockIdx.x * cols_per_block;
     const int ncb = min(cols_per_block, K - c0);
     const int nel = ncb * M;
@@ -162,14 +168,14 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
     C2<R>* gy = spec + ((size_t)K + c0) * M;
     for (int e = tid; e < nel; e += nthr) buf[e] = gx[e];
     __syncthreads();
-    fft_lds<R, false, EPT>(buf, planM, ncb, M, tw, M, tid, nthr);
+    fft_lds<R, false, EPT>(buf, planM, ncb, M, tw, M4, tid, nthr);
     C2<R>* buf2 = buf + nel;
     for (int e = tid; e < nel; e += nthr) {
         const int col = e / M;
         const int ky = e - col * M;
         const int kx = c0 + col;
-        const R skx = -tw[kx].y;
-        const R sky = -tw[ky].y;
+        const R skx = -tw_get<R>(tw, M4, kx).y;
+        const R sky = -tw_get<R>(tw, M4, ky).y;
         const R kxb = (R)kx;                            // kx <= M/2; (M/2)^2 = (-M/2)^2
         const R kyb = (R)(ky < H ? ky : ky - M);
         const R g = exp(neg_two_pi2_sigma2_over_M2 * (kxb * kxb + kyb * kyb)) * scale;
@@ -179,7 +185,7 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
         buf2[e] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
     }
     __syncthreads();
-    fft_lds<R, true, EPT>(buf, planM, 2 * ncb, M, tw, M, tid, nthr);
+    fft_lds<R, true, EPT>(buf, planM, 2 * ncb, M, tw, M4, tid, nthr);
     for (int e = tid; e < nel; e += nthr) {
         gx[e] = buf[e];
         gy[e] = buf2[e];
@@ -193,13 +199,15 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int DST>
+template <class R, int DST, int EPT>
 __global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                           int M, int nslices, int slices_per_group, int rows, int N, R out_scale,
-                          FftPlan planH, const C2<R>* __restrict__ tw) {
+                          FftPlan planH, const C2<R>* __restrict__ twg) {
     extern __shared__ unsigned char smem_raw[];
-    C2<R>* buf = reinterpret_cast<C2<R>*>(smem_raw);
+    const int M4 = M >> 2;
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
     const int H = M >> 1;
     const int K = H + 1;
     const int S = H + 1;  // LDS row stride
@@ -210,7 +218,7 @@ __global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
     const int s_end = min(nslices, s_begin + slices_per_group);
     const int nel = rows * H;
 
-    constexpr int EPT = ept<R>();
+    load_twiddles<R>(tw, twg, M4, tid, nthr);
     C2<R> acc[EPT], acc2[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -238,20 +246,20 @@ __global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
             // Z[k]
             const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);      // a + conj b
             const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);      // a - conj b
-            const C2<R> wa = cconj<R>(tw[k]);
+            const C2<R> wa = cconj<R>(tw_get<R>(tw, M4, k));
             const C2<R> ta = cmul<R>(wa, da);
             const C2<R> za = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
             // Z[H-k]
             const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
             const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
-            const C2<R> wb = cconj<R>(tw[kk]);
+            const C2<R> wb = cconj<R>(tw_get<R>(tw, M4, kk));
             const C2<R> tb = cmul<R>(wb, db);
             const C2<R> zb = cmk<R>(sb.x - tb.y, sb.y + tb.x);
             buf[row * S + k] = za;
             if (kk != k) buf[row * S + kk] = zb;
         }
         __syncthreads();
-        fft_lds<R, true, EPT>(buf, planH, rows, S, tw, M, tid, nthr);
+        fft_lds<R, true, EPT>(buf, planH, rows, S, tw, M4, tid, nthr);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + i * nthr;
@@ -510,21 +518,28 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
 // Launchers (host side, called by the runtime with validated arguments).
 // ---------------------------------------------------------------------------
 template <class R>
+static size_t tw_bytes(int M) {
+    return (size_t)(((M / 4 + 1) + 7) & ~7) * sizeof(C2<R>);
+}
+
+template <class R>
 hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_t* rmap, const R* vol,
                           C2<R>* spec, int M, int nslices, const LaunchGeom& g, const FftPlan& planH,
                           const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + g.row_slices - 1) / g.row_slices;
     dim3 grid(M / g.rows, groups);
-    const size_t lds = (size_t)g.rows * (M / 2) * sizeof(C2<R>);
-    if (src == SRC_LIFT)
-        hipLaunchKernelGGL((k_row_fwd<R, SRC_LIFT>), grid, dim3(g.row_threads), lds, st, f, mask, rmap,
-                           vol, spec, M, nslices, g.row_slices, g.rows, planH, tw);
-    else if (src == SRC_VOLUME)
-        hipLaunchKernelGGL((k_row_fwd<R, SRC_VOLUME>), grid, dim3(g.row_threads), lds, st, f, mask,
-                           rmap, vol, spec, M, nslices, g.row_slices, g.rows, planH, tw);
-    else
-        hipLaunchKernelGGL((k_row_fwd<R, SRC_IMAGE>), grid, dim3(g.row_threads), lds, st, f, mask,
-                           rmap, vol, spec, M, nslices, g.row_slices, g.rows, planH, tw);
+    const size_t lds = tw_bytes<R>(M) + (size_t)g.rows * (M / 2) * sizeof(C2<R>);
+#define SE2N_ROWFWD(S, E)                                                                               \
+    hipLaunchKernelGGL((k_row_fwd<R, S, E>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol, spec, \
+                       M, nslices, g.row_slices, g.rows, planH, tw)
+#define SE2N_ROWFWD_E(S)               \
+    if (g.row_ept == 8) SE2N_ROWFWD(S, 8); \
+    else SE2N_ROWFWD(S, 16);
+    if (src == SRC_LIFT) { SE2N_ROWFWD_E(SRC_LIFT) }
+    else if (src == SRC_VOLUME) { SE2N_ROWFWD_E(SRC_VOLUME) }
+    else { SE2N_ROWFWD_E(SRC_IMAGE) }
+#undef SE2N_ROWFWD_E
+#undef SE2N_ROWFWD
     return hipGetLastError();
 }
 
@@ -532,13 +547,17 @@ template <class R>
 hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
                           const FftPlan& planM, const C2<R>* tw, hipStream_t st) {
     dim3 grid((unsigned)((ncols + g.cols - 1) / g.cols));
-    const size_t lds = (size_t)g.cols * M * sizeof(C2<R>);
-    if (inverse)
-        hipLaunchKernelGGL((k_col_fft<R, true>), grid, dim3(g.col_threads), lds, st, spec, ncols, M,
-                           g.cols, planM, tw);
-    else
-        hipLaunchKernelGGL((k_col_fft<R, false>), grid, dim3(g.col_threads), lds, st, spec, ncols, M,
-                           g.cols, planM, tw);
+    const size_t lds = tw_bytes<R>(M) + (size_t)g.cols * M * sizeof(C2<R>);
+#define SE2N_COL(I, E) \
+    hipLaunchKernelGGL((k_col_fft<R, I, E>), grid, dim3(g.col_threads), lds, st, spec, ncols, M, g.cols, planM, tw)
+    if (inverse) {
+        if (g.col_ept == 8) SE2N_COL(true, 8);
+        else SE2N_COL(true, 16);
+    } else {
+        if (g.col_ept == 8) SE2N_COL(false, 8);
+        else SE2N_COL(false, 16);
+    }
+#undef SE2N_COL
     return hipGetLastError();
 }
 
@@ -547,11 +566,15 @@ hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftP
                              const C2<R>* tw, double sigma, hipStream_t st) {
     const int K = M / 2 + 1;
     dim3 grid((K + g.ocols - 1) / g.ocols);
-    const size_t lds = 2 * (size_t)g.ocols * M * sizeof(C2<R>);
+    const size_t lds = tw_bytes<R>(M) + 2 * (size_t)g.ocols * M * sizeof(C2<R>);
     const double c = -2.0 * 9.869604401089358619 * sigma * sigma / ((double)M * M);
     const double scale = sqrt((double)M) / ((double)M * M);
-    hipLaunchKernelGGL((k_col_orient<R>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols, planM,
-                       tw, (R)c, (R)scale);
+    if (g.ocol_ept == 8)
+        hipLaunchKernelGGL((k_col_orient<R, 8>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols, planM,
+                           tw, (R)c, (R)scale);
+    else
+        hipLaunchKernelGGL((k_col_orient<R, 16>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols, planM,
+                           tw, (R)c, (R)scale);
     return hipGetLastError();
 }
 
@@ -561,14 +584,18 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                           int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
     dim3 grid(M / g.rows, groups);
-    const size_t lds = (size_t)g.rows * (M / 2 + 1) * sizeof(C2<R>);
-#define SE2N_ROWINV(D)                                                                               \
-    hipLaunchKernelGGL((k_row_inv<R, D>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap, M, \
+    const size_t lds = tw_bytes<R>(M) + (size_t)g.rows * (M / 2 + 1) * sizeof(C2<R>);
+#define SE2N_ROWINV(D, E)                                                                                    \
+    hipLaunchKernelGGL((k_row_inv<R, D, E>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap, M,      \
                        nslices, slices_per_group, g.rows, N, out_scale, planH, tw)
-    if (dst == DST_MAX) SE2N_ROWINV(DST_MAX);
-    else if (dst == DST_SUM) SE2N_ROWINV(DST_SUM);
-    else if (dst == DST_VOLUME) SE2N_ROWINV(DST_VOLUME);
-    else SE2N_ROWINV(DST_ORIENT);
+#define SE2N_ROWINV_E(D)               \
+    if (g.row_ept == 8) SE2N_ROWINV(D, 8); \
+    else SE2N_ROWINV(D, 16);
+    if (dst == DST_MAX) { SE2N_ROWINV_E(DST_MAX) }
+    else if (dst == DST_SUM) { SE2N_ROWINV_E(DST_SUM) }
+    else if (dst == DST_VOLUME) { SE2N_ROWINV_E(DST_VOLUME) }
+    else { SE2N_ROWINV_E(DST_ORIENT) }
+#undef SE2N_ROWINV_E
 #undef SE2N_ROWINV
     return hipGetLastError();
 }

@@ -50,26 +50,37 @@ bool is_2a3b(int M, int* twos, int* threes) {
     return m == 1;
 }
 
-// Radix sequence of a length-L transform, L = 2^a 3^b: radix 8 where possible,
-// then 4 (or 4,4 in place of 8,2), then radix 3.
-FftPlan make_fft_plan(int L) {
+// Radix sequence of a length-L transform, L = 2^a 3^b dividing M: radix 8
+// where possible, then 4 (or 4,4 in place of 8,2), then radix 3.
+FftPlan make_fft_plan(int L, int M) {
     FftPlan p{};
     p.L = L;
     int a = 0, b = 0;
     is_2a3b(L, &a, &b);
-    int n = 0;
+    int rad[16], n = 0;
     int q = a / 3, r = a % 3;
     if (r == 1 && q >= 1) {
-        for (int i = 0; i < q - 1; ++i) p.radix[n++] = 8;
-        p.radix[n++] = 4;
-        p.radix[n++] = 4;
+        for (int i = 0; i < q - 1; ++i) rad[n++] = 8;
+        rad[n++] = 4;
+        rad[n++] = 4;
     } else {
-        for (int i = 0; i < q; ++i) p.radix[n++] = 8;
-        if (r == 1) p.radix[n++] = 2;
-        if (r == 2) p.radix[n++] = 4;
+        for (int i = 0; i < q; ++i) rad[n++] = 8;
+        if (r == 1) rad[n++] = 2;
+        if (r == 2) rad[n++] = 4;
     }
-    for (int i = 0; i < b; ++i) p.radix[n++] = 3;
+    for (int i = 0; i < b; ++i) rad[n++] = 3;
     p.nstages = n;
+    int Ns = 1;
+    for (int i = 0; i < n; ++i) {
+        FftStage& s = p.st[i];
+        s.radix = rad[i];
+        s.nb = L / rad[i];
+        s.Ns = Ns;
+        s.twstep = M / (Ns * rad[i]);
+        s.inv_nb = 1.0f / (float)s.nb;
+        s.inv_Ns = 1.0f / (float)Ns;
+        Ns *= rad[i];
+    }
     return p;
 }
 
@@ -96,7 +107,7 @@ struct se2n_plan_s {
     int M = 0, N = 0;
     se2n_dtype dt = SE2N_F32;
     int device = 0;
-    void* tw = nullptr;  // w_M^m, m < M, in the plan dtype
+    void* tw = nullptr;  // w_M^m, m <= M/4, in the plan dtype
     FftPlan planH{}, planM{};
     LaunchGeom geom{};
     std::list<CacheEntry> cache;  // most recently used first
@@ -172,16 +183,25 @@ struct ProfScope {
         SE2N_HIP(call, what);                  \
     } while (0)
 
+// Threads and per-thread staging for `elems` complex elements in one workgroup.
+void fft_threads(int elems, int* threads, int* ept) {
+    *ept = 8;
+    *threads = (elems + 7) / 8;
+    if (*threads > 1024) {
+        *ept = 16;
+        *threads = (elems + 15) / 16;
+    }
+}
+
 template <class R>
 LaunchGeom make_geom(int M, int N) {
-    constexpr int EPT = ept<R>();
     const int target = sizeof(R) == 4 ? 4096 : 2048;  // complex elements per FFT workgroup
     const int H = M / 2;
     LaunchGeom g{};
     int rows = 64 / (int)sizeof(C2<R>);  // 64-byte segments per (slice, kx)
     while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
     g.rows = rows;
-    g.row_threads = (rows * H + EPT - 1) / EPT;
+    fft_threads(rows * H, &g.row_threads, &g.row_ept);
     const int row_blocks = M / rows;
     int groups = (1024 + row_blocks - 1) / row_blocks;
     if (groups > N) groups = N;
@@ -189,9 +209,9 @@ LaunchGeom make_geom(int M, int N) {
     g.row_slices = (N + groups - 1) / groups;
     g.inv_slices = g.row_slices;
     g.cols = target / M > 1 ? target / M : 1;
-    g.col_threads = (g.cols * M + EPT - 1) / EPT;
+    fft_threads(g.cols * M, &g.col_threads, &g.col_ept);
     g.ocols = target / (2 * M) > 1 ? target / (2 * M) : 1;
-    g.ocol_threads = (2 * g.ocols * M + EPT - 1) / EPT;
+    fft_threads(2 * g.ocols * M, &g.ocol_threads, &g.ocol_ept);
     return g;
 }
 
@@ -375,18 +395,20 @@ int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_s
     return SE2N_OK;
 }
 
+// Quarter table w_M^m = exp(-2 pi i m / M), m in [0, M/4], evaluated in
+// extended precision before rounding to the plan dtype.
 template <class R>
 int make_twiddles(se2n_plan p) {
     const int M = p->M;
-    std::vector<C2<R>> h(M);
-    for (int m = 0; m < M; ++m) {
-        // exp(-2 pi i m / M), evaluated in extended precision before rounding
+    const int n = M / 4 + 1;
+    std::vector<C2<R>> h(n);
+    for (int m = 0; m < n; ++m) {
         const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)M;
         h[m].x = (R)(double)cosl(a);
         h[m].y = (R)(double)(-sinl(a));
     }
-    SE2N_HIP(hipMalloc(&p->tw, (size_t)M * sizeof(C2<R>)), "hipMalloc twiddles");
-    SE2N_HIP(hipMemcpy(p->tw, h.data(), (size_t)M * sizeof(C2<R>), hipMemcpyHostToDevice), "twiddle upload");
+    SE2N_HIP(hipMalloc(&p->tw, (size_t)n * sizeof(C2<R>)), "hipMalloc twiddles");
+    SE2N_HIP(hipMemcpy(p->tw, h.data(), (size_t)n * sizeof(C2<R>), hipMemcpyHostToDevice), "twiddle upload");
     return SE2N_OK;
 }
 
@@ -409,8 +431,8 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     p->N = N;
     p->dt = dtype;
     (void)hipGetDevice(&p->device);
-    p->planH = make_fft_plan(M / 2);
-    p->planM = make_fft_plan(M);
+    p->planH = make_fft_plan(M / 2, M);
+    p->planM = make_fft_plan(M, M);
     int rc;
     if (dtype == SE2N_F32) {
         p->geom = make_geom<float>(M, N);
