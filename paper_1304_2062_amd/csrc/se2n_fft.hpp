@@ -110,6 +110,12 @@ __device__ __forceinline__ void dft(C2<R>* v) {
     else dft8<R, INV>(v);
 }
 
+// LDS position of logical element i of a transform buffer: one complex of
+// padding after every 16 keeps the strided writes of the early Stockham
+// stages (stride radix * 8 or 16 bytes) spread over the banks.
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
+__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 4) + 1; }
+
 // Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal (inv = 1/d
 // rounded to float): (n + 1/2) inv lies at least 1/(2d) away from an integer,
 // far more than the float rounding of the product.
@@ -151,14 +157,28 @@ __device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restric
     for (int i = tid; i <= M4; i += nthr) dst[i] = src[i];
 }
 
+// Synchronisation of a stage: the whole workgroup, or one wavefront that owns
+// its transforms alone (a wavefront issues its LDS operations in order, so a
+// compiler-level barrier with wavefront-scope fences suffices).
+template <bool WAVE>
+__device__ __forceinline__ void fft_sync() {
+    if (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // One Stockham stage, in place.  `nbatch` transforms of length L start at
-// buf + t*bstride.  Butterfly j of a transform reads x[j + r L/RADIX],
+// buf + (tbase + t)*bstride.  Butterfly j of a transform reads x[j + r L/RADIX],
 // multiplies input r by w_{Ns RADIX}^{r (j mod Ns)}, and writes output r to
 // (j / Ns) Ns RADIX + (j mod Ns) + r Ns.  Every thread first reads all its
 // butterflies, the block synchronises, then every thread writes.
 // The caller guarantees nbatch*L <= EPT*nthr.
-template <class R, int RADIX, bool INV, int EPT>
-__device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nbatch, int bstride,
+template <class R, int RADIX, bool INV, int EPT, bool WAVE>
+__device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nbatch, int bstride, int tbase,
                                           const C2<R>* twq, int M4, int tid, int nthr) {
     constexpr int MAXB = (EPT + RADIX - 1) / RADIX;
     const int total = s.nb * nbatch;
@@ -172,14 +192,14 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
             const int j = b - t * s.nb;
             const int q = fdiv(j, s.inv_Ns);
             const int k = j - q * s.Ns;
-            const int ib = t * bstride + j;
+            const int ib = (tbase + t) * bstride + j;
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[ib + r * s.nb];
-            obase[i] = t * bstride + q * s.Ns * RADIX + k;
+            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * s.nb)];
+            obase[i] = (tbase + t) * bstride + q * s.Ns * RADIX + k;
             kk[i] = k;
         }
     }
-    __syncthreads();
+    fft_sync<WAVE>();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthr;
@@ -195,25 +215,28 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
             }
             dft<R, RADIX, INV>(v[i]);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[obase[i] + r * s.Ns] = v[i][r];
+            for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * s.Ns)] = v[i][r];
         }
     }
-    __syncthreads();
+    fft_sync<WAVE>();
 }
 
-// Unnormalised transforms of `nbatch` sequences of length plan.L held in LDS.
+// Unnormalised transforms of `nbatch` sequences of length plan.L held in LDS
+// (logical element i of the buffer at buf[lds_pad(i)]).
 // Forward: X_k = sum_n x_n w_L^{nk}; inverse: the same with w_L^{-nk}.
 // twq is the LDS quarter twiddle table of the plan's side M (M4 = M/4).
-// Must be called by all nthr threads of the workgroup (it synchronises).
-template <class R, bool INV, int EPT>
+// Block mode (WAVE = false): all nthr threads of the workgroup call it and it
+// synchronises the workgroup.  Wave mode: one wavefront (tid = lane,
+// nthr = 64) transforms sequences tbase .. tbase+nbatch-1 on its own.
+template <class R, bool INV, int EPT, bool WAVE = false>
 __device__ void fft_lds(C2<R>* buf, const FftPlan& plan, int nbatch, int bstride, const C2<R>* twq, int M4,
-                        int tid, int nthr) {
+                        int tid, int nthr, int tbase = 0) {
     for (int s = 0; s < plan.nstages; ++s) {
         const FftStage& st = plan.st[s];
-        if (st.radix == 8) fft_stage<R, 8, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
-        else if (st.radix == 4) fft_stage<R, 4, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
-        else if (st.radix == 3) fft_stage<R, 3, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
-        else fft_stage<R, 2, INV, EPT>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        if (st.radix == 8) fft_stage<R, 8, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
+        else if (st.radix == 4) fft_stage<R, 4, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
+        else if (st.radix == 3) fft_stage<R, 3, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
+        else fft_stage<R, 2, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
     }
 }
 

@@ -55,6 +55,8 @@ struct LaunchGeom {
     int ocols;        // columns per orientation column workgroup
     int ocol_threads;
     int ocol_ept;
+    int xcd_pair;     // pair adjacent row blocks on one XCD (row passes)
+    int row_wave;     // row transforms run one per wavefront (rows*64 threads)
 };
 
 template <class R>

@@ -24,6 +24,26 @@
 
 namespace se2n {
 
+// Workgroup -> (row block, slice group) of a row pass launched on a 1-D grid.
+// The dispatcher hands consecutive workgroups to the 8 XCDs in turn.  With
+// `pair` set, row blocks 2j and 2j+1 of one slice group go to two workgroups
+// that the same XCD runs back to back, so both 64-byte halves of every
+// 128-byte line of a (slice, kx) column run are fetched through one L2.
+__device__ __forceinline__ void row_block_of(int nrb, int ngroups, bool pair, int& rb, int& g) {
+    const int i = blockIdx.x;
+    if (pair && (nrb & 1) == 0 && ((nrb * ngroups) & 15) == 0) {
+        const int xcd = i & 7;
+        const int slot = i >> 3;
+        const int pr = (slot >> 1) * 8 + xcd;
+        const int per_group = nrb >> 1;
+        g = pr / per_group;
+        rb = 2 * (pr - g * per_group) + (slot & 1);
+    } else {
+        g = i / nrb;
+        rb = i - g * nrb;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass, forward: lift + R2C along x, written transposed.
 // ---------------------------------------------------------------------------
@@ -31,11 +51,11 @@ namespace se2n {
 // z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
 //   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
 // grid: (M/ROWS row blocks, slice groups); block: nthr threads; LDS ROWS*H.
-template <class R, int SRC, int EPT>
-__global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
+template <class R, int SRC, int EPT, bool WAVE>
+__global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
                           const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
                           C2<R>* __restrict__ spec, int M, int nslices, int slices_per_group,
-                          int rows, FftPlan planH, const C2<R>* __restrict__ twg) {
+                          int rows, int xcd_pair, FftPlan planH, const C2<R>* __restrict__ twg) {
     extern __shared__ unsigned char smem_raw[];
     const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
@@ -44,8 +64,10 @@ __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ m
     const int K = H + 1;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int y0 = blockIdx.x * rows;
-    const int s_begin = blockIdx.y * slices_per_group;
+    int rb, grp;
+    row_block_of(M / rows, (nslices + slices_per_group - 1) / slices_per_group, xcd_pair != 0, rb, grp);
+    const int y0 = rb * rows;
+    const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     const int nel = rows * H;
 
@@ -95,19 +117,26 @@ __global__ void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ m
                     z.x = fc0[i];
                     z.y = fc1[i];
                 }
-                buf[e] = z;
+                buf[lds_pad(e)] = z;
             }
         }
         __syncthreads();
-        fft_lds<R, false, EPT>(buf, planH, rows, H, tw, M4, tid, nthr);
+        if (WAVE) {
+            // one wavefront per row, no workgroup barrier inside the transform
+            const int w = tid >> 6;
+            if (w < rows) fft_lds<R, false, EPT, true>(buf, planH, 1, H, tw, M4, tid & 63, 64, w);
+            __syncthreads();
+        } else {
+            fft_lds<R, false, EPT>(buf, planH, rows, H, tw, M4, tid, nthr);
+        }
         // unpack the real transform and write (r, kx, y0..y0+rows) segments
         const int nout = rows * K;
         C2<R>* out = spec + (size_t)s * K * M + y0;
         for (int e = tid; e < nout; e += nthr) {
             const int kx = e / rows;
             const int row = e - kx * rows;
-            const C2<R> z1 = buf[row * H + (kx == H ? 0 : kx)];
-            const C2<R> z2 = buf[row * H + (kx == 0 ? 0 : H - kx)];
+            const C2<R> z1 = buf[lds_pad(row * H + (kx == H ? 0 : kx))];
+            const C2<R> z2 = buf[lds_pad(row * H + (kx == 0 ? 0 : H - kx))];
             const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
             // (z1 - conj z2)/(2i)
             const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
@@ -135,10 +164,10 @@ __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M, int cols_
     const int ncb = (int)min((long)cols_per_block, ncols - c0);
     const int nel = ncb * M;
     C2<R>* base = spec + c0 * M;
-    for (int e = tid; e < nel; e += nthr) buf[e] = base[e];
+    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
     __syncthreads();
     fft_lds<R, INV, EPT>(buf, planM, ncb, M, tw, M4, tid, nthr);
-    for (int e = tid; e < nel; e += nthr) base[e] = buf[e];
+    for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
 }
 
 // ---------------------------------------------------------------------------
@@ -166,10 +195,9 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
     const int nel = ncb * M;
     C2<R>* gx = spec + (size_t)c0 * M;
     C2<R>* gy = spec + ((size_t)K + c0) * M;
-    for (int e = tid; e < nel; e += nthr) buf[e] = gx[e];
+    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = gx[e];
     __syncthreads();
     fft_lds<R, false, EPT>(buf, planM, ncb, M, tw, M4, tid, nthr);
-    C2<R>* buf2 = buf + nel;
     for (int e = tid; e < nel; e += nthr) {
         const int col = e / M;
         const int ky = e - col * M;
@@ -179,16 +207,16 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
         const R kxb = (R)kx;                            // kx <= M/2; (M/2)^2 = (-M/2)^2
         const R kyb = (R)(ky < H ? ky : ky - M);
         const R g = exp(neg_two_pi2_sigma2_over_M2 * (kxb * kxb + kyb * kyb)) * scale;
-        const C2<R> F = buf[e];
+        const C2<R> F = buf[lds_pad(e)];
         const C2<R> iF = cmk<R>(-F.y, F.x);
-        buf[e] = cmk<R>(iF.x * skx * g, iF.y * skx * g);
-        buf2[e] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
+        buf[lds_pad(e)] = cmk<R>(iF.x * skx * g, iF.y * skx * g);
+        buf[lds_pad(nel + e)] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
     }
     __syncthreads();
     fft_lds<R, true, EPT>(buf, planM, 2 * ncb, M, tw, M4, tid, nthr);
     for (int e = tid; e < nel; e += nthr) {
-        gx[e] = buf[e];
-        gy[e] = buf2[e];
+        gx[e] = buf[lds_pad(e)];
+        gy[e] = buf[lds_pad(nel + e)];
     }
 }
 
@@ -199,11 +227,11 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int DST, int EPT>
-__global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
+template <class R, int DST, int EPT, bool WAVE>
+__global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
-                          int M, int nslices, int slices_per_group, int rows, int N, R out_scale,
-                          FftPlan planH, const C2<R>* __restrict__ twg) {
+                          int M, int nslices, int slices_per_group, int rows, int xcd_pair, int N,
+                          R out_scale, FftPlan planH, const C2<R>* __restrict__ twg) {
     extern __shared__ unsigned char smem_raw[];
     const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
@@ -213,8 +241,10 @@ __global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
     const int S = H + 1;  // LDS row stride
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    const int y0 = blockIdx.x * rows;
-    const int s_begin = blockIdx.y * slices_per_group;
+    int rb, grp;
+    row_block_of(M / rows, (nslices + slices_per_group - 1) / slices_per_group, xcd_pair != 0, rb, grp);
+    const int y0 = rb * rows;
+    const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     const int nel = rows * H;
 
@@ -227,22 +257,37 @@ __global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
         acc2[i] = cmk<R>(R(0), R(0));
     }
 
+    // The next slice's (kx, row) segments are loaded into registers while the
+    // current slice is transformed.  Thread t reads row t mod rows of columns
+    // kx = t/rows + i*kstep (rows and nthr are multiples of each other).
+    constexpr int MAXL = EPT + 2;
+    const int rshift = __ffs(rows) - 1;  // rows is a power of two
+    const int row_t = tid & (rows - 1);
+    const int kx_t = tid >> rshift;
+    const int kstep = nthr >> rshift;
+    C2<R> pre[MAXL];
+#define SE2N_FETCH(SL)                                                                      \
+    do {                                                                                   \
+        const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;    \
+        _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < K) pre[i] = \
+            in_[(size_t)(i * kstep) * M];                                                   \
+    } while (0)
+    SE2N_FETCH(s_begin);
     for (int s = s_begin; s < s_end; ++s) {
-        const C2<R>* in = spec + (size_t)s * K * M + y0;
-        const int nin = rows * K;
-        for (int e = tid; e < nin; e += nthr) {
-            const int kx = e / rows;
-            const int row = e - kx * rows;
-            buf[row * S + kx] = in[(size_t)kx * M + row];
+#pragma unroll
+        for (int i = 0; i < MAXL; ++i) {
+            const int kx = kx_t + i * kstep;
+            if (kx < K) buf[lds_pad(row_t * S + kx)] = pre[i];
         }
         __syncthreads();
+        if (s + 1 < s_end) SE2N_FETCH(s + 1);
         const int npair = H / 2 + 1;
         for (int e = tid; e < rows * npair; e += nthr) {
             const int row = e / npair;
             const int k = e - row * npair;
             const int kk = H - k;
-            const C2<R> a = buf[row * S + k];
-            const C2<R> b = buf[row * S + kk];
+            const C2<R> a = buf[lds_pad(row * S + k)];
+            const C2<R> b = buf[lds_pad(row * S + kk)];
             // Z[k]
             const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);      // a + conj b
             const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);      // a - conj b
@@ -255,18 +300,24 @@ __global__ void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
             const C2<R> wb = cconj<R>(tw_get<R>(tw, M4, kk));
             const C2<R> tb = cmul<R>(wb, db);
             const C2<R> zb = cmk<R>(sb.x - tb.y, sb.y + tb.x);
-            buf[row * S + k] = za;
-            if (kk != k) buf[row * S + kk] = zb;
+            buf[lds_pad(row * S + k)] = za;
+            if (kk != k) buf[lds_pad(row * S + kk)] = zb;
         }
         __syncthreads();
-        fft_lds<R, true, EPT>(buf, planH, rows, S, tw, M4, tid, nthr);
+        if (WAVE) {
+            const int w = tid >> 6;
+            if (w < rows) fft_lds<R, true, EPT, true>(buf, planH, 1, S, tw, M4, tid & 63, 64, w);
+            __syncthreads();
+        } else {
+            fft_lds<R, true, EPT>(buf, planH, rows, S, tw, M4, tid, nthr);
+        }
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + i * nthr;
             if (e < nel) {
                 const int row = e / H;
                 const int n = e - row * H;
-                const C2<R> z = buf[row * S + n];
+                const C2<R> z = buf[lds_pad(row * S + n)];
                 if (DST == DST_VOLUME) {
                     *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
                         cmk<R>(z.x * out_scale, z.y * out_scale);
@@ -527,14 +578,19 @@ hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_
                           C2<R>* spec, int M, int nslices, const LaunchGeom& g, const FftPlan& planH,
                           const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + g.row_slices - 1) / g.row_slices;
-    dim3 grid(M / g.rows, groups);
-    const size_t lds = tw_bytes<R>(M) + (size_t)g.rows * (M / 2) * sizeof(C2<R>);
-#define SE2N_ROWFWD(S, E)                                                                               \
-    hipLaunchKernelGGL((k_row_fwd<R, S, E>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol, spec, \
-                       M, nslices, g.row_slices, g.rows, planH, tw)
-#define SE2N_ROWFWD_E(S)               \
-    if (g.row_ept == 8) SE2N_ROWFWD(S, 8); \
-    else SE2N_ROWFWD(S, 16);
+    dim3 grid((M / g.rows) * groups);
+    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(g.rows * (M / 2)) * sizeof(C2<R>);
+#define SE2N_ROWFWD(S, E, W)                                                                             \
+    hipLaunchKernelGGL((k_row_fwd<R, S, E, W>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol, spec, \
+                       M, nslices, g.row_slices, g.rows, g.xcd_pair, planH, tw)
+#define SE2N_ROWFWD_E(S)                               \
+    if (g.row_wave) {                                  \
+        if (g.row_ept == 8) SE2N_ROWFWD(S, 8, true);   \
+        else SE2N_ROWFWD(S, 16, true);                 \
+    } else {                                           \
+        if (g.row_ept == 8) SE2N_ROWFWD(S, 8, false);  \
+        else SE2N_ROWFWD(S, 16, false);                \
+    }
     if (src == SRC_LIFT) { SE2N_ROWFWD_E(SRC_LIFT) }
     else if (src == SRC_VOLUME) { SE2N_ROWFWD_E(SRC_VOLUME) }
     else { SE2N_ROWFWD_E(SRC_IMAGE) }
@@ -547,7 +603,7 @@ template <class R>
 hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
                           const FftPlan& planM, const C2<R>* tw, hipStream_t st) {
     dim3 grid((unsigned)((ncols + g.cols - 1) / g.cols));
-    const size_t lds = tw_bytes<R>(M) + (size_t)g.cols * M * sizeof(C2<R>);
+    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(g.cols * M) * sizeof(C2<R>);
 #define SE2N_COL(I, E) \
     hipLaunchKernelGGL((k_col_fft<R, I, E>), grid, dim3(g.col_threads), lds, st, spec, ncols, M, g.cols, planM, tw)
     if (inverse) {
@@ -566,7 +622,7 @@ hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftP
                              const C2<R>* tw, double sigma, hipStream_t st) {
     const int K = M / 2 + 1;
     dim3 grid((K + g.ocols - 1) / g.ocols);
-    const size_t lds = tw_bytes<R>(M) + 2 * (size_t)g.ocols * M * sizeof(C2<R>);
+    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(2 * g.ocols * M) * sizeof(C2<R>);
     const double c = -2.0 * 9.869604401089358619 * sigma * sigma / ((double)M * M);
     const double scale = sqrt((double)M) / ((double)M * M);
     if (g.ocol_ept == 8)
@@ -583,14 +639,19 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                           int M, int nslices, int N, R out_scale, const LaunchGeom& g,
                           int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
-    dim3 grid(M / g.rows, groups);
-    const size_t lds = tw_bytes<R>(M) + (size_t)g.rows * (M / 2 + 1) * sizeof(C2<R>);
-#define SE2N_ROWINV(D, E)                                                                                    \
-    hipLaunchKernelGGL((k_row_inv<R, D, E>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap, M,      \
-                       nslices, slices_per_group, g.rows, N, out_scale, planH, tw)
-#define SE2N_ROWINV_E(D)               \
-    if (g.row_ept == 8) SE2N_ROWINV(D, 8); \
-    else SE2N_ROWINV(D, 16);
+    dim3 grid((M / g.rows) * groups);
+    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(g.rows * (M / 2 + 1)) * sizeof(C2<R>);
+#define SE2N_ROWINV(D, E, W)                                                                                  \
+    hipLaunchKernelGGL((k_row_inv<R, D, E, W>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap, M,      \
+                       nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH, tw)
+#define SE2N_ROWINV_E(D)                               \
+    if (g.row_wave) {                                  \
+        if (g.row_ept == 8) SE2N_ROWINV(D, 8, true);   \
+        else SE2N_ROWINV(D, 16, true);                 \
+    } else {                                           \
+        if (g.row_ept == 8) SE2N_ROWINV(D, 8, false);  \
+        else SE2N_ROWINV(D, 16, false);                \
+    }
     if (dst == DST_MAX) { SE2N_ROWINV_E(DST_MAX) }
     else if (dst == DST_SUM) { SE2N_ROWINV_E(DST_SUM) }
     else if (dst == DST_VOLUME) { SE2N_ROWINV_E(DST_VOLUME) }

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <list>
 #include <map>
@@ -202,6 +203,17 @@ LaunchGeom make_geom(int M, int N) {
     while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
     g.rows = rows;
     fft_threads(rows * H, &g.row_threads, &g.row_ept);
+    // the row passes walk (kx, row) pairs with thread t on row t mod rows
+    g.row_threads = (g.row_threads + rows - 1) / rows * rows;
+    // optionally one wavefront per row (8 or 16 elements per lane); measured
+    // slower than the workgroup-wide transform at 2048^2, so off by default
+    g.row_wave = 0;
+    const char* wv = std::getenv("SE2N_ROW_WAVE");
+    if (wv && std::atoi(wv) != 0 && H % 64 == 0 && (H / 64 == 8 || H / 64 == 16) && rows * 64 <= 512) {
+        g.row_wave = 1;
+        g.row_threads = rows * 64;
+        g.row_ept = H / 64;
+    }
     const int row_blocks = M / rows;
     int groups = (1024 + row_blocks - 1) / row_blocks;
     if (groups > N) groups = N;
@@ -212,6 +224,8 @@ LaunchGeom make_geom(int M, int N) {
     fft_threads(g.cols * M, &g.col_threads, &g.col_ept);
     g.ocols = target / (2 * M) > 1 ? target / (2 * M) : 1;
     fft_threads(2 * g.ocols * M, &g.ocol_threads, &g.ocol_ept);
+    g.xcd_pair = 1;
+    if (const char* v = std::getenv("SE2N_XCD_PAIR")) g.xcd_pair = std::atoi(v);
     return g;
 }
 

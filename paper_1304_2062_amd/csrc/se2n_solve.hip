@@ -28,11 +28,26 @@ namespace se2n {
 //
 // A workgroup takes one lx and CLS consecutive ly, stages their propagators
 // in LDS once (a contiguous row of CLS values per element), and applies them
-// to all 8 members of each class.  A wavefront handles one member for 64
-// consecutive classes, i.e. 64 consecutive (or reversed) ky of one column, so
-// every orientation plane is read and written in whole 512-byte runs.
-template <class R, int N, int CLS>
-__global__ __launch_bounds__(256) void k_solve(C2<R>* __restrict__ spec, const R* __restrict__ P, int M,
+// to all 8 members of each class.  Each mode is handled by a pair of adjacent
+// lanes: the even lane loads x_j and the odd lane x_{j+N/2} (j < N/2); one
+// DPP swap gives the even lane p = x_j + x_{j+N/2} and the odd lane
+// q = x_j - x_{j+N/2}; each applies its block (periodic / antiperiodic) and a
+// second swap forms x'_j = y_p + y_q (even) and x'_{j+N/2} = y_p - y_q (odd).
+// A wavefront covers one member for 32 consecutive classes, i.e. 32
+// consecutive (or reversed) ky of one column per orientation plane.
+__device__ __forceinline__ float swap_pair(float v) {
+    // lanes (0,1)(2,3)...: quad_perm [1,0,3,2]
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffff), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <class R, int N, int CLS, int WAVES>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_solve(C2<R>* __restrict__ spec, const R* __restrict__ P, int M,
                                                int Q) {
     constexpr int h = N / 2;
     constexpr int Eh = h * (h + 1) / 2;
@@ -53,39 +68,56 @@ __global__ __launch_bounds__(256) void k_solve(C2<R>* __restrict__ spec, const R
     }
     __syncthreads();
     const size_t plane = (size_t)(H + 1) * M;
-    for (int item = tid; item < 8 * CLS; item += nthr) {
-        const int m = item / CLS;
-        const int c = item - m * CLS;
-        if (c >= ncls) continue;
+    const int odd = tid & 1;
+    // A wavefront holds 32 pairs; with CLS >= 32 they all belong to one member,
+    // so the member, its column kx and its orientation mirroring are uniform
+    // across the wavefront and the plane addresses live in scalar registers.
+    constexpr bool UNIFORM = CLS >= 32;
+    // every lane of a pair runs the same iterations, so the swaps always meet
+#pragma unroll 1
+    for (int pair = tid >> 1; pair < 8 * CLS; pair += nthr >> 1) {
+        int m = pair / CLS;
+        if (UNIFORM) m = __builtin_amdgcn_readfirstlane(m);
+        const int c = pair - m * CLS;
         const int ly = ly0 + c;
         const int a = m >> 2;
         const int b = m & 3;
-        if (a == 1 && 2 * lx == H) continue;              // kx = M/4 is its own mirror
-        if (ly == 0 && b >= 2) continue;                  // ky in {0, M/2} only
-        if (2 * ly == H && (b & 1)) continue;             // ky in {M/4, 3M/4} only
+        bool live = c < ncls;
+        live = live && !(a == 1 && 2 * lx == H);           // kx = M/4 is its own mirror
+        live = live && !(ly == 0 && b >= 2);               // ky in {0, M/2} only
+        live = live && !(2 * ly == H && (b & 1));          // ky in {M/4, 3M/4} only
         const int kx = a ? H - lx : lx;
         int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
-        if (ky == M) ky = 0;
-        const bool perm = ky > H;
-        C2<R>* base = spec + (size_t)kx * M + ky;
-        const R* Pc = Ps + c;
+        if (!live) ky = 0;  // harmless in-range address; nothing is stored
+        // s_ky < 0 exactly for the live members b = 2, 3 (ky in (M/2, M))
+        const bool perm = b >= 2;
+        C2<R>* colbase = spec + (size_t)kx * M;
+        const R* Pc = Ps + (size_t)odd * Eh * CLS + c;
 
-        C2<R> p[h], q[h];
+        // this lane's half of the orientation vector (every address is valid;
+        // dead lanes read row 0 and discard it)
+        C2<R> x[h];
 #pragma unroll
         for (int j = 0; j < h; ++j) {
-            const int a0 = perm ? (j == 0 ? 0 : N - j) : j;
-            const int a1 = perm ? (N - j - h) % N : j + h;
-            const C2<R> x0 = base[a0 * plane];
-            const C2<R> x1 = base[a1 * plane];
-            p[j] = cadd<R>(x0, x1);
-            q[j] = csub<R>(x0, x1);
+            const int r0 = j, r1 = j + h;
+            const int a0 = perm ? (r0 == 0 ? 0 : N - r0) : r0;
+            const int a1 = perm ? N - r1 : r1;
+            const C2<R>* pl0 = colbase + (size_t)a0 * plane;  // wave-uniform
+            const C2<R>* pl1 = colbase + (size_t)a1 * plane;
+            const C2<R> v = odd ? pl1[ky] : pl0[ky];
+            x[j].x = live ? v.x : R(0);
+            x[j].y = live ? v.y : R(0);
         }
-        C2<R> yp[h], yq[h];
+        // even lane: p = x_j + x_{j+h};  odd lane: q = x_j - x_{j+h}
 #pragma unroll
         for (int j = 0; j < h; ++j) {
-            yp[j] = cmk<R>(R(0), R(0));
-            yq[j] = cmk<R>(R(0), R(0));
+            const R ox = swap_pair(x[j].x);
+            const R oy = swap_pair(x[j].y);
+            x[j] = odd ? cmk<R>(ox - x[j].x, oy - x[j].y) : cmk<R>(x[j].x + ox, x[j].y + oy);
         }
+        C2<R> y[h];
+#pragma unroll
+        for (int j = 0; j < h; ++j) y[j] = cmk<R>(R(0), R(0));
         {
             int e = 0;
 #pragma unroll
@@ -93,36 +125,34 @@ __global__ __launch_bounds__(256) void k_solve(C2<R>* __restrict__ spec, const R
 #pragma unroll
                 for (int j = i; j < h; ++j) {
                     const R w = Pc[e * CLS];
-                    yp[i].x += w * p[j].x;
-                    yp[i].y += w * p[j].y;
+                    y[i].x += w * x[j].x;
+                    y[i].y += w * x[j].y;
                     if (j != i) {
-                        yp[j].x += w * p[i].x;
-                        yp[j].y += w * p[i].y;
+                        y[j].x += w * x[i].x;
+                        y[j].y += w * x[i].y;
                     }
                     ++e;
                 }
-            }
-#pragma unroll
-            for (int i = 0; i < h; ++i) {
-#pragma unroll
-                for (int j = i; j < h; ++j) {
-                    const R w = Pc[e * CLS];
-                    yq[i].x += w * q[j].x;
-                    yq[i].y += w * q[j].y;
-                    if (j != i) {
-                        yq[j].x += w * q[i].x;
-                        yq[j].y += w * q[i].y;
-                    }
-                    ++e;
-                }
+                // keep each row's LDS reads next to their use (bounded registers)
+                __builtin_amdgcn_sched_barrier(0);
             }
         }
+        // even lane: y_p + y_q -> x'_j;  odd lane: y_p - y_q -> x'_{j+h}
 #pragma unroll
         for (int j = 0; j < h; ++j) {
-            const int a0 = perm ? (j == 0 ? 0 : N - j) : j;
-            const int a1 = perm ? (N - j - h) % N : j + h;
-            base[a0 * plane] = cadd<R>(yp[j], yq[j]);
-            base[a1 * plane] = csub<R>(yp[j], yq[j]);
+            const R ox = swap_pair(y[j].x);
+            const R oy = swap_pair(y[j].y);
+            y[j] = odd ? cmk<R>(ox - y[j].x, oy - y[j].y) : cmk<R>(y[j].x + ox, y[j].y + oy);
+        }
+        if (live) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const int r0 = j, r1 = j + h;
+                const int a0 = perm ? (r0 == 0 ? 0 : N - r0) : r0;
+                const int a1 = perm ? N - r1 : r1;
+                C2<R>* pl = colbase + (size_t)(odd ? a1 : a0) * plane;
+                pl[ky] = y[j];
+            }
         }
     }
 }
@@ -141,13 +171,16 @@ constexpr int solve_cls() {
 template <class R, int N>
 static hipError_t launch_solve_n(C2<R>* spec, const R* P, int M, hipStream_t st) {
     constexpr int CLS = solve_cls<R, N>();
+    // occupancy target: 4 waves/SIMD (<= 128 VGPRs) while a lane's half
+    // vector and accumulator fit, else 2 (<= 256 VGPRs) rather than spill
+    constexpr int WAVES = (N * (int)sizeof(R)) <= 160 ? 4 : 2;
     constexpr int h = N / 2;
     constexpr int E = h * (h + 1);
     const int Q = M / 4 + 1;
     dim3 grid((Q + CLS - 1) / CLS, Q);
-    const int threads = 8 * CLS < 256 ? 8 * CLS : 256;
+    const int threads = 16 * CLS < 512 ? 16 * CLS : 512;  // two lanes per mode
     const size_t lds = (size_t)E * CLS * sizeof(R);
-    hipLaunchKernelGGL((k_solve<R, N, CLS>), grid, dim3(threads), lds, st, spec, P, M, Q);
+    hipLaunchKernelGGL((k_solve<R, N, CLS, WAVES>), grid, dim3(threads), lds, st, spec, P, M, Q);
     return hipGetLastError();
 }
 
