@@ -4,9 +4,9 @@
 //
 // Each stage reads every butterfly's inputs into registers, synchronises,
 // and writes the outputs back to the same LDS buffer, so a transform needs
-// no second buffer.  Twiddles come from an LDS copy of the quarter table
-// w_M^r, r <= M/4, of the plan's side M; a transform of length L | M reads it
-// with stride M/L.
+// no second buffer.  Twiddles come from a full-period LDS table w_M^m of the
+// plan's side M (expanded from a quarter-wave table in global memory); a
+// transform of length L | M reads it with stride M/L.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -129,6 +129,7 @@ struct FftStage {
     int twstep;     // M / (Ns * radix): twiddle w_{Ns radix}^e = w_M^{e twstep}
     float inv_nb;   // 1/nb
     float inv_Ns;   // 1/Ns
+    int lg_Ns;      // log2(Ns) when Ns is a power of two, else -1
 };
 
 // Radix sequence of one transform length.
@@ -138,50 +139,59 @@ struct FftPlan {
     FftStage st[12];
 };
 
-// w_M^m = exp(-2 pi i m / M) for m in [0, M) from the quarter table
-// q[r] = w_M^r, r in [0, M/4]: w_M^{a M/4 + r} = (-i)^a w_M^r.
-template <class R>
-__device__ __forceinline__ C2<R> tw_get(const C2<R>* q, int M4, int m) {
+// Twiddle w_M^m = exp(-2 pi i m / M), m in [0, M), from the LDS table: the
+// full period (FULL) or the quarter r in [0, M/4] with
+// w_M^{a M/4 + r} = (-i)^a w_M^r.
+template <class R, bool FULL>
+__device__ __forceinline__ C2<R> tw_get(const C2<R>* tw, int m, int M4) {
+    if (FULL) return tw[m];
     const int a = (m >= M4) + (m >= 2 * M4) + (m >= 3 * M4);
-    const C2<R> w = q[m - a * M4];
+    const C2<R> w = tw[m - __mul24(a, M4)];
     if (a == 0) return w;
     if (a == 1) return cmk<R>(w.y, -w.x);
     if (a == 2) return cmk<R>(-w.x, -w.y);
     return cmk<R>(-w.y, w.x);
 }
 
-// Copy the quarter twiddle table into LDS (callers synchronise afterwards).
+// Copy the twiddles into LDS from the quarter table q[r] = w_M^r,
+// r in [0, M/4], in global memory: the full period if `full`, else the
+// quarter table itself (callers synchronise afterwards).
 template <class R>
-__device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restrict__ src, int M4, int tid,
-                                              int nthr) {
-    for (int i = tid; i <= M4; i += nthr) dst[i] = src[i];
-}
-
-// Synchronisation of a stage: the whole workgroup, or one wavefront that owns
-// its transforms alone (a wavefront issues its LDS operations in order, so a
-// compiler-level barrier with wavefront-scope fences suffices).
-template <bool WAVE>
-__device__ __forceinline__ void fft_sync() {
-    if (WAVE) {
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    } else {
-        __syncthreads();
+__device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restrict__ q, int M4, bool full,
+                                              int tid, int nthr) {
+    if (!full) {
+        for (int i = tid; i <= M4; i += nthr) dst[i] = q[i];
+        return;
+    }
+    for (int m = tid; m < 4 * M4; m += nthr) {
+        const int a = (m >= M4) + (m >= 2 * M4) + (m >= 3 * M4);
+        const C2<R> w = q[m - a * M4];
+        C2<R> v;
+        if (a == 0) v = w;
+        else if (a == 1) v = cmk<R>(w.y, -w.x);
+        else if (a == 2) v = cmk<R>(-w.x, -w.y);
+        else v = cmk<R>(-w.y, w.x);
+        dst[m] = v;
     }
 }
 
+// Elements the LDS twiddle table occupies.
+__host__ __device__ constexpr int tw_elems(int M, bool full) { return full ? M : ((M / 4 + 1 + 7) & ~7); }
+
 // One Stockham stage, in place.  `nbatch` transforms of length L start at
-// buf + (tbase + t)*bstride.  Butterfly j of a transform reads x[j + r L/RADIX],
+// buf + t*bstride.  Butterfly j of a transform reads x[j + r L/RADIX],
 // multiplies input r by w_{Ns RADIX}^{r (j mod Ns)}, and writes output r to
 // (j / Ns) Ns RADIX + (j mod Ns) + r Ns.  Every thread first reads all its
 // butterflies, the block synchronises, then every thread writes.
-// The caller guarantees nbatch*L <= EPT*nthr.
-template <class R, int RADIX, bool INV, int EPT, bool WAVE>
-__device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nbatch, int bstride, int tbase,
+// Thread tid owns butterflies b = tid + i*nthr, i.e. transform t = b / nb and
+// butterfly j = b mod nb.  The caller guarantees nbatch*L <= EPT*nthr.
+template <class R, int RADIX, bool INV, int EPT, bool TWFULL>
+__device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nbatch, int bstride,
                                           const C2<R>* twq, int M4, int tid, int nthr) {
     constexpr int MAXB = (EPT + RADIX - 1) / RADIX;
-    const int total = s.nb * nbatch;
+    const int nb = s.nb;
+    const int Ns = s.Ns;
+    const int total = nb * nbatch;
     C2<R> v[MAXB][RADIX];
     int obase[MAXB], kk[MAXB];
 #pragma unroll
@@ -189,54 +199,136 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
         const int b = tid + i * nthr;
         if (b < total) {
             const int t = fdiv(b, s.inv_nb);
-            const int j = b - t * s.nb;
+            const int j = b - __mul24(t, nb);
             const int q = fdiv(j, s.inv_Ns);
-            const int k = j - q * s.Ns;
-            const int ib = (tbase + t) * bstride + j;
+            const int k = j - __mul24(q, Ns);
+            const int ib = __mul24(t, bstride) + j;
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * s.nb)];
-            obase[i] = (tbase + t) * bstride + q * s.Ns * RADIX + k;
+            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * nb)];
+            obase[i] = __mul24(t, bstride) + __mul24(q, Ns * RADIX) + k;
             kk[i] = k;
         }
     }
-    fft_sync<WAVE>();
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthr;
         if (b < total) {
-            if (s.Ns > 1) {
-                const int e = kk[i] * s.twstep;
+            if (Ns > 1) {
+                const int e = __mul24(kk[i], s.twstep);
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) {
-                    C2<R> w = tw_get<R>(twq, M4, r * e);
+                    C2<R> w = tw_get<R, TWFULL>(twq, r * e, M4);
                     if (INV) w.y = -w.y;
                     v[i][r] = cmul<R>(v[i][r], w);
                 }
             }
             dft<R, RADIX, INV>(v[i]);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * s.Ns)] = v[i][r];
+            for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * Ns)] = v[i][r];
         }
     }
-    fft_sync<WAVE>();
+    __syncthreads();
 }
 
 // Unnormalised transforms of `nbatch` sequences of length plan.L held in LDS
 // (logical element i of the buffer at buf[lds_pad(i)]).
 // Forward: X_k = sum_n x_n w_L^{nk}; inverse: the same with w_L^{-nk}.
-// twq is the LDS quarter twiddle table of the plan's side M (M4 = M/4).
-// Block mode (WAVE = false): all nthr threads of the workgroup call it and it
-// synchronises the workgroup.  Wave mode: one wavefront (tid = lane,
-// nthr = 64) transforms sequences tbase .. tbase+nbatch-1 on its own.
-template <class R, bool INV, int EPT, bool WAVE = false>
+// twq is the LDS twiddle table of the plan's side M (full period or quarter).
+// All nthr threads of the workgroup call it; it synchronises the workgroup.
+template <class R, bool INV, int EPT, bool TWFULL>
 __device__ void fft_lds(C2<R>* buf, const FftPlan& plan, int nbatch, int bstride, const C2<R>* twq, int M4,
-                        int tid, int nthr, int tbase = 0) {
+                        int tid, int nthr) {
     for (int s = 0; s < plan.nstages; ++s) {
         const FftStage& st = plan.st[s];
-        if (st.radix == 8) fft_stage<R, 8, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
-        else if (st.radix == 4) fft_stage<R, 4, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
-        else if (st.radix == 3) fft_stage<R, 3, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
-        else fft_stage<R, 2, INV, EPT, WAVE>(buf, st, nbatch, bstride, tbase, twq, M4, tid, nthr);
+        if (st.radix == 8) fft_stage<R, 8, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else if (st.radix == 4) fft_stage<R, 4, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else if (st.radix == 3) fft_stage<R, 3, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else fft_stage<R, 2, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Compile-time specialisation for the hot sizes: the same Stockham stages
+// with the length, batch, stride, thread count and radix sequence known to
+// the compiler, so every index is a shift or a constant multiply.
+// ---------------------------------------------------------------------------
+
+// Radix of stage s of a length-L transform (0 past the last stage); the same
+// sequence the host builds: radix 8 where possible, then 4 (or 4,4 in place
+// of 8,2), then radix 3.
+__host__ __device__ constexpr int static_radix(int L, int s) {
+    int a = 0, b = 0, m = L;
+    while (m % 2 == 0) { m /= 2; ++a; }
+    while (m % 3 == 0) { m /= 3; ++b; }
+    int rad[16] = {};
+    int n = 0;
+    const int q = a / 3, r = a % 3;
+    if (r == 1 && q >= 1) {
+        for (int i = 0; i < q - 1; ++i) rad[n++] = 8;
+        rad[n++] = 4;
+        rad[n++] = 4;
+    } else {
+        for (int i = 0; i < q; ++i) rad[n++] = 8;
+        if (r == 1) rad[n++] = 2;
+        if (r == 2) rad[n++] = 4;
+    }
+    for (int i = 0; i < b; ++i) rad[n++] = 3;
+    return s < n ? rad[s] : 0;
+}
+
+template <class R, int RADIX, bool INV, bool TWFULL, int L, int NS, int NBATCH, int BSTRIDE, int NTHR, int M>
+__device__ __forceinline__ void fft_stage_static(C2<R>* buf, const C2<R>* twq, int tid) {
+    constexpr int NB = L / RADIX;
+    constexpr int TOTAL = NB * NBATCH;
+    constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+    constexpr int TWSTEP = M / (NS * RADIX);
+    constexpr int M4 = M / 4;
+    C2<R> v[MAXB][RADIX];
+    int obase[MAXB], kk[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * NTHR;
+        if (TOTAL % NTHR == 0 || b < TOTAL) {
+            const int t = b / NB;
+            const int j = b - t * NB;
+            const int q = j / NS;
+            const int k = j - q * NS;
+            const int ib = t * BSTRIDE + j;
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * NB)];
+            obase[i] = t * BSTRIDE + q * NS * RADIX + k;
+            kk[i] = k;
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * NTHR;
+        if (TOTAL % NTHR == 0 || b < TOTAL) {
+            if (NS > 1) {
+                const int e = kk[i] * TWSTEP;
+#pragma unroll
+                for (int r = 1; r < RADIX; ++r) {
+                    C2<R> w = tw_get<R, TWFULL>(twq, r * e, M4);
+                    if (INV) w.y = -w.y;
+                    v[i][r] = cmul<R>(v[i][r], w);
+                }
+            }
+            dft<R, RADIX, INV>(v[i]);
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * NS)] = v[i][r];
+        }
+    }
+    __syncthreads();
+}
+
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S = 0, int NS = 1>
+__device__ __forceinline__ void fft_static(C2<R>* buf, const C2<R>* twq, int tid) {
+    constexpr int RADIX = static_radix(L, S);
+    if constexpr (RADIX != 0) {
+        fft_stage_static<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(buf, twq, tid);
+        fft_static<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(buf, twq, tid);
     }
 }
 

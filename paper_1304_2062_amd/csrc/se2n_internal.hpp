@@ -56,8 +56,52 @@ struct LaunchGeom {
     int ocol_threads;
     int ocol_ept;
     int xcd_pair;     // pair adjacent row blocks on one XCD (row passes)
-    int row_wave;     // row transforms run one per wavefront (rows*64 threads)
+    int tw_full;      // row passes: full-period twiddle table in LDS (else the quarter table)
+    int tw_full_col;  // column passes: the same choice
+    int static_ok;    // use the kernels compiled for a fixed M when M has one
 };
+
+// The size-dependent part of the launch geometry, shared by the host (plan
+// creation) and by the kernels compiled for a fixed M.
+struct GeomCore {
+    int rows, row_threads, row_ept;
+    int cols, col_threads, col_ept;
+    int ocols, ocol_threads, ocol_ept;
+    int tw_full, tw_full_col;
+};
+
+__host__ __device__ constexpr void fft_threads_of(int elems, int& threads, int& ept) {
+    ept = 8;
+    threads = (elems + 7) / 8;
+    if (threads > 1024) {
+        ept = 16;
+        threads = (elems + 15) / 16;
+    }
+}
+
+template <class R>
+__host__ __device__ constexpr GeomCore geom_core(int M) {
+    GeomCore g{};
+    const int cs = (int)sizeof(R) * 2;
+    const int target = sizeof(R) == 4 ? 4096 : 2048;  // complex elements per FFT workgroup
+    const int H = M / 2;
+    int rows = 64 / cs;                                // 64-byte segments per (slice, kx)
+    while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
+    g.rows = rows;
+    fft_threads_of(rows * H, g.row_threads, g.row_ept);
+    // the row passes walk (kx, row) pairs with thread t on row t mod rows
+    g.row_threads = (g.row_threads + rows - 1) / rows * rows;
+    g.cols = target / M > 1 ? target / M : 1;
+    fft_threads_of(g.cols * M, g.col_threads, g.col_ept);
+    g.ocols = target / (2 * M) > 1 ? target / (2 * M) : 1;
+    fft_threads_of(2 * g.ocols * M, g.ocol_threads, g.ocol_ept);
+    // full-period twiddle table for the row passes when it fits beside the row
+    // buffer; a column workgroup transforms only a few columns, for which
+    // expanding the full table would cost as much as the transform
+    g.tw_full = (long)M * cs + (long)lds_padded_size(rows * (H + 1)) * cs <= 150 * 1024 ? 1 : 0;
+    g.tw_full_col = 0;
+    return g;
+}
 
 template <class R>
 hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_t* rmap, const R* vol,

@@ -44,6 +44,24 @@ __device__ __forceinline__ void row_block_of(int nrb, int ngroups, bool pair, in
     }
 }
 
+// (q, r) = divmod(tid + i*nthr, d) without a per-element division when nthr
+// is a multiple of d or d of nthr (uniform branches); inv_d = 1/d in float.
+__device__ __forceinline__ void split_index(int tid, int i, int nthr, int d, float inv_d, int& q, int& r) {
+    if (nthr % d == 0) {
+        const int qt = tid / d;
+        q = qt + i * (nthr / d);
+        r = tid - qt * d;
+    } else if (d % nthr == 0) {
+        const int c = d / nthr;
+        q = i / c;
+        r = tid + (i - q * c) * nthr;
+    } else {
+        const int b = tid + i * nthr;
+        q = fdiv(b, inv_d);
+        r = b - q * d;
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Row pass, forward: lift + R2C along x, written transposed.
 // ---------------------------------------------------------------------------
@@ -51,27 +69,33 @@ __device__ __forceinline__ void row_block_of(int nrb, int ngroups, bool pair, in
 // z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
 //   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
 // grid: (M/ROWS row blocks, slice groups); block: nthr threads; LDS ROWS*H.
-template <class R, int SRC, int EPT, bool WAVE>
-__global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
+template <class R, int SRC, int EPT, bool TWF, int MS>
+__global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
                           const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
-                          C2<R>* __restrict__ spec, int M, int nslices, int slices_per_group,
-                          int rows, int xcd_pair, FftPlan planH, const C2<R>* __restrict__ twg) {
+                          C2<R>* __restrict__ spec, int M_, int nslices, int slices_per_group,
+                          int rows_, int xcd_pair, FftPlan planH, const C2<R>* __restrict__ twg) {
+    constexpr bool twfull = TWF;
+    // MS != 0: compiled for M = MS with the geometry geom_core<R>(MS)
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int rows = MS ? GC.rows : rows_;
     extern __shared__ unsigned char smem_raw[];
     const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
+    C2<R>* buf = tw + tw_elems(M, twfull);
     const int H = M >> 1;
     const int K = H + 1;
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+    const int nthr = MS ? GC.row_threads : (int)blockDim.x;
     int rb, grp;
     row_block_of(M / rows, (nslices + slices_per_group - 1) / slices_per_group, xcd_pair != 0, rb, grp);
     const int y0 = rb * rows;
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     const int nel = rows * H;
+    const float inv_H = 1.0f / (float)H;
 
-    load_twiddles<R>(tw, twg, M4, tid, nthr);
+    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
     // Lift sources are read once per block and kept in registers.
     R fc0[EPT], fc1[EPT];
     uint8_t rm0[EPT], rm1[EPT];
@@ -84,8 +108,8 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_fwd(const R* __restri
             rm0[i] = 0xff;
             rm1[i] = 0xff;
             if (e < nel) {
-                const int row = e / H;
-                const int n = e - row * H;
+                int row, n;
+                split_index(tid, i, nthr, H, inv_H, row, n);
                 const size_t p = (size_t)(y0 + row) * M + 2 * n;
                 const C2<R> fv = *reinterpret_cast<const C2<R>*>(f + p);
                 const uint16_t mv = *reinterpret_cast<const uint16_t*>(mask + p);
@@ -107,8 +131,8 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_fwd(const R* __restri
             if (e < nel) {
                 C2<R> z;
                 if (SRC == SRC_VOLUME) {
-                    const int row = e / H;
-                    const int n = e - row * H;
+                    int row, n;
+                    split_index(tid, i, nthr, H, inv_H, row, n);
                     z = *reinterpret_cast<const C2<R>*>(vol + ((size_t)s * M + y0 + row) * M + 2 * n);
                 } else if (SRC == SRC_LIFT) {
                     z.x = (rm0[i] == s) ? fc0[i] : R(0);
@@ -121,27 +145,24 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_fwd(const R* __restri
             }
         }
         __syncthreads();
-        if (WAVE) {
-            // one wavefront per row, no workgroup barrier inside the transform
-            const int w = tid >> 6;
-            if (w < rows) fft_lds<R, false, EPT, true>(buf, planH, 1, H, tw, M4, tid & 63, 64, w);
-            __syncthreads();
-        } else {
-            fft_lds<R, false, EPT>(buf, planH, rows, H, tw, M4, tid, nthr);
-        }
+        if constexpr (MS != 0)
+            fft_static<R, false, TWF, MS / 2, GC.rows, MS / 2, GC.row_threads, MS>(buf, tw, tid);
+        else
+            fft_lds<R, false, EPT, TWF>(buf, planH, rows, H, tw, M4, tid, nthr);
         // unpack the real transform and write (r, kx, y0..y0+rows) segments
         const int nout = rows * K;
         C2<R>* out = spec + (size_t)s * K * M + y0;
+        const int rshift = __ffs(rows) - 1;  // rows is a power of two
         for (int e = tid; e < nout; e += nthr) {
-            const int kx = e / rows;
-            const int row = e - kx * rows;
+            const int kx = e >> rshift;
+            const int row = e & (rows - 1);
             const C2<R> z1 = buf[lds_pad(row * H + (kx == H ? 0 : kx))];
             const C2<R> z2 = buf[lds_pad(row * H + (kx == 0 ? 0 : H - kx))];
             const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
             // (z1 - conj z2)/(2i)
             const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
             const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
-            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R>(tw, M4, kx), od));
+            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R, TWF>(tw, kx, M4), od));
         }
         __syncthreads();
     }
@@ -150,23 +171,32 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_fwd(const R* __restri
 // ---------------------------------------------------------------------------
 // Column pass: FFT along y of `cols_per_block` contiguous columns of length M.
 // ---------------------------------------------------------------------------
-template <class R, bool INV, int EPT>
-__global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M, int cols_per_block,
+template <class R, bool INV, int EPT, bool TWF, int MS>
+__global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M_, int cols_per_block_,
                           FftPlan planM, const C2<R>* __restrict__ twg) {
+    constexpr bool twfull = TWF;
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int cols_per_block = MS ? GC.cols : cols_per_block_;
     extern __shared__ unsigned char smem_raw[];
     const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
+    C2<R>* buf = tw + tw_elems(M, twfull);
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    load_twiddles<R>(tw, twg, M4, tid, nthr);
+    const int nthr = MS ? GC.col_threads : (int)blockDim.x;
+    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
     const long c0 = (long)blockIdx.x * cols_per_block;
     const int ncb = (int)min((long)cols_per_block, ncols - c0);
     const int nel = ncb * M;
     C2<R>* base = spec + c0 * M;
     for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
     __syncthreads();
-    fft_lds<R, INV, EPT>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    if constexpr (MS != 0) {
+        if (ncb == GC.cols) fft_static<R, INV, TWF, MS, GC.cols, MS, GC.col_threads, MS>(buf, tw, tid);
+        else fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    } else {
+        fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    }
     for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
 }
 
@@ -178,18 +208,19 @@ __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M, int cols_
 //   s_k = sin(2 pi k/M), g(k) = exp(-2 pi^2 sigma^2 kbar^2 / M^2).
 // (The 1/M^2 only keeps magnitudes moderate; the angle ignores it.)
 // ---------------------------------------------------------------------------
-template <class R, int EPT>
+template <class R, int EPT, bool TWF>
 __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block, FftPlan planM,
                              const C2<R>* __restrict__ twg, R neg_two_pi2_sigma2_over_M2, R scale) {
+    constexpr bool twfull = TWF;
     extern __shared__ unsigned char smem_raw[];
     const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
+    C2<R>* buf = tw + tw_elems(M, twfull);
     const int H = M >> 1;
     const int K = H + 1;
     const int tid = threadIdx.x;
     const int nthr = blockDim.x;
-    load_twiddles<R>(tw, twg, M4, tid, nthr);
+    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
     const int c0 = blockIdx.x * cols_per_block;
     const int ncb = min(cols_per_block, K - c0);
     const int nel = ncb * M;
@@ -197,13 +228,14 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
     C2<R>* gy = spec + ((size_t)K + c0) * M;
     for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = gx[e];
     __syncthreads();
-    fft_lds<R, false, EPT>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    fft_lds<R, false, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    const float inv_M = 1.0f / (float)M;
     for (int e = tid; e < nel; e += nthr) {
-        const int col = e / M;
+        const int col = fdiv(e, inv_M);
         const int ky = e - col * M;
         const int kx = c0 + col;
-        const R skx = -tw_get<R>(tw, M4, kx).y;
-        const R sky = -tw_get<R>(tw, M4, ky).y;
+        const R skx = -tw_get<R, TWF>(tw, kx, M4).y;
+        const R sky = -tw_get<R, TWF>(tw, ky, M4).y;
         const R kxb = (R)kx;                            // kx <= M/2; (M/2)^2 = (-M/2)^2
         const R kyb = (R)(ky < H ? ky : ky - M);
         const R g = exp(neg_two_pi2_sigma2_over_M2 * (kxb * kxb + kyb * kyb)) * scale;
@@ -213,7 +245,7 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
         buf[lds_pad(nel + e)] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
     }
     __syncthreads();
-    fft_lds<R, true, EPT>(buf, planM, 2 * ncb, M, tw, M4, tid, nthr);
+    fft_lds<R, true, EPT, TWF>(buf, planM, 2 * ncb, M, tw, M4, tid, nthr);
     for (int e = tid; e < nel; e += nthr) {
         gx[e] = buf[lds_pad(e)];
         gy[e] = buf[lds_pad(nel + e)];
@@ -227,28 +259,33 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int DST, int EPT, bool WAVE>
-__global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
+template <class R, int DST, int EPT, bool TWF, int MS>
+__global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
-                          int M, int nslices, int slices_per_group, int rows, int xcd_pair, int N,
+                          int M_, int nslices, int slices_per_group, int rows_, int xcd_pair, int N,
                           R out_scale, FftPlan planH, const C2<R>* __restrict__ twg) {
+    constexpr bool twfull = TWF;
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int rows = MS ? GC.rows : rows_;
     extern __shared__ unsigned char smem_raw[];
     const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + ((M4 + 1 + 7) & ~7);
+    C2<R>* buf = tw + tw_elems(M, twfull);
     const int H = M >> 1;
     const int K = H + 1;
     const int S = H + 1;  // LDS row stride
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
+    const int nthr = MS ? GC.row_threads : (int)blockDim.x;
     int rb, grp;
     row_block_of(M / rows, (nslices + slices_per_group - 1) / slices_per_group, xcd_pair != 0, rb, grp);
     const int y0 = rb * rows;
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     const int nel = rows * H;
+    const float inv_H = 1.0f / (float)H;
 
-    load_twiddles<R>(tw, twg, M4, tid, nthr);
+    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
     C2<R> acc[EPT], acc2[EPT];
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
@@ -282,8 +319,9 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_inv(const C2<R>* __re
         __syncthreads();
         if (s + 1 < s_end) SE2N_FETCH(s + 1);
         const int npair = H / 2 + 1;
+        const float inv_npair = 1.0f / (float)npair;
         for (int e = tid; e < rows * npair; e += nthr) {
-            const int row = e / npair;
+            const int row = fdiv(e, inv_npair);
             const int k = e - row * npair;
             const int kk = H - k;
             const C2<R> a = buf[lds_pad(row * S + k)];
@@ -291,32 +329,29 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_inv(const C2<R>* __re
             // Z[k]
             const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);      // a + conj b
             const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);      // a - conj b
-            const C2<R> wa = cconj<R>(tw_get<R>(tw, M4, k));
+            const C2<R> wa = cconj<R>(tw_get<R, TWF>(tw, k, M4));
             const C2<R> ta = cmul<R>(wa, da);
             const C2<R> za = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
             // Z[H-k]
             const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
             const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
-            const C2<R> wb = cconj<R>(tw_get<R>(tw, M4, kk));
+            const C2<R> wb = cconj<R>(tw_get<R, TWF>(tw, kk, M4));
             const C2<R> tb = cmul<R>(wb, db);
             const C2<R> zb = cmk<R>(sb.x - tb.y, sb.y + tb.x);
             buf[lds_pad(row * S + k)] = za;
             if (kk != k) buf[lds_pad(row * S + kk)] = zb;
         }
         __syncthreads();
-        if (WAVE) {
-            const int w = tid >> 6;
-            if (w < rows) fft_lds<R, true, EPT, true>(buf, planH, 1, S, tw, M4, tid & 63, 64, w);
-            __syncthreads();
-        } else {
-            fft_lds<R, true, EPT>(buf, planH, rows, S, tw, M4, tid, nthr);
-        }
+        if constexpr (MS != 0)
+            fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 1, GC.row_threads, MS>(buf, tw, tid);
+        else
+            fft_lds<R, true, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
             const int e = tid + i * nthr;
             if (e < nel) {
-                const int row = e / H;
-                const int n = e - row * H;
+                int row, n;
+                split_index(tid, i, nthr, H, inv_H, row, n);
                 const C2<R> z = buf[lds_pad(row * S + n)];
                 if (DST == DST_VOLUME) {
                     *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
@@ -341,8 +376,8 @@ __global__ __launch_bounds__(WAVE ? 512 : 1024) void k_row_inv(const C2<R>* __re
     for (int i = 0; i < EPT; ++i) {
         const int e = tid + i * nthr;
         if (e < nel) {
-            const int row = e / H;
-            const int n = e - row * H;
+            int row, n;
+            split_index(tid, i, nthr, H, inv_H, row, n);
             const size_t p = (size_t)(y0 + row) * M + 2 * n;
             if (DST == DST_MAX) {
                 if (enc) {
@@ -569,8 +604,24 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
 // Launchers (host side, called by the runtime with validated arguments).
 // ---------------------------------------------------------------------------
 template <class R>
-static size_t tw_bytes(int M) {
-    return (size_t)(((M / 4 + 1) + 7) & ~7) * sizeof(C2<R>);
+constexpr bool kStatic = sizeof(R) == 4;  // fixed-size kernels exist for FP32 only
+
+// M of the kernels compiled for a fixed size that this plan can use (0: none):
+// FP32, M in {512, 1024, 2048}, with the default geometry.
+template <class R>
+static int static_size(int M, const LaunchGeom& g) {
+    if (sizeof(R) != 4 || !g.static_ok) return 0;
+    if (M != 512 && M != 1024 && M != 2048) return 0;
+    const GeomCore c = geom_core<R>(M);
+    const bool same = g.rows == c.rows && g.row_threads == c.row_threads && g.row_ept == 8 && c.row_ept == 8 &&
+                      g.cols == c.cols && g.col_threads == c.col_threads && g.col_ept == 8 && c.col_ept == 8 &&
+                      g.tw_full == 1 && c.tw_full == 1 && g.tw_full_col == 0;
+    return same ? M : 0;
+}
+
+template <class R>
+static size_t tw_bytes(int M, bool full) {
+    return (size_t)tw_elems(M, full) * sizeof(C2<R>);
 }
 
 template <class R>
@@ -579,17 +630,20 @@ hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_
                           const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + g.row_slices - 1) / g.row_slices;
     dim3 grid((M / g.rows) * groups);
-    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(g.rows * (M / 2)) * sizeof(C2<R>);
-#define SE2N_ROWFWD(S, E, W)                                                                             \
-    hipLaunchKernelGGL((k_row_fwd<R, S, E, W>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol, spec, \
-                       M, nslices, g.row_slices, g.rows, g.xcd_pair, planH, tw)
-#define SE2N_ROWFWD_E(S)                               \
-    if (g.row_wave) {                                  \
-        if (g.row_ept == 8) SE2N_ROWFWD(S, 8, true);   \
-        else SE2N_ROWFWD(S, 16, true);                 \
-    } else {                                           \
-        if (g.row_ept == 8) SE2N_ROWFWD(S, 8, false);  \
-        else SE2N_ROWFWD(S, 16, false);                \
+    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2)) * sizeof(C2<R>);
+#define SE2N_ROWFWD(S, E, W, MSV)                                                                          \
+    hipLaunchKernelGGL((k_row_fwd<R, S, E, W, MSV>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol,    \
+                       spec, M, nslices, g.row_slices, g.rows, g.xcd_pair, planH, tw)
+#define SE2N_ROWFWD_E(S)                                                    \
+    if (static_size<R>(M, g) == 2048) SE2N_ROWFWD(S, 8, true, kStatic<R> ? 2048 : 0);        \
+    else if (static_size<R>(M, g) == 1024) SE2N_ROWFWD(S, 8, true, kStatic<R> ? 1024 : 0);   \
+    else if (static_size<R>(M, g) == 512) SE2N_ROWFWD(S, 8, true, kStatic<R> ? 512 : 0);     \
+    else if (g.tw_full) {                                                   \
+        if (g.row_ept == 8) SE2N_ROWFWD(S, 8, true, 0);                     \
+        else SE2N_ROWFWD(S, 16, true, 0);                                   \
+    } else {                                                                \
+        if (g.row_ept == 8) SE2N_ROWFWD(S, 8, false, 0);                    \
+        else SE2N_ROWFWD(S, 16, false, 0);                                  \
     }
     if (src == SRC_LIFT) { SE2N_ROWFWD_E(SRC_LIFT) }
     else if (src == SRC_VOLUME) { SE2N_ROWFWD_E(SRC_VOLUME) }
@@ -603,16 +657,24 @@ template <class R>
 hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
                           const FftPlan& planM, const C2<R>* tw, hipStream_t st) {
     dim3 grid((unsigned)((ncols + g.cols - 1) / g.cols));
-    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(g.cols * M) * sizeof(C2<R>);
-#define SE2N_COL(I, E) \
-    hipLaunchKernelGGL((k_col_fft<R, I, E>), grid, dim3(g.col_threads), lds, st, spec, ncols, M, g.cols, planM, tw)
-    if (inverse) {
-        if (g.col_ept == 8) SE2N_COL(true, 8);
-        else SE2N_COL(true, 16);
-    } else {
-        if (g.col_ept == 8) SE2N_COL(false, 8);
-        else SE2N_COL(false, 16);
+    const size_t lds = tw_bytes<R>(M, g.tw_full_col != 0) + (size_t)lds_padded_size(g.cols * M) * sizeof(C2<R>);
+#define SE2N_COL(I, E, W, MSV)                                                                                 \
+    hipLaunchKernelGGL((k_col_fft<R, I, E, W, MSV>), grid, dim3(g.col_threads), lds, st, spec, ncols, M, g.cols, planM, \
+                       tw)
+#define SE2N_COL_E(I)                                                   \
+    if (static_size<R>(M, g) == 2048) SE2N_COL(I, 8, false, kStatic<R> ? 2048 : 0);      \
+    else if (static_size<R>(M, g) == 1024) SE2N_COL(I, 8, false, kStatic<R> ? 1024 : 0); \
+    else if (static_size<R>(M, g) == 512) SE2N_COL(I, 8, false, kStatic<R> ? 512 : 0);   \
+    else if (g.tw_full_col) {                                           \
+        if (g.col_ept == 8) SE2N_COL(I, 8, true, 0);                    \
+        else SE2N_COL(I, 16, true, 0);                                  \
+    } else {                                                            \
+        if (g.col_ept == 8) SE2N_COL(I, 8, false, 0);                   \
+        else SE2N_COL(I, 16, false, 0);                                 \
     }
+    if (inverse) { SE2N_COL_E(true) }
+    else { SE2N_COL_E(false) }
+#undef SE2N_COL_E
 #undef SE2N_COL
     return hipGetLastError();
 }
@@ -622,15 +684,15 @@ hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftP
                              const C2<R>* tw, double sigma, hipStream_t st) {
     const int K = M / 2 + 1;
     dim3 grid((K + g.ocols - 1) / g.ocols);
-    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(2 * g.ocols * M) * sizeof(C2<R>);
+    const size_t lds = tw_bytes<R>(M, g.tw_full_col != 0) + (size_t)lds_padded_size(2 * g.ocols * M) * sizeof(C2<R>);
     const double c = -2.0 * 9.869604401089358619 * sigma * sigma / ((double)M * M);
     const double scale = sqrt((double)M) / ((double)M * M);
     if (g.ocol_ept == 8)
-        hipLaunchKernelGGL((k_col_orient<R, 8>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols, planM,
-                           tw, (R)c, (R)scale);
+        hipLaunchKernelGGL((k_col_orient<R, 8, false>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols,
+                           planM, tw, (R)c, (R)scale);
     else
-        hipLaunchKernelGGL((k_col_orient<R, 16>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols, planM,
-                           tw, (R)c, (R)scale);
+        hipLaunchKernelGGL((k_col_orient<R, 16, false>), grid, dim3(g.ocol_threads), lds, st, spec, M, g.ocols,
+                           planM, tw, (R)c, (R)scale);
     return hipGetLastError();
 }
 
@@ -640,17 +702,20 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                           int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
     dim3 grid((M / g.rows) * groups);
-    const size_t lds = tw_bytes<R>(M) + (size_t)lds_padded_size(g.rows * (M / 2 + 1)) * sizeof(C2<R>);
-#define SE2N_ROWINV(D, E, W)                                                                                  \
-    hipLaunchKernelGGL((k_row_inv<R, D, E, W>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap, M,      \
-                       nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH, tw)
-#define SE2N_ROWINV_E(D)                               \
-    if (g.row_wave) {                                  \
-        if (g.row_ept == 8) SE2N_ROWINV(D, 8, true);   \
-        else SE2N_ROWINV(D, 16, true);                 \
-    } else {                                           \
-        if (g.row_ept == 8) SE2N_ROWINV(D, 8, false);  \
-        else SE2N_ROWINV(D, 16, false);                \
+    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 1)) * sizeof(C2<R>);
+#define SE2N_ROWINV(D, E, W, MSV)                                                                            \
+    hipLaunchKernelGGL((k_row_inv<R, D, E, W, MSV>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap,   \
+                       M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH, tw)
+#define SE2N_ROWINV_E(D)                                                    \
+    if (static_size<R>(M, g) == 2048) SE2N_ROWINV(D, 8, true, kStatic<R> ? 2048 : 0);        \
+    else if (static_size<R>(M, g) == 1024) SE2N_ROWINV(D, 8, true, kStatic<R> ? 1024 : 0);   \
+    else if (static_size<R>(M, g) == 512) SE2N_ROWINV(D, 8, true, kStatic<R> ? 512 : 0);     \
+    else if (g.tw_full) {                                                   \
+        if (g.row_ept == 8) SE2N_ROWINV(D, 8, true, 0);                     \
+        else SE2N_ROWINV(D, 16, true, 0);                                   \
+    } else {                                                                \
+        if (g.row_ept == 8) SE2N_ROWINV(D, 8, false, 0);                    \
+        else SE2N_ROWINV(D, 16, false, 0);                                  \
     }
     if (dst == DST_MAX) { SE2N_ROWINV_E(DST_MAX) }
     else if (dst == DST_SUM) { SE2N_ROWINV_E(DST_SUM) }

@@ -80,6 +80,7 @@ FftPlan make_fft_plan(int L, int M) {
         s.twstep = M / (Ns * rad[i]);
         s.inv_nb = 1.0f / (float)s.nb;
         s.inv_Ns = 1.0f / (float)Ns;
+        s.lg_Ns = (Ns & (Ns - 1)) == 0 ? __builtin_ctz((unsigned)Ns) : -1;
         Ns *= rad[i];
     }
     return p;
@@ -184,49 +185,51 @@ struct ProfScope {
         SE2N_HIP(call, what);                  \
     } while (0)
 
-// Threads and per-thread staging for `elems` complex elements in one workgroup.
-void fft_threads(int elems, int* threads, int* ept) {
-    *ept = 8;
-    *threads = (elems + 7) / 8;
-    if (*threads > 1024) {
-        *ept = 16;
-        *threads = (elems + 15) / 16;
-    }
-}
-
 template <class R>
 LaunchGeom make_geom(int M, int N) {
-    const int target = sizeof(R) == 4 ? 4096 : 2048;  // complex elements per FFT workgroup
-    const int H = M / 2;
+    const GeomCore c = geom_core<R>(M);
     LaunchGeom g{};
-    int rows = 64 / (int)sizeof(C2<R>);  // 64-byte segments per (slice, kx)
-    while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
-    g.rows = rows;
-    fft_threads(rows * H, &g.row_threads, &g.row_ept);
-    // the row passes walk (kx, row) pairs with thread t on row t mod rows
-    g.row_threads = (g.row_threads + rows - 1) / rows * rows;
-    // optionally one wavefront per row (8 or 16 elements per lane); measured
-    // slower than the workgroup-wide transform at 2048^2, so off by default
-    g.row_wave = 0;
-    const char* wv = std::getenv("SE2N_ROW_WAVE");
-    if (wv && std::atoi(wv) != 0 && H % 64 == 0 && (H / 64 == 8 || H / 64 == 16) && rows * 64 <= 512) {
-        g.row_wave = 1;
-        g.row_threads = rows * 64;
-        g.row_ept = H / 64;
-    }
-    const int row_blocks = M / rows;
+    g.rows = c.rows;
+    g.row_threads = c.row_threads;
+    g.row_ept = c.row_ept;
+    g.cols = c.cols;
+    g.col_threads = c.col_threads;
+    g.col_ept = c.col_ept;
+    g.ocols = c.ocols;
+    g.ocol_threads = c.ocol_threads;
+    g.ocol_ept = c.ocol_ept;
+    g.tw_full = c.tw_full;
+    g.tw_full_col = c.tw_full_col;
+    const int row_blocks = M / c.rows;
     int groups = (1024 + row_blocks - 1) / row_blocks;
     if (groups > N) groups = N;
     if (groups < 1) groups = 1;
     g.row_slices = (N + groups - 1) / groups;
     g.inv_slices = g.row_slices;
-    g.cols = target / M > 1 ? target / M : 1;
-    fft_threads(g.cols * M, &g.col_threads, &g.col_ept);
-    g.ocols = target / (2 * M) > 1 ? target / (2 * M) : 1;
-    fft_threads(2 * g.ocols * M, &g.ocol_threads, &g.ocol_ept);
     g.xcd_pair = 1;
+    if (const char* v = std::getenv("SE2N_TW_FULL")) g.tw_full = std::atoi(v) != 0 && g.tw_full;
     if (const char* v = std::getenv("SE2N_XCD_PAIR")) g.xcd_pair = std::atoi(v);
+    g.static_ok = std::getenv("SE2N_NO_STATIC") == nullptr;
     return g;
+}
+
+// Invariants the kernels rely on; a violation is a library bug, reported as
+// SE2N_EUNSUPPORTED instead of launching.
+template <class R>
+int check_geom(const LaunchGeom& g, int M) {
+    const int H = M / 2;
+    const size_t cs = sizeof(C2<R>);
+    const size_t lds_max = 160 * 1024;
+    const bool ok =
+        g.rows >= 1 && (g.rows & (g.rows - 1)) == 0 && M % g.rows == 0 && g.row_slices >= 1 &&
+        g.inv_slices >= 1 && g.row_threads >= 1 && g.row_threads <= 1024 && g.row_threads % g.rows == 0 &&
+        g.rows * H <= g.row_ept * g.row_threads && g.cols >= 1 && g.col_threads >= 1 && g.col_threads <= 1024 &&
+        g.cols * M <= g.col_ept * g.col_threads && g.ocols >= 1 && g.ocol_threads >= 1 && g.ocol_threads <= 1024 &&
+        2 * g.ocols * M <= g.ocol_ept * g.ocol_threads &&
+        (size_t)(tw_elems(M, g.tw_full) + lds_padded_size(g.rows * (H + 1))) * cs <= lds_max &&
+        (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(2 * g.ocols * M)) * cs <= lds_max &&
+        (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(g.cols * M)) * cs <= lds_max;
+    return ok ? SE2N_OK : fail(SE2N_EUNSUPPORTED, "internal launch geometry invalid for M=%d", M);
 }
 
 int check_plan(se2n_plan p) {
@@ -450,10 +453,12 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     int rc;
     if (dtype == SE2N_F32) {
         p->geom = make_geom<float>(M, N);
-        rc = make_twiddles<float>(p);
+        rc = check_geom<float>(p->geom, M);
+        if (!rc) rc = make_twiddles<float>(p);
     } else {
         p->geom = make_geom<double>(M, N);
-        rc = make_twiddles<double>(p);
+        rc = check_geom<double>(p->geom, M);
+        if (!rc) rc = make_twiddles<double>(p);
     }
     if (rc) {
         if (p->tw) (void)hipFree(p->tw);
