@@ -98,7 +98,7 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     // full-period twiddle table for the row passes when it fits beside the row
     // buffer; a column workgroup transforms only a few columns, for which
     // expanding the full table would cost as much as the transform
-    g.tw_full = (long)M * cs + (long)lds_padded_size(rows * (H + 1)) * cs <= 150 * 1024 ? 1 : 0;
+    g.tw_full = (long)M * cs + (long)lds_padded_size(rows * (H + 2)) * cs <= 150 * 1024 ? 1 : 0;
     g.tw_full_col = 0;
     return g;
 }

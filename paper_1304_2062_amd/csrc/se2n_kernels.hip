@@ -85,6 +85,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const
     C2<R>* buf = tw + tw_elems(M, twfull);
     const int H = M >> 1;
     const int K = H + 1;
+    const int S = H + 2;  // LDS row stride: 8 rows of the transposed phase fall in distinct banks
     const int tid = threadIdx.x;
     const int nthr = MS ? GC.row_threads : (int)blockDim.x;
     int rb, grp;
@@ -141,14 +142,16 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const
                     z.x = fc0[i];
                     z.y = fc1[i];
                 }
-                buf[lds_pad(e)] = z;
+                int row, n;
+                split_index(tid, i, nthr, H, inv_H, row, n);
+                buf[lds_pad(row * S + n)] = z;
             }
         }
         __syncthreads();
         if constexpr (MS != 0)
-            fft_static<R, false, TWF, MS / 2, GC.rows, MS / 2, GC.row_threads, MS>(buf, tw, tid);
+            fft_static<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
         else
-            fft_lds<R, false, EPT, TWF>(buf, planH, rows, H, tw, M4, tid, nthr);
+            fft_lds<R, false, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
         // unpack the real transform and write (r, kx, y0..y0+rows) segments
         const int nout = rows * K;
         C2<R>* out = spec + (size_t)s * K * M + y0;
@@ -156,8 +159,8 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const
         for (int e = tid; e < nout; e += nthr) {
             const int kx = e >> rshift;
             const int row = e & (rows - 1);
-            const C2<R> z1 = buf[lds_pad(row * H + (kx == H ? 0 : kx))];
-            const C2<R> z2 = buf[lds_pad(row * H + (kx == 0 ? 0 : H - kx))];
+            const C2<R> z1 = buf[lds_pad(row * S + (kx == H ? 0 : kx))];
+            const C2<R> z2 = buf[lds_pad(row * S + (kx == 0 ? 0 : H - kx))];
             const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
             // (z1 - conj z2)/(2i)
             const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
@@ -274,7 +277,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
     C2<R>* buf = tw + tw_elems(M, twfull);
     const int H = M >> 1;
     const int K = H + 1;
-    const int S = H + 1;  // LDS row stride
+    const int S = H + 2;  // LDS row stride: 8 rows of the transposed phase fall in distinct banks
     const int tid = threadIdx.x;
     const int nthr = MS ? GC.row_threads : (int)blockDim.x;
     int rb, grp;
@@ -318,6 +321,8 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
         }
         __syncthreads();
         if (s + 1 < s_end) SE2N_FETCH(s + 1);
+        // pairing step of the real inverse transform:
+        //   Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]),  k < H
         const int npair = H / 2 + 1;
         const float inv_npair = 1.0f / (float)npair;
         for (int e = tid; e < rows * npair; e += nthr) {
@@ -326,24 +331,18 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
             const int kk = H - k;
             const C2<R> a = buf[lds_pad(row * S + k)];
             const C2<R> b = buf[lds_pad(row * S + kk)];
-            // Z[k]
             const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);      // a + conj b
             const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);      // a - conj b
-            const C2<R> wa = cconj<R>(tw_get<R, TWF>(tw, k, M4));
-            const C2<R> ta = cmul<R>(wa, da);
-            const C2<R> za = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
-            // Z[H-k]
+            const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, TWF>(tw, k, M4)), da);
             const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
             const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
-            const C2<R> wb = cconj<R>(tw_get<R, TWF>(tw, kk, M4));
-            const C2<R> tb = cmul<R>(wb, db);
-            const C2<R> zb = cmk<R>(sb.x - tb.y, sb.y + tb.x);
-            buf[lds_pad(row * S + k)] = za;
-            if (kk != k) buf[lds_pad(row * S + kk)] = zb;
+            const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, TWF>(tw, kk, M4)), db);
+            buf[lds_pad(row * S + k)] = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
+            if (kk != k) buf[lds_pad(row * S + kk)] = cmk<R>(sb.x - tb.y, sb.y + tb.x);
         }
         __syncthreads();
         if constexpr (MS != 0)
-            fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 1, GC.row_threads, MS>(buf, tw, tid);
+            fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
         else
             fft_lds<R, true, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
 #pragma unroll
@@ -630,7 +629,7 @@ hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_
                           const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + g.row_slices - 1) / g.row_slices;
     dim3 grid((M / g.rows) * groups);
-    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2)) * sizeof(C2<R>);
+    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 2)) * sizeof(C2<R>);
 #define SE2N_ROWFWD(S, E, W, MSV)                                                                          \
     hipLaunchKernelGGL((k_row_fwd<R, S, E, W, MSV>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol,    \
                        spec, M, nslices, g.row_slices, g.rows, g.xcd_pair, planH, tw)
@@ -702,7 +701,7 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                           int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
     dim3 grid((M / g.rows) * groups);
-    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 1)) * sizeof(C2<R>);
+    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 2)) * sizeof(C2<R>);
 #define SE2N_ROWINV(D, E, W, MSV)                                                                            \
     hipLaunchKernelGGL((k_row_inv<R, D, E, W, MSV>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap,   \
                        M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH, tw)

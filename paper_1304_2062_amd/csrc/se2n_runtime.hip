@@ -226,7 +226,7 @@ int check_geom(const LaunchGeom& g, int M) {
         g.rows * H <= g.row_ept * g.row_threads && g.cols >= 1 && g.col_threads >= 1 && g.col_threads <= 1024 &&
         g.cols * M <= g.col_ept * g.col_threads && g.ocols >= 1 && g.ocol_threads >= 1 && g.ocol_threads <= 1024 &&
         2 * g.ocols * M <= g.ocol_ept * g.ocol_threads &&
-        (size_t)(tw_elems(M, g.tw_full) + lds_padded_size(g.rows * (H + 1))) * cs <= lds_max &&
+        (size_t)(tw_elems(M, g.tw_full) + lds_padded_size(g.rows * (H + 2))) * cs <= lds_max &&
         (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(2 * g.ocols * M)) * cs <= lds_max &&
         (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(g.cols * M)) * cs <= lds_max;
     return ok ? SE2N_OK : fail(SE2N_EUNSUPPORTED, "internal launch geometry invalid for M=%d", M);
