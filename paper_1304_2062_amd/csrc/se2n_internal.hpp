@@ -103,6 +103,28 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     return g;
 }
 
+// Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its
+// own L2.  This maps dispatch index i of n to a logical index such that each
+// XCD receives one contiguous range of logical indices, in order: logical
+// neighbours run on the same XCD at about the same time and share the L2
+// lines they both touch.  A bijection on [0, n) for any n.
+__host__ __device__ constexpr int xcd_contiguous(int i, int n) {
+    const int per = n / 8;
+    const int rem = n % 8;
+    const int xcd = i % 8;
+    const int slot = i / 8;
+    return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
+}
+
+// Row stride (in elements) of the propagator table P[lx][element][ly]: the
+// M/4 + 1 classes of a row rounded up to a whole number of 128-byte lines,
+// so that a workgroup's contiguous run of classes touches no extra line.
+template <class R>
+__host__ __device__ constexpr int table_stride(int M) {
+    constexpr int line = 128 / (int)sizeof(R);
+    return (M / 4 + 1 + line - 1) / line * line;
+}
+
 template <class R>
 hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_t* rmap, const R* vol,
                           C2<R>* spec, int M, int nslices, const LaunchGeom& g, const FftPlan& planH,

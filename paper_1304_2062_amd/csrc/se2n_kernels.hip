@@ -466,7 +466,7 @@ __device__ void lds_copy(const double* A, double* B, int n, int tid) {
 }
 
 template <class R>
-__global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q,
+__global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q, int Qs,
                                                    double beta, double T, int nsteps, int scheme,
                                                    double scale) {
     extern __shared__ double sm[];
@@ -585,14 +585,14 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
             }
         }
         // packed upper triangle, symmetrised, scaled, stored as R
-        R* dst = Ptab + (size_t)lx * E * Q + ly;
+        R* dst = Ptab + (size_t)lx * E * Qs + ly;
         for (int idx = tid; idx < hh; idx += 64) {
             const int i = idx / h;
             const int j = idx - i * h;
             if (j >= i) {
                 const int e = blk * Eh + i * h - i * (i - 1) / 2 + (j - i);
                 const double v = 0.5 * (Rs[i * h + j] + Rs[j * h + i]) * scale;
-                dst[(size_t)e * Q] = (R)v;
+                dst[(size_t)e * Qs] = (R)v;
             }
         }
         __syncthreads();
@@ -762,7 +762,8 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
     const int h = N / 2;
     const size_t lds = (size_t)(6 * h * h + h) * sizeof(double);
     const double scale = 1.0 / (2.0 * (double)M * (double)M);
-    hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q, beta,
+    hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q,
+                       table_stride<R>(M), beta,
                        T, nsteps, scheme, scale);
     return hipGetLastError();
 }

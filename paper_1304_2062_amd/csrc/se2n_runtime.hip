@@ -136,8 +136,9 @@ struct se2n_plan_s {
     size_t workspace() const { return spec_bytes() + enc_bytes() + rmap_bytes(); }
     size_t table_bytes() const {
         const size_t Q = (size_t)(M / 4 + 1);
+        const size_t Qs = (size_t)(dt == SE2N_F32 ? table_stride<float>(M) : table_stride<double>(M));
         const size_t h = (size_t)(N / 2);
-        return Q * Q * h * (h + 1) * real_size();
+        return Q * Qs * h * (h + 1) * real_size();
     }
 };
 

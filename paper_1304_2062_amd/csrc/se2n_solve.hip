@@ -18,7 +18,7 @@ namespace se2n {
 // coupling).  The table holds, per frequency class (lx, ly) with
 // |s_kx| = sin(2 pi lx/M), |s_ky| = sin(2 pi ly/M), lx, ly in [0, M/4], the
 // packed upper triangles of both blocks, scaled by 1/(2 M^2), laid out as
-// P[lx][element][ly].
+// P[lx][element][ly] with a line-aligned ly stride.
 //
 // The members of class (lx, ly) in the half spectrum are kx in {lx, M/2-lx}
 // and ky in {ly, M/2-ly, M/2+ly, M-ly}.  Where s_kx s_ky < 0 (ky > M/2) the
@@ -48,23 +48,53 @@ __device__ __forceinline__ double swap_pair(double v) {
 
 template <class R, int N, int CLS, int WAVES>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_solve(C2<R>* __restrict__ spec, const R* __restrict__ P, int M,
-                                               int Q) {
+                                               int Q, int Qs) {
     constexpr int h = N / 2;
     constexpr int Eh = h * (h + 1) / 2;
     constexpr int E = 2 * Eh;
     extern __shared__ unsigned char smem_raw[];
     R* Ps = reinterpret_cast<R*>(smem_raw);
     const int H = M >> 1;
+    constexpr int NT = 16 * CLS < 512 ? 16 * CLS : 512;  // blockDim.x: two lanes per mode
     const int tid = threadIdx.x;
-    const int nthr = blockDim.x;
-    const int lx = blockIdx.y;
-    const int ly0 = blockIdx.x * CLS;
+    const int nthr = NT;
+    // adjacent class blocks of one lx share the cache lines at the ends of
+    // their mirrored (reversed) ky runs: keep them on one XCD
+    const int nb = (Q + CLS - 1) / CLS;
+    const int blk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int lx = blk / nb;
+    const int ly0 = (blk - lx * nb) * CLS;
     const int ncls = min(CLS, Q - ly0);
-    const R* __restrict__ src = P + (size_t)lx * E * Q + ly0;
-    for (int i = tid; i < E * CLS; i += nthr) {
-        const int e = i / CLS;
-        const int c = i - e * CLS;
-        Ps[i] = c < ncls ? src[(size_t)e * Q + c] : R(0);
+    // Stage the block's propagators: 16-byte chunks, every load of a thread
+    // issued before the first is waited on.  A chunk that starts inside the
+    // block's classes lies inside the line-padded row; classes past the last
+    // one are zeroed.
+    {
+        constexpr int VEC = 16 / (int)sizeof(R);
+        typedef R vec_t __attribute__((ext_vector_type(VEC)));
+        constexpr int CH = E * CLS / VEC;  // CLS >= 8 is a multiple of VEC
+        constexpr int NST = (CH + NT - 1) / NT;
+        constexpr int BATCH = NST < 8 ? NST : 8;  // loads in flight per thread
+        const R* __restrict__ src = P + (size_t)lx * E * Qs + ly0;
+        for (int k0 = 0; k0 < NST; k0 += BATCH) {
+        vec_t v[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int i = tid + (k0 + k) * NT;
+            const int e = i / (CLS / VEC);
+            const int c0 = (i - e * (CLS / VEC)) * VEC;
+            v[k] = vec_t(0);
+            if (i < CH && c0 < ncls) v[k] = *reinterpret_cast<const vec_t*>(src + (size_t)e * Qs + c0);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q)
+                if (c0 + q >= ncls) v[k][q] = R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int i = tid + (k0 + k) * NT;
+            if (i < CH) reinterpret_cast<vec_t*>(Ps)[i] = v[k];
+        }
+        }
     }
     __syncthreads();
     const size_t plane = (size_t)(H + 1) * M;
@@ -177,10 +207,11 @@ static hipError_t launch_solve_n(C2<R>* spec, const R* P, int M, hipStream_t st)
     constexpr int h = N / 2;
     constexpr int E = h * (h + 1);
     const int Q = M / 4 + 1;
-    dim3 grid((Q + CLS - 1) / CLS, Q);
-    const int threads = 16 * CLS < 512 ? 16 * CLS : 512;  // two lanes per mode
+    const dim3 grid((unsigned)(((Q + CLS - 1) / CLS) * Q));
+    const int threads = 16 * CLS < 512 ? 16 * CLS : 512;  // the kernel's NT
     const size_t lds = (size_t)E * CLS * sizeof(R);
-    hipLaunchKernelGGL((k_solve<R, N, CLS, WAVES>), grid, dim3(threads), lds, st, spec, P, M, Q);
+    hipLaunchKernelGGL((k_solve<R, N, CLS, WAVES>), grid, dim3(threads), lds, st, spec, P, M, Q,
+                       table_stride<R>(M));
     return hipGetLastError();
 }
 
