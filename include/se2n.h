@@ -160,6 +160,129 @@ typedef struct {
 int se2n_profile(se2n_plan plan, int enable);
 int se2n_profile_stats(se2n_plan plan, se2n_kernel_stat *out, int capacity, int *count);
 
+/* ------------------------------------------------------------------------
+ * Batched inpainting of many independent images (FP32)
+ * ------------------------------------------------------------------------
+ * The whole path of se2n_inpaint (orientation map computed, CN or EXACT,
+ * max or mean projection) for `count` images of possibly different M, N,
+ * T, beta, n_steps, sigma.  Each pass (orientation rows / columns /
+ * inverse rows, lift + row FFT, column FFT, per-mode propagation, inverse
+ * column FFT, inverse row FFT + projection) is ONE persistent launch over
+ * the tiles of every image; the passes of a batch are captured once into a
+ * hipGraph that each call replays with a single graph launch.
+ *
+ * The library keeps, per device and per batch signature (the list of
+ * (M, N, n_steps, scheme, proj, T, beta, sigma) of the items, pointers
+ * excluded), a batch plan: the FP64-precomputed propagator tables (one per
+ * distinct (M, N, T, beta, n_steps, scheme)), twiddle tables, tile lists
+ * and the instantiated graph.  The first call with a new signature builds
+ * it (propagators computed on `stream`); later calls only upload the items'
+ * pointers when they changed and launch the graph.  At most 4 signatures
+ * are cached per device (least recently used dropped); se2n_batch_clear
+ * frees them all.
+ *
+ * Items: M = 2^a 3^b, a >= 3, 16 <= M <= 1024; N even in [4, 64];
+ * T >= 0, beta >= 0, sigma > 0, n_steps >= 1 for SE2N_CN; f, mask, out
+ * non-NULL device pointers ([M][M] float / uint8 / float), rmap_out NULL or
+ * [M][M] uint8 (receives the orientation map).  Outputs of different items
+ * must not overlap.  count in [1, 4096].
+ * Calls on one device that overlap in time must use different workspaces
+ * and signatures or be ordered on one stream: a batch plan holds one
+ * device-side item table. */
+typedef struct {
+    int M, N, n_steps;
+    int scheme; /* se2n_scheme */
+    int proj;   /* se2n_proj */
+    int reserved;
+    double T, beta, sigma;
+    const float *f;
+    const uint8_t *mask;
+    uint8_t *rmap_out;
+    float *out;
+} se2n_item;
+
+/* Schedule of a batch (what the autotuner chooses).
+ *   wg_per_cu   persistent workgroups per compute unit for every pass
+ *               (1..16); 0 launches one workgroup per tile instead.
+ *   order       0: tiles of each pass sorted by decreasing cost (largest
+ *               first), 1: image by image in item order.
+ *   row_groups  slice groups of the lift and inverse row passes (1..64,
+ *               clamped to N): >1 gives more, smaller tiles; the max
+ *               projection then combines groups with integer atomics
+ *               (extra clear and decode passes). */
+typedef struct {
+    int wg_per_cu;
+    int order;
+    int row_groups;
+    int reserved;
+} se2n_tune;
+
+/* Device workspace bytes se2n_inpaint_batched needs for these items: per
+ * item the half-spectrum volume, a max-combining buffer and an orientation
+ * map.  Returns 0 if an item is invalid (see se2n_last_error). */
+size_t se2n_batch_workspace_bytes(const se2n_item *items, int count);
+
+/* Inpaint every item (see above).  workspace: at least
+ * se2n_batch_workspace_bytes(items, count) bytes of device memory.
+ * Errors: SE2N_EINVAL (count, item or pointer), SE2N_ENOMEM, SE2N_EHIP. */
+int se2n_inpaint_batched(const se2n_item *items, int count, void *workspace, void *stream);
+
+/* Autotuner: time the batch under each candidate schedule (wg_per_cu in
+ * {0, 1, 2, 4} x order in {0, 1} x row_groups in {1, 2, 4}), `reps` graph
+ * launches each after one warm-up, on `stream` (this call synchronises it),
+ * and keep the fastest for this signature.  If table_path is non-NULL the
+ * choice is also written there (one JSON object per line, keyed by the
+ * device's architecture name and the signature hash; an existing entry for
+ * the key is replaced).  best / best_ms may be NULL.  The items' outputs
+ * hold the result of one of the runs (all candidates compute the same
+ * result up to FP32 rounding order).
+ * Errors: as se2n_inpaint_batched; SE2N_EINVAL if reps < 1; SE2N_EHIP if the
+ * table file cannot be written. */
+int se2n_batch_autotune(const se2n_item *items, int count, void *workspace, void *stream, int reps,
+                        const char *table_path, se2n_tune *best, double *best_ms);
+
+/* Read tuning entries written by se2n_batch_autotune; later batch plans
+ * whose architecture and signature match use them.  The table named by the
+ * environment variable SE2N_TUNE_TABLE, if set, is read at the first batched
+ * call.  Lines that do not parse are skipped.
+ * Errors: SE2N_EINVAL (NULL path), SE2N_EHIP (file cannot be read). */
+int se2n_batch_load_tune_table(const char *path);
+
+/* Set (tune non-NULL) or query the schedule used for this signature on the
+ * current device; setting drops a cached plan of that signature so the next
+ * call rebuilds it.  Precedence: se2n_batch_set_tune > loaded table >
+ * defaults {wg_per_cu 2, order 0, row_groups 1}.  Host only.
+ * Errors: SE2N_EINVAL (bad items, NULL out, tune field out of range). */
+int se2n_batch_set_tune(const se2n_item *items, int count, const se2n_tune *tune);
+int se2n_batch_get_tune(const se2n_item *items, int count, se2n_tune *out);
+
+/* The tile list of one pass of a batch under `tune` (NULL: the current
+ * schedule), in execution order, 4 ints per tile {item, a, b, c}:
+ *   pass 0 orientation rows     {item, row block, 0, 1}
+ *   pass 1 orientation columns  {item, first column kx, 0, 0}
+ *   pass 2 orientation inverse  {item, row block, 0, 2}
+ *   pass 3 lift + row FFT       {item, row block, first slice, end slice}
+ *   pass 4 column FFT (fwd and inverse share it) {item, first column, 0, 0}
+ *   pass 5 per-mode propagation {item, lx, first ly, N}
+ *   pass 6 inverse rows         {item, row block, first slice, end slice}
+ *   pass 7 max clear / decode   {item, first pixel, pixel count, 0}
+ * tiles may be NULL to query *ntiles only; at most `capacity` tiles are
+ * written.  Host only, no device work.
+ * Errors: SE2N_EINVAL. */
+int se2n_batch_tiles(const se2n_item *items, int count, const se2n_tune *tune, int pass, int *tiles,
+                     int capacity, int *ntiles);
+
+/* Per-pass timing of batched calls.  While enabled, se2n_inpaint_batched
+ * launches the passes one by one (no graph) with hipEvents around each;
+ * se2n_batch_profile_stats returns the launches and summed milliseconds per
+ * pass name as se2n_profile_stats does.  Enabling or disabling clears them.
+ * Errors: SE2N_EINVAL, SE2N_EHIP. */
+int se2n_batch_profile(int enable);
+int se2n_batch_profile_stats(se2n_kernel_stat *out, int capacity, int *count);
+
+/* Free every cached batch plan on every device (waits for the device). */
+int se2n_batch_clear(void);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *se2n_last_error(void);
 

@@ -1,0 +1,281 @@
+// Persistent batched kernels (FP32): every pass of the inpainting path as one
+// launch over the tiles of many images.  A workgroup walks the pass's tile
+// list with stride gridDim.x; a tile {item, a, b, c} names its image and the
+// part of that image's work (row block and slice range, first column, class
+// block, pixel range).  The image's twiddle table is expanded into LDS only
+// when the previous tile of the workgroup belonged to an image of another
+// table.  The tile bodies are the ones the single-image kernels run; images
+// of side 512 and 1024 use the bodies compiled for those sizes.
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "se2n_batch.hpp"
+#include "se2n_fft.hpp"
+#include "se2n_internal.hpp"
+#include "se2n_passes.hpp"
+
+namespace se2n {
+
+namespace {
+
+constexpr int BT = kBatchThreads;
+// the fixed-size bodies assume their own thread counts: they must be BT
+static_assert(geom_core<float>(1024).row_threads == BT && geom_core<float>(1024).col_threads == BT,
+              "fixed-size row/column bodies for M=1024 need 512 threads");
+static_assert(geom_core<float>(512).row_threads == BT && geom_core<float>(512).col_threads == BT,
+              "fixed-size row/column bodies for M=512 need 512 threads");
+static_assert(geom_core<float>(1024).tw_full == 1 && geom_core<float>(512).tw_full == 1,
+              "fixed-size row bodies use the full twiddle table");
+
+using C = C2<float>;
+
+// The thread index, hidden from loop-invariant code motion: the tile bodies
+// derive many per-thread addresses from it, and hoisting them out of the
+// tile loop would keep all of them live across it.
+__device__ __forceinline__ int opaque_tid() {
+    int t = threadIdx.x;
+    asm volatile("" : "+v"(t));
+    return t;
+}
+
+__device__ __forceinline__ const BItem& item_of(const BItem* __restrict__ items, int idx) {
+    return items[__builtin_amdgcn_readfirstlane(idx)];
+}
+
+// Expand the image's quarter table into LDS unless it is already there.
+// Called right after a barrier, so no thread still reads the old table.
+template <bool FULL>
+__device__ __forceinline__ void ensure_twiddles(C* tw, const C* src, int M, const C*& cur) {
+    if (src != cur) {
+        load_twiddles<float>(tw, src, M >> 2, FULL, threadIdx.x, BT);
+        cur = src;
+    }
+}
+
+// Uniform copy of a value loaded from the item table (kept in scalar registers).
+template <class T>
+__device__ __forceinline__ T uni(T v) {
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit values only");
+    int w[sizeof(T) / 4];
+    __builtin_memcpy(w, &v, sizeof(T));
+#pragma unroll
+    for (int i = 0; i < (int)(sizeof(T) / 4); ++i) w[i] = __builtin_amdgcn_readfirstlane(w[i]);
+    __builtin_memcpy(&v, w, sizeof(T));
+    return v;
+}
+
+// The row and column kernels come in three size classes, each launched over
+// the tiles of its own images: MS = 1024 and MS = 512 run the bodies compiled
+// for that side, MS = 0 the generic body for every other side.
+template <int SRC, int MS>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb_row_fwd(const BItem* __restrict__ items, const int4* __restrict__ tiles,
+                                                 int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    const C* cur = nullptr;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        const int M = MS ? MS : uni(d.M);
+        C* buf = tw + tw_elems(M, true);
+        __syncthreads();
+        ensure_twiddles<true>(tw, uni(d.tw), M, cur);
+        row_fwd_tile<float, SRC, 8, true, MS>(uni(d.f), uni(d.mask), SRC == SRC_LIFT ? uni(d.rmap) : nullptr, nullptr,
+                                              uni(d.spec), M, uni(d.rows), BT, tl.y, tl.z, tl.w, d.planH, tw, buf,
+                                              opaque_tid());
+    }
+}
+
+template <bool INV, int MS>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb_col_fft(const BItem* __restrict__ items, const int4* __restrict__ tiles,
+                                                 int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    const C* cur = nullptr;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        const int M = MS ? MS : uni(d.M);
+        C* buf = tw + tw_elems(M, false);
+        const long ncols = (long)uni(d.N) * (M / 2 + 1);
+        __syncthreads();
+        ensure_twiddles<false>(tw, uni(d.tw), M, cur);
+        col_fft_tile<float, INV, 8, false, MS>(uni(d.spec), ncols, M, uni(d.cols), BT, tl.y, d.planM, tw, buf,
+                                               opaque_tid());
+    }
+}
+
+__global__ __launch_bounds__(BT) void kb_col_orient(const BItem* __restrict__ items, const int4* __restrict__ tiles,
+                                                    int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    const C* cur = nullptr;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        const int M = uni(d.M);
+        C* buf = tw + tw_elems(M, false);
+        __syncthreads();
+        ensure_twiddles<false>(tw, uni(d.tw), M, cur);
+        col_orient_tile<float, 8, false>(uni(d.spec), M, uni(d.ocols), BT, tl.y, d.planM, tw, buf, uni(d.ocoef),
+                                         uni(d.oscale), opaque_tid());
+    }
+}
+
+// Inverse row pass: orientation binning (DST_ORIENT), max projection
+// (DST_MAX: written directly with one slice group, else combined through the
+// item's atomic buffer) or mean projection (DST_SUM, one slice group).
+template <int DST, int MS>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb_row_inv(const BItem* __restrict__ items, const int4* __restrict__ tiles,
+                                                 int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    const C* cur = nullptr;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        const int M = MS ? MS : uni(d.M);
+        const int N = uni(d.N);
+        C* buf = tw + tw_elems(M, true);
+        __syncthreads();
+        ensure_twiddles<true>(tw, uni(d.tw), M, cur);
+        unsigned* enc = (DST == DST_MAX && uni(d.groups) > 1) ? uni(d.enc) : nullptr;
+        const float sc = DST == DST_SUM ? 1.0f / (float)N : 1.0f;
+        row_inv_tile<float, DST, 8, true, MS>(uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
+                                              DST == DST_ORIENT ? uni(d.rmap) : nullptr, M, uni(d.rows), BT, tl.y,
+                                              tl.z, tl.w, N, sc, d.planH, tw, buf, opaque_tid());
+    }
+}
+
+// Clear (DECODE = false) or decode into the output (DECODE = true) the
+// max-combining buffer over pixels [b, b + c) of an image.
+template <bool DECODE>
+__global__ __launch_bounds__(BT) void kb_enc(const BItem* __restrict__ items, const int4* __restrict__ tiles,
+                                             int ntiles) {
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        unsigned* enc = uni(d.enc);
+        float* out = uni(d.out);
+        for (int e = threadIdx.x; e < tl.z; e += BT) {
+            const long p = (long)tl.y + e;
+            if (DECODE) out[p] = Enc<float>::decode(enc[p]);
+            else enc[p] = 0u;
+        }
+    }
+}
+
+template <int N, int CLS, int WAVES>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) void kb_solve(
+    const BItem* __restrict__ items, const int4* __restrict__ tiles, int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    float* Ps = reinterpret_cast<float*>(smem_raw);
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        __syncthreads();
+        solve_tile<float, N, CLS>(uni(d.spec), uni(d.P), uni(d.M), uni(d.Q), uni(d.Qs), tl.y, tl.z, Ps,
+                                  opaque_tid());
+    }
+}
+
+template <int N>
+struct SolveCfg {
+    static constexpr int CLS = solve_cls<float, N>();
+    static constexpr int WAVES = (N * 4) <= 160 ? 4 : 2;
+    static constexpr int THREADS = 16 * CLS < 512 ? 16 * CLS : 512;
+};
+
+// Calls f(kernel pointer, threads) for the kernel of a pass; `cls` selects
+// the size class of the row and column kernels (0 generic, 1: M = 512,
+// 2: M = 1024), N the solve instance.
+template <class F>
+hipError_t with_kernel(int kind, int N, int cls, F&& f) {
+#define SE2N_BY_CLASS(K)                                        \
+    (cls == 2 ? (const void*)K<1024> : cls == 1 ? (const void*)K<512> : (const void*)K<0>)
+    switch (kind) {
+        case BK_ORIENT_ROW: {
+#define K_(m) kb_row_fwd<SRC_IMAGE, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+        case BK_LIFT_ROW: {
+#define K_(m) kb_row_fwd<SRC_LIFT, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+        case BK_ORIENT_COL: return f((const void*)kb_col_orient, BT);
+        case BK_ORIENT_INV: {
+#define K_(m) kb_row_inv<DST_ORIENT, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+        case BK_ROW_INV_MAX: {
+#define K_(m) kb_row_inv<DST_MAX, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+        case BK_ROW_INV_MEAN: {
+#define K_(m) kb_row_inv<DST_SUM, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+        case BK_COL_FWD: {
+#define K_(m) kb_col_fft<false, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+        case BK_COL_INV: {
+#define K_(m) kb_col_fft<true, m>
+            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+#undef K_
+        }
+#undef SE2N_BY_CLASS
+        case BK_FILL: return f((const void*)kb_enc<false>, BT);
+        case BK_DECODE: return f((const void*)kb_enc<true>, BT);
+        case BK_SOLVE:
+            switch (N) {
+#define SE2N_BCASE(n)                                                                                     \
+    case n:                                                                                               \
+        return f((const void*)kb_solve<n, SolveCfg<n>::CLS, SolveCfg<n>::WAVES>, SolveCfg<n>::THREADS);
+                SE2N_BCASE(4) SE2N_BCASE(6) SE2N_BCASE(8) SE2N_BCASE(10) SE2N_BCASE(12) SE2N_BCASE(14)
+                SE2N_BCASE(16) SE2N_BCASE(18) SE2N_BCASE(20) SE2N_BCASE(22) SE2N_BCASE(24) SE2N_BCASE(26)
+                SE2N_BCASE(28) SE2N_BCASE(30) SE2N_BCASE(32) SE2N_BCASE(34) SE2N_BCASE(36) SE2N_BCASE(38)
+                SE2N_BCASE(40) SE2N_BCASE(42) SE2N_BCASE(44) SE2N_BCASE(46) SE2N_BCASE(48) SE2N_BCASE(50)
+                SE2N_BCASE(52) SE2N_BCASE(54) SE2N_BCASE(56) SE2N_BCASE(58) SE2N_BCASE(60) SE2N_BCASE(62)
+                SE2N_BCASE(64)
+#undef SE2N_BCASE
+                default: return hipErrorInvalidValue;
+            }
+        default: return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace
+
+int batch_threads(int kind, int N) {
+    int threads = 0;
+    (void)with_kernel(kind, N, 0, [&](const void*, int th) {
+        threads = th;
+        return hipSuccess;
+    });
+    return threads;
+}
+
+hipError_t launch_batch(int kind, int N, int cls, const BItem* items, const int4* tiles, int ntiles, int grid,
+                        size_t lds, hipStream_t st) {
+    if (ntiles <= 0) return hipSuccess;
+    return with_kernel(kind, N, cls, [&](const void* fn, int threads) {
+        void* args[] = {(void*)&items, (void*)&tiles, (void*)&ntiles};
+        return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, lds, st);
+    });
+}
+
+hipError_t batch_occupancy(int kind, int N, int cls, size_t lds, int* per_cu) {
+    return with_kernel(kind, N, cls, [&](const void* fn, int threads) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(per_cu, fn, threads, lds);
+    });
+}
+
+}  // namespace se2n

@@ -1,0 +1,63 @@
+// Batched inpainting: the device-side item table and the persistent pass
+// kernels' launch interface (FP32).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "se2n_fft.hpp"
+#include "se2n_internal.hpp"
+
+namespace se2n {
+
+// One image of a batch as the kernels see it.  Pointers are refreshed on the
+// device whenever a call passes different buffers; the rest is fixed per
+// batch plan.
+struct BItem {
+    const float* f;
+    const uint8_t* mask;
+    uint8_t* rmap;     // orientation map (caller's rmap_out or workspace)
+    float* out;
+    C2<float>* spec;   // half-spectrum volume [N][M/2+1][M] (workspace)
+    unsigned* enc;     // max-combining buffer [M][M] (workspace)
+    const float* P;    // propagator table of (M, N, T, beta, n, scheme)
+    const C2<float>* tw;  // quarter-wave twiddles of M
+    int M, N, K, rows, cols, ocols, proj, groups, Q, Qs;
+    float ocoef, oscale;  // orientation: -2 pi^2 sigma^2 / M^2 and sqrt(M)/M^2
+    FftPlan planH, planM;
+};
+
+// Passes of a batch, in launch order.
+enum BatchKind {
+    BK_ORIENT_ROW = 0,
+    BK_ORIENT_COL,
+    BK_ORIENT_INV,
+    BK_LIFT_ROW,
+    BK_COL_FWD,
+    BK_SOLVE,
+    BK_COL_INV,
+    BK_FILL,
+    BK_ROW_INV_MAX,
+    BK_ROW_INV_MEAN,
+    BK_DECODE,
+    BK_COUNT
+};
+
+constexpr int kBatchThreads = 512;  // block size of every batched FFT / elementwise kernel
+constexpr int kBatchMaxM = 1024;    // largest M the batched kernels are built for
+
+// Threads per block of a pass (the solve's depends on N).
+int batch_threads(int kind, int N);
+// Size class of the row and column kernels: 2 for M = 1024, 1 for M = 512
+// (bodies compiled for that side), 0 for every other side.
+inline int batch_class(int M) { return M == 1024 ? 2 : (M == 512 ? 1 : 0); }
+
+// Launch one pass (size class `cls`, solve instance N): `grid` workgroups
+// walk tiles[0..ntiles) with stride grid.
+hipError_t launch_batch(int kind, int N, int cls, const BItem* items, const int4* tiles, int ntiles, int grid,
+                        size_t lds, hipStream_t st);
+// Resident workgroups per compute unit of a pass's kernel with `lds` bytes.
+hipError_t batch_occupancy(int kind, int N, int cls, size_t lds, int* per_cu);
+
+}  // namespace se2n

@@ -189,8 +189,13 @@ template <class R, int RADIX, bool INV, int EPT, bool TWFULL>
 __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nbatch, int bstride,
                                           const C2<R>* twq, int M4, int tid, int nthr) {
     constexpr int MAXB = (EPT + RADIX - 1) / RADIX;
-    const int nb = s.nb;
-    const int Ns = s.Ns;
+    // the stage parameters are uniform: keep them in scalar registers even
+    // when the plan lives in memory the compiler cannot prove read-only
+    const int nb = __builtin_amdgcn_readfirstlane(s.nb);
+    const int Ns = __builtin_amdgcn_readfirstlane(s.Ns);
+    const float inv_nb = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.inv_nb)));
+    const float inv_Ns = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(s.inv_Ns)));
+    const int twstep = __builtin_amdgcn_readfirstlane(s.twstep);
     const int total = nb * nbatch;
     C2<R> v[MAXB][RADIX];
     int obase[MAXB], kk[MAXB];
@@ -198,9 +203,9 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthr;
         if (b < total) {
-            const int t = fdiv(b, s.inv_nb);
+            const int t = fdiv(b, inv_nb);
             const int j = b - __mul24(t, nb);
-            const int q = fdiv(j, s.inv_Ns);
+            const int q = fdiv(j, inv_Ns);
             const int k = j - __mul24(q, Ns);
             const int ib = __mul24(t, bstride) + j;
 #pragma unroll
@@ -215,7 +220,7 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
         const int b = tid + i * nthr;
         if (b < total) {
             if (Ns > 1) {
-                const int e = __mul24(kk[i], s.twstep);
+                const int e = __mul24(kk[i], twstep);
 #pragma unroll
                 for (int r = 1; r < RADIX; ++r) {
                     C2<R> w = tw_get<R, TWFULL>(twq, r * e, M4);
@@ -239,11 +244,13 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
 template <class R, bool INV, int EPT, bool TWFULL>
 __device__ void fft_lds(C2<R>* buf, const FftPlan& plan, int nbatch, int bstride, const C2<R>* twq, int M4,
                         int tid, int nthr) {
-    for (int s = 0; s < plan.nstages; ++s) {
+    const int nst = __builtin_amdgcn_readfirstlane(plan.nstages);
+    for (int s = 0; s < nst; ++s) {
         const FftStage& st = plan.st[s];
-        if (st.radix == 8) fft_stage<R, 8, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
-        else if (st.radix == 4) fft_stage<R, 4, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
-        else if (st.radix == 3) fft_stage<R, 3, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        const int radix = __builtin_amdgcn_readfirstlane(st.radix);
+        if (radix == 8) fft_stage<R, 8, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else if (radix == 4) fft_stage<R, 4, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
+        else if (radix == 3) fft_stage<R, 3, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
         else fft_stage<R, 2, INV, EPT, TWFULL>(buf, st, nbatch, bstride, twq, M4, tid, nthr);
     }
 }

@@ -21,6 +21,7 @@
 
 #include "se2n_fft.hpp"
 #include "se2n_internal.hpp"
+#include "se2n_passes.hpp"
 
 namespace se2n {
 
@@ -44,363 +45,80 @@ __device__ __forceinline__ void row_block_of(int nrb, int ngroups, bool pair, in
     }
 }
 
-// (q, r) = divmod(tid + i*nthr, d) without a per-element division when nthr
-// is a multiple of d or d of nthr (uniform branches); inv_d = 1/d in float.
-__device__ __forceinline__ void split_index(int tid, int i, int nthr, int d, float inv_d, int& q, int& r) {
-    if (nthr % d == 0) {
-        const int qt = tid / d;
-        q = qt + i * (nthr / d);
-        r = tid - qt * d;
-    } else if (d % nthr == 0) {
-        const int c = d / nthr;
-        q = i / c;
-        r = tid + (i - q * c) * nthr;
-    } else {
-        const int b = tid + i * nthr;
-        q = fdiv(b, inv_d);
-        r = b - q * d;
-    }
-}
-
 // ---------------------------------------------------------------------------
-// Row pass, forward: lift + R2C along x, written transposed.
+// Single-image kernels: one workgroup per tile; the tile bodies are shared
+// with the batched kernels.
 // ---------------------------------------------------------------------------
-// A real row x[0..M) is transformed as the half-length complex sequence
-// z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
-//   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
-// grid: (M/ROWS row blocks, slice groups); block: nthr threads; LDS ROWS*H.
+// Row passes: grid (M/rows row blocks) x (slice groups) on a 1-D grid;
+// block: nthr threads; LDS: twiddles + rows x (H+2) (padded).
 template <class R, int SRC, int EPT, bool TWF, int MS>
 __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
                           const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
                           C2<R>* __restrict__ spec, int M_, int nslices, int slices_per_group,
                           int rows_, int xcd_pair, FftPlan planH, const C2<R>* __restrict__ twg) {
-    constexpr bool twfull = TWF;
-    // MS != 0: compiled for M = MS with the geometry geom_core<R>(MS)
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int rows = MS ? GC.rows : rows_;
-    extern __shared__ unsigned char smem_raw[];
-    const int M4 = M >> 2;
-    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + tw_elems(M, twfull);
-    const int H = M >> 1;
-    const int K = H + 1;
-    const int S = H + 2;  // LDS row stride: 8 rows of the transposed phase fall in distinct banks
-    const int tid = threadIdx.x;
     const int nthr = MS ? GC.row_threads : (int)blockDim.x;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + tw_elems(M, TWF);
     int rb, grp;
     row_block_of(M / rows, (nslices + slices_per_group - 1) / slices_per_group, xcd_pair != 0, rb, grp);
-    const int y0 = rb * rows;
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
-    const int nel = rows * H;
-    const float inv_H = 1.0f / (float)H;
-
-    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
-    // Lift sources are read once per block and kept in registers.
-    R fc0[EPT], fc1[EPT];
-    uint8_t rm0[EPT], rm1[EPT];
-    if (SRC != SRC_VOLUME) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * nthr;
-            fc0[i] = R(0);
-            fc1[i] = R(0);
-            rm0[i] = 0xff;
-            rm1[i] = 0xff;
-            if (e < nel) {
-                int row, n;
-                split_index(tid, i, nthr, H, inv_H, row, n);
-                const size_t p = (size_t)(y0 + row) * M + 2 * n;
-                const C2<R> fv = *reinterpret_cast<const C2<R>*>(f + p);
-                const uint16_t mv = *reinterpret_cast<const uint16_t*>(mask + p);
-                fc0[i] = (mv & 0xff) ? R(0) : fv.x;
-                fc1[i] = (mv >> 8) ? R(0) : fv.y;
-                if (SRC == SRC_LIFT) {
-                    const uint16_t rv = *reinterpret_cast<const uint16_t*>(rmap + p);
-                    rm0[i] = (uint8_t)(rv & 0xff);
-                    rm1[i] = (uint8_t)(rv >> 8);
-                }
-            }
-        }
-    }
-
-    for (int s = s_begin; s < s_end; ++s) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * nthr;
-            if (e < nel) {
-                C2<R> z;
-                if (SRC == SRC_VOLUME) {
-                    int row, n;
-                    split_index(tid, i, nthr, H, inv_H, row, n);
-                    z = *reinterpret_cast<const C2<R>*>(vol + ((size_t)s * M + y0 + row) * M + 2 * n);
-                } else if (SRC == SRC_LIFT) {
-                    z.x = (rm0[i] == s) ? fc0[i] : R(0);
-                    z.y = (rm1[i] == s) ? fc1[i] : R(0);
-                } else {
-                    z.x = fc0[i];
-                    z.y = fc1[i];
-                }
-                int row, n;
-                split_index(tid, i, nthr, H, inv_H, row, n);
-                buf[lds_pad(row * S + n)] = z;
-            }
-        }
-        __syncthreads();
-        if constexpr (MS != 0)
-            fft_static<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
-        else
-            fft_lds<R, false, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
-        // unpack the real transform and write (r, kx, y0..y0+rows) segments
-        const int nout = rows * K;
-        C2<R>* out = spec + (size_t)s * K * M + y0;
-        const int rshift = __ffs(rows) - 1;  // rows is a power of two
-        for (int e = tid; e < nout; e += nthr) {
-            const int kx = e >> rshift;
-            const int row = e & (rows - 1);
-            const C2<R> z1 = buf[lds_pad(row * S + (kx == H ? 0 : kx))];
-            const C2<R> z2 = buf[lds_pad(row * S + (kx == 0 ? 0 : H - kx))];
-            const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
-            // (z1 - conj z2)/(2i)
-            const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
-            const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
-            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R, TWF>(tw, kx, M4), od));
-        }
-        __syncthreads();
-    }
+    load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
+    row_fwd_tile<R, SRC, EPT, TWF, MS>(f, mask, rmap, vol, spec, M, rows, nthr, rb, s_begin, s_end, planH, tw,
+                                       buf, threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Column pass: FFT along y of `cols_per_block` contiguous columns of length M.
-// ---------------------------------------------------------------------------
+// Column pass: one tile of cols_per_block contiguous columns per workgroup.
 template <class R, bool INV, int EPT, bool TWF, int MS>
 __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M_, int cols_per_block_,
                           FftPlan planM, const C2<R>* __restrict__ twg) {
-    constexpr bool twfull = TWF;
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int cols_per_block = MS ? GC.cols : cols_per_block_;
-    extern __shared__ unsigned char smem_raw[];
-    const int M4 = M >> 2;
-    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + tw_elems(M, twfull);
-    const int tid = threadIdx.x;
     const int nthr = MS ? GC.col_threads : (int)blockDim.x;
-    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
-    const long c0 = (long)blockIdx.x * cols_per_block;
-    const int ncb = (int)min((long)cols_per_block, ncols - c0);
-    const int nel = ncb * M;
-    C2<R>* base = spec + c0 * M;
-    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
-    __syncthreads();
-    if constexpr (MS != 0) {
-        if (ncb == GC.cols) fft_static<R, INV, TWF, MS, GC.cols, MS, GC.col_threads, MS>(buf, tw, tid);
-        else fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
-    } else {
-        fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
-    }
-    for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + tw_elems(M, TWF);
+    load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
+    col_fft_tile<R, INV, EPT, TWF, MS>(spec, ncols, M, cols_per_block, nthr, (long)blockIdx.x * cols_per_block,
+                                      planM, tw, buf, threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Orientation: column FFT of the corrupted image's row spectrum F[kx][ky]
-// (slice 0), multiplication by the smoothed central-difference symbols and
-// inverse column FFTs.  Writes G_x into slice 0 and G_y into slice 1.
-//   G_x = F * i sqrt(M) s_kx g(kx) g(ky) / M^2,  G_y likewise with s_ky,
-//   s_k = sin(2 pi k/M), g(k) = exp(-2 pi^2 sigma^2 kbar^2 / M^2).
-// (The 1/M^2 only keeps magnitudes moderate; the angle ignores it.)
-// ---------------------------------------------------------------------------
 template <class R, int EPT, bool TWF>
 __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block, FftPlan planM,
                              const C2<R>* __restrict__ twg, R neg_two_pi2_sigma2_over_M2, R scale) {
-    constexpr bool twfull = TWF;
     extern __shared__ unsigned char smem_raw[];
-    const int M4 = M >> 2;
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + tw_elems(M, twfull);
-    const int H = M >> 1;
-    const int K = H + 1;
-    const int tid = threadIdx.x;
+    C2<R>* buf = tw + tw_elems(M, TWF);
     const int nthr = blockDim.x;
-    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
-    const int c0 = blockIdx.x * cols_per_block;
-    const int ncb = min(cols_per_block, K - c0);
-    const int nel = ncb * M;
-    C2<R>* gx = spec + (size_t)c0 * M;
-    C2<R>* gy = spec + ((size_t)K + c0) * M;
-    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = gx[e];
-    __syncthreads();
-    fft_lds<R, false, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
-    const float inv_M = 1.0f / (float)M;
-    for (int e = tid; e < nel; e += nthr) {
-        const int col = fdiv(e, inv_M);
-        const int ky = e - col * M;
-        const int kx = c0 + col;
-        const R skx = -tw_get<R, TWF>(tw, kx, M4).y;
-        const R sky = -tw_get<R, TWF>(tw, ky, M4).y;
-        const R kxb = (R)kx;                            // kx <= M/2; (M/2)^2 = (-M/2)^2
-        const R kyb = (R)(ky < H ? ky : ky - M);
-        const R g = exp(neg_two_pi2_sigma2_over_M2 * (kxb * kxb + kyb * kyb)) * scale;
-        const C2<R> F = buf[lds_pad(e)];
-        const C2<R> iF = cmk<R>(-F.y, F.x);
-        buf[lds_pad(e)] = cmk<R>(iF.x * skx * g, iF.y * skx * g);
-        buf[lds_pad(nel + e)] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
-    }
-    __syncthreads();
-    fft_lds<R, true, EPT, TWF>(buf, planM, 2 * ncb, M, tw, M4, tid, nthr);
-    for (int e = tid; e < nel; e += nthr) {
-        gx[e] = buf[lds_pad(e)];
-        gy[e] = buf[lds_pad(nel + e)];
-    }
+    load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
+    col_orient_tile<R, EPT, TWF>(spec, M, cols_per_block, nthr, blockIdx.x * cols_per_block, planM, tw, buf,
+                                 neg_two_pi2_sigma2_over_M2, scale, threadIdx.x);
 }
 
-// ---------------------------------------------------------------------------
-// Row pass, inverse: C2R along x from the transposed half spectrum, then
-// projection over the block's slices (max / sum), the real volume, or the
-// orientation binning (slices 0, 1 = g_x, g_y).
-// With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
-// the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
-// ---------------------------------------------------------------------------
 template <class R, int DST, int EPT, bool TWF, int MS>
 __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                           int M_, int nslices, int slices_per_group, int rows_, int xcd_pair, int N,
                           R out_scale, FftPlan planH, const C2<R>* __restrict__ twg) {
-    constexpr bool twfull = TWF;
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int rows = MS ? GC.rows : rows_;
-    extern __shared__ unsigned char smem_raw[];
-    const int M4 = M >> 2;
-    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
-    C2<R>* buf = tw + tw_elems(M, twfull);
-    const int H = M >> 1;
-    const int K = H + 1;
-    const int S = H + 2;  // LDS row stride: 8 rows of the transposed phase fall in distinct banks
-    const int tid = threadIdx.x;
     const int nthr = MS ? GC.row_threads : (int)blockDim.x;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + tw_elems(M, TWF);
     int rb, grp;
     row_block_of(M / rows, (nslices + slices_per_group - 1) / slices_per_group, xcd_pair != 0, rb, grp);
-    const int y0 = rb * rows;
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
-    const int nel = rows * H;
-    const float inv_H = 1.0f / (float)H;
-
-    load_twiddles<R>(tw, twg, M4, twfull, tid, nthr);
-    C2<R> acc[EPT], acc2[EPT];
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const R init = (DST == DST_MAX) ? -INFINITY : R(0);
-        acc[i] = cmk<R>(init, init);
-        acc2[i] = cmk<R>(R(0), R(0));
-    }
-
-    // The next slice's (kx, row) segments are loaded into registers while the
-    // current slice is transformed.  Thread t reads row t mod rows of columns
-    // kx = t/rows + i*kstep (rows and nthr are multiples of each other).
-    constexpr int MAXL = EPT + 2;
-    const int rshift = __ffs(rows) - 1;  // rows is a power of two
-    const int row_t = tid & (rows - 1);
-    const int kx_t = tid >> rshift;
-    const int kstep = nthr >> rshift;
-    C2<R> pre[MAXL];
-#define SE2N_FETCH(SL)                                                                      \
-    do {                                                                                   \
-        const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;    \
-        _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < K) pre[i] = \
-            in_[(size_t)(i * kstep) * M];                                                   \
-    } while (0)
-    SE2N_FETCH(s_begin);
-    for (int s = s_begin; s < s_end; ++s) {
-#pragma unroll
-        for (int i = 0; i < MAXL; ++i) {
-            const int kx = kx_t + i * kstep;
-            if (kx < K) buf[lds_pad(row_t * S + kx)] = pre[i];
-        }
-        __syncthreads();
-        if (s + 1 < s_end) SE2N_FETCH(s + 1);
-        // pairing step of the real inverse transform:
-        //   Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]),  k < H
-        const int npair = H / 2 + 1;
-        const float inv_npair = 1.0f / (float)npair;
-        for (int e = tid; e < rows * npair; e += nthr) {
-            const int row = fdiv(e, inv_npair);
-            const int k = e - row * npair;
-            const int kk = H - k;
-            const C2<R> a = buf[lds_pad(row * S + k)];
-            const C2<R> b = buf[lds_pad(row * S + kk)];
-            const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);      // a + conj b
-            const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);      // a - conj b
-            const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, TWF>(tw, k, M4)), da);
-            const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
-            const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
-            const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, TWF>(tw, kk, M4)), db);
-            buf[lds_pad(row * S + k)] = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
-            if (kk != k) buf[lds_pad(row * S + kk)] = cmk<R>(sb.x - tb.y, sb.y + tb.x);
-        }
-        __syncthreads();
-        if constexpr (MS != 0)
-            fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
-        else
-            fft_lds<R, true, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * nthr;
-            if (e < nel) {
-                int row, n;
-                split_index(tid, i, nthr, H, inv_H, row, n);
-                const C2<R> z = buf[lds_pad(row * S + n)];
-                if (DST == DST_VOLUME) {
-                    *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
-                        cmk<R>(z.x * out_scale, z.y * out_scale);
-                } else if (DST == DST_MAX) {
-                    acc[i].x = fmax(acc[i].x, z.x);
-                    acc[i].y = fmax(acc[i].y, z.y);
-                } else if (DST == DST_SUM) {
-                    acc[i].x += z.x;
-                    acc[i].y += z.y;
-                } else {  // DST_ORIENT
-                    if (s == 0) acc[i] = z;
-                    else acc2[i] = z;
-                }
-            }
-        }
-        __syncthreads();
-    }
-
-    if (DST == DST_VOLUME) return;
-#pragma unroll
-    for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * nthr;
-        if (e < nel) {
-            int row, n;
-            split_index(tid, i, nthr, H, inv_H, row, n);
-            const size_t p = (size_t)(y0 + row) * M + 2 * n;
-            if (DST == DST_MAX) {
-                if (enc) {
-                    atomicMax(enc + p, Enc<R>::encode(acc[i].x));
-                    atomicMax(enc + p + 1, Enc<R>::encode(acc[i].y));
-                } else {
-                    *reinterpret_cast<C2<R>*>(out + p) = acc[i];
-                }
-            } else if (DST == DST_SUM) {
-                *reinterpret_cast<C2<R>*>(out + p) = cmk<R>(acc[i].x * out_scale, acc[i].y * out_scale);
-            } else {  // orientation bins of pixels 2n and 2n+1
-                const R two_pi = R(6.283185307179586476925);
-                const R half_pi = R(1.570796326794896619231);
-                R t0 = (atan2(acc2[i].x, acc[i].x) + half_pi) * (R)N / two_pi + R(0.5);
-                R t1 = (atan2(acc2[i].y, acc[i].y) + half_pi) * (R)N / two_pi + R(0.5);
-                int b0 = (int)floor(t0) % N;
-                int b1 = (int)floor(t1) % N;
-                if (b0 < 0) b0 += N;
-                if (b1 < 0) b1 += N;
-                const uint16_t packed = (uint16_t)((unsigned)b0 | ((unsigned)b1 << 8));
-                *reinterpret_cast<uint16_t*>(rmap + p) = packed;
-            }
-        }
-    }
+    load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
+    row_inv_tile<R, DST, EPT, TWF, MS>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N, out_scale,
+                                       planH, tw, buf, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------

@@ -1,0 +1,535 @@
+// Workgroup-level bodies of the passes of one diffusion, shared by the
+// single-image kernels (one workgroup per tile, tile from blockIdx) and the
+// batched persistent kernels (each workgroup walks a list of tiles of many
+// images).  A body receives its tile, the image's sizes and the LDS twiddle
+// table already loaded; it leaves LDS free for the next tile only after the
+// caller's next barrier.
+//
+// Spectral layout (see the kernels file): spec[r][kx][ky], kx in [0, M/2],
+// ky in [0, M) contiguous.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "se2n_fft.hpp"
+#include "se2n_internal.hpp"
+
+namespace se2n {
+
+// (q, r) = divmod(tid + i*nthr, d) without a per-element division when nthr
+// is a multiple of d or d of nthr (uniform branches); inv_d = 1/d in float.
+__device__ __forceinline__ void split_index(int tid, int i, int nthr, int d, float inv_d, int& q, int& r) {
+    if (nthr % d == 0) {
+        const int qt = tid / d;
+        q = qt + i * (nthr / d);
+        r = tid - qt * d;
+    } else if (d % nthr == 0) {
+        const int b = tid + i * nthr;
+        const int per = d / nthr;
+        q = i / per;
+        r = b - q * d;
+    } else {
+        const int b = tid + i * nthr;
+        q = fdiv(b, inv_d);
+        r = b - q * d;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, forward: lift + R2C along x of `rows` image rows starting at
+// y0 = rb*rows, for slices [s_begin, s_end), written transposed.
+// ---------------------------------------------------------------------------
+// A real row x[0..M) is transformed as the half-length complex sequence
+// z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
+//   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
+// MS != 0: compiled for M = MS with the geometry geom_core<R>(MS).
+template <class R, int SRC, int EPT, bool TWF, int MS>
+__device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint8_t* __restrict__ mask,
+                                             const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
+                                             C2<R>* __restrict__ spec, int M_, int rows_, int nthr_, int rb,
+                                             int s_begin, int s_end, const FftPlan& planH, const C2<R>* tw,
+                                             C2<R>* buf, int tid) {
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int rows = MS ? GC.rows : rows_;
+    const int nthr = MS ? GC.row_threads : nthr_;
+    const int M4 = M >> 2;
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int S = H + 2;  // LDS row stride: 8 rows of the transposed phase fall in distinct banks
+    const int y0 = rb * rows;
+    const int nel = rows * H;
+    const float inv_H = 1.0f / (float)H;
+
+    // Lift sources are read once per tile and kept in registers.
+    R fc0[EPT], fc1[EPT];
+    uint8_t rm0[EPT], rm1[EPT];
+    if (SRC != SRC_VOLUME) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * nthr;
+            fc0[i] = R(0);
+            fc1[i] = R(0);
+            rm0[i] = 0xff;
+            rm1[i] = 0xff;
+            if (e < nel) {
+                int row, n;
+                split_index(tid, i, nthr, H, inv_H, row, n);
+                const size_t p = (size_t)(y0 + row) * M + 2 * n;
+                const C2<R> fv = *reinterpret_cast<const C2<R>*>(f + p);
+                const uint16_t mv = *reinterpret_cast<const uint16_t*>(mask + p);
+                fc0[i] = (mv & 0xff) ? R(0) : fv.x;
+                fc1[i] = (mv >> 8) ? R(0) : fv.y;
+                if (SRC == SRC_LIFT) {
+                    const uint16_t rv = *reinterpret_cast<const uint16_t*>(rmap + p);
+                    rm0[i] = (uint8_t)(rv & 0xff);
+                    rm1[i] = (uint8_t)(rv >> 8);
+                }
+            }
+        }
+    }
+
+    for (int s = s_begin; s < s_end; ++s) {
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * nthr;
+            if (e < nel) {
+                C2<R> z;
+                if (SRC == SRC_VOLUME) {
+                    int row, n;
+                    split_index(tid, i, nthr, H, inv_H, row, n);
+                    z = *reinterpret_cast<const C2<R>*>(vol + ((size_t)s * M + y0 + row) * M + 2 * n);
+                } else if (SRC == SRC_LIFT) {
+                    z.x = (rm0[i] == s) ? fc0[i] : R(0);
+                    z.y = (rm1[i] == s) ? fc1[i] : R(0);
+                } else {
+                    z.x = fc0[i];
+                    z.y = fc1[i];
+                }
+                int row, n;
+                split_index(tid, i, nthr, H, inv_H, row, n);
+                buf[lds_pad(row * S + n)] = z;
+            }
+        }
+        __syncthreads();
+        if constexpr (MS != 0)
+            fft_static<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
+        else
+            fft_lds<R, false, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
+        // unpack the real transform and write (r, kx, y0..y0+rows) segments
+        const int nout = rows * K;
+        C2<R>* out = spec + (size_t)s * K * M + y0;
+        const int rshift = __ffs(rows) - 1;  // rows is a power of two
+        for (int e = tid; e < nout; e += nthr) {
+            const int kx = e >> rshift;
+            const int row = e & (rows - 1);
+            const C2<R> z1 = buf[lds_pad(row * S + (kx == H ? 0 : kx))];
+            const C2<R> z2 = buf[lds_pad(row * S + (kx == 0 ? 0 : H - kx))];
+            const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
+            // (z1 - conj z2)/(2i)
+            const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
+            const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
+            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R, TWF>(tw, kx, M4), od));
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Column pass: FFT along y of the columns [c0, c0 + ncb) (each M contiguous
+// values), ncb = min(cols_per_tile, ncols - c0).
+// ---------------------------------------------------------------------------
+template <class R, bool INV, int EPT, bool TWF, int MS>
+__device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncols, int M_, int cols_,
+                                             int nthr_, long c0, const FftPlan& planM, const C2<R>* tw,
+                                             C2<R>* buf, int tid) {
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int cols_per_tile = MS ? GC.cols : cols_;
+    const int nthr = MS ? GC.col_threads : nthr_;
+    const int M4 = M >> 2;
+    const int ncb = (int)min((long)cols_per_tile, ncols - c0);
+    const int nel = ncb * M;
+    C2<R>* base = spec + c0 * M;
+    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
+    __syncthreads();
+    if constexpr (MS != 0) {
+        if (ncb == GC.cols) fft_static<R, INV, TWF, MS, GC.cols, MS, GC.col_threads, MS>(buf, tw, tid);
+        else fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    } else {
+        fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    }
+    for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
+}
+
+// ---------------------------------------------------------------------------
+// Orientation: column FFT of the corrupted image's row spectrum F[kx][ky]
+// (slice 0) for kx in [c0, c0 + ncb), multiplication by the smoothed
+// central-difference symbols and inverse column FFTs.  Writes G_x into
+// slice 0 and G_y into slice 1.
+//   G_x = F * i sqrt(M) s_kx g(kx) g(ky) / M^2,  G_y likewise with s_ky,
+//   s_k = sin(2 pi k/M), g(k) = exp(-2 pi^2 sigma^2 kbar^2 / M^2).
+// (The 1/M^2 only keeps magnitudes moderate; the angle ignores it.)
+// ---------------------------------------------------------------------------
+template <class R, int EPT, bool TWF>
+__device__ __forceinline__ void col_orient_tile(C2<R>* __restrict__ spec, int M, int cols_per_tile, int nthr,
+                                                int c0, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
+                                                R neg_two_pi2_sigma2_over_M2, R scale, int tid) {
+    const int M4 = M >> 2;
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int ncb = min(cols_per_tile, K - c0);
+    const int nel = ncb * M;
+    C2<R>* gx = spec + (size_t)c0 * M;
+    C2<R>* gy = spec + ((size_t)K + c0) * M;
+    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = gx[e];
+    __syncthreads();
+    fft_lds<R, false, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    const float inv_M = 1.0f / (float)M;
+    for (int e = tid; e < nel; e += nthr) {
+        const int col = fdiv(e, inv_M);
+        const int ky = e - col * M;
+        const int kx = c0 + col;
+        const R skx = -tw_get<R, TWF>(tw, kx, M4).y;
+        const R sky = -tw_get<R, TWF>(tw, ky, M4).y;
+        const R kxb = (R)kx;  // kx <= M/2; (M/2)^2 = (-M/2)^2
+        const R kyb = (R)(ky < H ? ky : ky - M);
+        const R g = exp(neg_two_pi2_sigma2_over_M2 * (kxb * kxb + kyb * kyb)) * scale;
+        const C2<R> F = buf[lds_pad(e)];
+        const C2<R> iF = cmk<R>(-F.y, F.x);
+        buf[lds_pad(e)] = cmk<R>(iF.x * skx * g, iF.y * skx * g);
+        buf[lds_pad(nel + e)] = cmk<R>(iF.x * sky * g, iF.y * sky * g);
+    }
+    __syncthreads();
+    fft_lds<R, true, EPT, TWF>(buf, planM, 2 * ncb, M, tw, M4, tid, nthr);
+    for (int e = tid; e < nel; e += nthr) {
+        gx[e] = buf[lds_pad(e)];
+        gy[e] = buf[lds_pad(nel + e)];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Row pass, inverse: C2R along x of rows y0 = rb*rows .. y0+rows from the
+// transposed half spectrum of slices [s_begin, s_end), then projection over
+// those slices (max / sum), the real volume, or the orientation binning
+// (slices 0, 1 = g_x, g_y).  DST_MAX combines slice groups through `enc`
+// (order-preserving integer atomics) when it is not null, else writes `out`.
+// With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
+// the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
+// ---------------------------------------------------------------------------
+template <class R, int DST, int EPT, bool TWF, int MS>
+__device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* __restrict__ out,
+                                             typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
+                                             int M_, int rows_, int nthr_, int rb, int s_begin, int s_end, int N,
+                                             R out_scale, const FftPlan& planH, const C2<R>* tw, C2<R>* buf,
+                                             int tid) {
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int rows = MS ? GC.rows : rows_;
+    const int nthr = MS ? GC.row_threads : nthr_;
+    const int M4 = M >> 2;
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int S = H + 2;  // LDS row stride: 8 rows of the transposed phase fall in distinct banks
+    const int y0 = rb * rows;
+    const int nel = rows * H;
+    const float inv_H = 1.0f / (float)H;
+
+    C2<R> acc[EPT], acc2[EPT];
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const R init = (DST == DST_MAX) ? -INFINITY : R(0);
+        acc[i] = cmk<R>(init, init);
+        acc2[i] = cmk<R>(R(0), R(0));
+    }
+
+    // The next slice's (kx, row) segments are loaded into registers while the
+    // current slice is transformed.  Thread t reads row t mod rows of columns
+    // kx = t/rows + i*kstep (rows and nthr are multiples of each other).
+    constexpr int MAXL = EPT + 2;
+    const int rshift = __ffs(rows) - 1;  // rows is a power of two
+    const int row_t = tid & (rows - 1);
+    const int kx_t = tid >> rshift;
+    const int kstep = nthr >> rshift;
+    C2<R> pre[MAXL];
+#define SE2N_FETCH(SL)                                                                      \
+    do {                                                                                   \
+        const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;    \
+        _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < K) pre[i] = \
+            in_[(size_t)(i * kstep) * M];                                                   \
+    } while (0)
+    SE2N_FETCH(s_begin);
+    for (int s = s_begin; s < s_end; ++s) {
+#pragma unroll
+        for (int i = 0; i < MAXL; ++i) {
+            const int kx = kx_t + i * kstep;
+            if (kx < K) buf[lds_pad(row_t * S + kx)] = pre[i];
+        }
+        __syncthreads();
+        if (s + 1 < s_end) SE2N_FETCH(s + 1);
+        // pairing step of the real inverse transform:
+        //   Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]),  k < H
+        const int npair = H / 2 + 1;
+        const float inv_npair = 1.0f / (float)npair;
+        for (int e = tid; e < rows * npair; e += nthr) {
+            const int row = fdiv(e, inv_npair);
+            const int k = e - row * npair;
+            const int kk = H - k;
+            const C2<R> a = buf[lds_pad(row * S + k)];
+            const C2<R> b = buf[lds_pad(row * S + kk)];
+            const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
+            const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
+            const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, TWF>(tw, k, M4)), da);
+            const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
+            const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
+            const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, TWF>(tw, kk, M4)), db);
+            buf[lds_pad(row * S + k)] = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
+            if (kk != k) buf[lds_pad(row * S + kk)] = cmk<R>(sb.x - tb.y, sb.y + tb.x);
+        }
+        __syncthreads();
+        if constexpr (MS != 0)
+            fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
+        else
+            fft_lds<R, true, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
+#pragma unroll
+        for (int i = 0; i < EPT; ++i) {
+            const int e = tid + i * nthr;
+            if (e < nel) {
+                int row, n;
+                split_index(tid, i, nthr, H, inv_H, row, n);
+                const C2<R> z = buf[lds_pad(row * S + n)];
+                if (DST == DST_VOLUME) {
+                    *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
+                        cmk<R>(z.x * out_scale, z.y * out_scale);
+                } else if (DST == DST_MAX) {
+                    acc[i].x = fmax(acc[i].x, z.x);
+                    acc[i].y = fmax(acc[i].y, z.y);
+                } else if (DST == DST_SUM) {
+                    acc[i].x += z.x;
+                    acc[i].y += z.y;
+                } else {  // DST_ORIENT
+                    if (s == 0) acc[i] = z;
+                    else acc2[i] = z;
+                }
+            }
+        }
+        __syncthreads();
+    }
+#undef SE2N_FETCH
+
+    if (DST == DST_VOLUME) return;
+#pragma unroll
+    for (int i = 0; i < EPT; ++i) {
+        const int e = tid + i * nthr;
+        if (e < nel) {
+            int row, n;
+            split_index(tid, i, nthr, H, inv_H, row, n);
+            const size_t p = (size_t)(y0 + row) * M + 2 * n;
+            if (DST == DST_MAX) {
+                if (enc) {
+                    atomicMax(enc + p, Enc<R>::encode(acc[i].x));
+                    atomicMax(enc + p + 1, Enc<R>::encode(acc[i].y));
+                } else {
+                    *reinterpret_cast<C2<R>*>(out + p) = acc[i];
+                }
+            } else if (DST == DST_SUM) {
+                *reinterpret_cast<C2<R>*>(out + p) = cmk<R>(acc[i].x * out_scale, acc[i].y * out_scale);
+            } else {  // orientation bins of pixels 2n and 2n+1
+                const R two_pi = R(6.283185307179586476925);
+                const R half_pi = R(1.570796326794896619231);
+                R t0 = (atan2(acc2[i].x, acc[i].x) + half_pi) * (R)N / two_pi + R(0.5);
+                R t1 = (atan2(acc2[i].y, acc[i].y) + half_pi) * (R)N / two_pi + R(0.5);
+                int b0 = (int)floor(t0) % N;
+                int b1 = (int)floor(t1) % N;
+                if (b0 < 0) b0 += N;
+                if (b1 < 0) b1 += N;
+                const uint16_t packed = (uint16_t)((unsigned)b0 | ((unsigned)b1 << 8));
+                *reinterpret_cast<uint16_t*>(rmap + p) = packed;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Per-mode solve: psi_hat(kx,ky) <- P(kx,ky) psi_hat(kx,ky).
+// ---------------------------------------------------------------------------
+// The potential M (cos e_r s_kx + sin e_r s_ky)^2 has period N/2 in r, so in
+// the basis p_j = x_j + x_{j+N/2}, q_j = x_j - x_{j+N/2} (j < N/2) the N x N
+// propagator is two symmetric N/2 x N/2 blocks (periodic and antiperiodic
+// coupling).  The table holds, per frequency class (lx, ly) with
+// |s_kx| = sin(2 pi lx/M), |s_ky| = sin(2 pi ly/M), lx, ly in [0, M/4], the
+// packed upper triangles of both blocks, scaled by 1/(2 M^2), laid out as
+// P[lx][element][ly] with a line-aligned ly stride.
+//
+// The members of class (lx, ly) in the half spectrum are kx in {lx, M/2-lx}
+// and ky in {ly, M/2-ly, M/2+ly, M-ly}.  Where s_kx s_ky < 0 (ky > M/2) the
+// potential is the class potential with r -> -r, so the propagator is the
+// class one conjugated by that permutation: the kernel loads and stores
+// through the mirrored orientation index.
+//
+// A workgroup takes one lx and CLS consecutive ly, stages their propagators
+// in LDS once (a contiguous row of CLS values per element), and applies them
+// to all 8 members of each class.  Each mode is handled by a pair of adjacent
+// lanes: the even lane loads x_j and the odd lane x_{j+N/2} (j < N/2); one
+// DPP swap gives the even lane p = x_j + x_{j+N/2} and the odd lane
+// q = x_j - x_{j+N/2}; each applies its block (periodic / antiperiodic) and a
+// second swap forms x'_j = y_p + y_q (even) and x'_{j+N/2} = y_p - y_q (odd).
+// A wavefront covers one member for 32 consecutive classes, i.e. 32
+// consecutive (or reversed) ky of one column per orientation plane.
+__device__ __forceinline__ float swap_pair(float v) {
+    // lanes (0,1)(2,3)...: quad_perm [1,0,3,2]
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
+}
+__device__ __forceinline__ double swap_pair(double v) {
+    const long long u = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)(u & 0xffffffff), 0xB1, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(u >> 32), 0xB1, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+template <class R, int N, int CLS>
+__device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q,
+                                           int Qs, int lx, int ly0, R* Ps, int tid) {
+    constexpr int h = N / 2;
+    constexpr int Eh = h * (h + 1) / 2;
+    constexpr int E = 2 * Eh;
+    const int H = M >> 1;
+    constexpr int NT = 16 * CLS < 512 ? 16 * CLS : 512;  // blockDim.x: two lanes per mode
+    const int nthr = NT;
+    const int ncls = min(CLS, Q - ly0);
+    // Stage the block's propagators: 16-byte chunks, every load of a thread
+    // issued before the first is waited on.  A chunk that starts inside the
+    // block's classes lies inside the line-padded row; classes past the last
+    // one are zeroed.
+    {
+        constexpr int VEC = 16 / (int)sizeof(R);
+        typedef R vec_t __attribute__((ext_vector_type(VEC)));
+        constexpr int CH = E * CLS / VEC;  // CLS >= 8 is a multiple of VEC
+        constexpr int NST = (CH + NT - 1) / NT;
+        constexpr int BATCH = NST < 8 ? NST : 8;  // loads in flight per thread
+        const R* __restrict__ src = P + (size_t)lx * E * Qs + ly0;
+        for (int k0 = 0; k0 < NST; k0 += BATCH) {
+        vec_t v[BATCH];
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int i = tid + (k0 + k) * NT;
+            const int e = i / (CLS / VEC);
+            const int c0 = (i - e * (CLS / VEC)) * VEC;
+            v[k] = vec_t(0);
+            if (i < CH && c0 < ncls) v[k] = *reinterpret_cast<const vec_t*>(src + (size_t)e * Qs + c0);
+#pragma unroll
+            for (int q = 0; q < VEC; ++q)
+                if (c0 + q >= ncls) v[k][q] = R(0);
+        }
+#pragma unroll
+        for (int k = 0; k < BATCH; ++k) {
+            const int i = tid + (k0 + k) * NT;
+            if (i < CH) reinterpret_cast<vec_t*>(Ps)[i] = v[k];
+        }
+        }
+    }
+    __syncthreads();
+    const size_t plane = (size_t)(H + 1) * M;
+    const int odd = tid & 1;
+    // A wavefront holds 32 pairs; with CLS >= 32 they all belong to one member,
+    // so the member, its column kx and its orientation mirroring are uniform
+    // across the wavefront and the plane addresses live in scalar registers.
+    constexpr bool UNIFORM = CLS >= 32;
+    // every lane of a pair runs the same iterations, so the swaps always meet
+#pragma unroll 1
+    for (int pair = tid >> 1; pair < 8 * CLS; pair += nthr >> 1) {
+        int m = pair / CLS;
+        if (UNIFORM) m = __builtin_amdgcn_readfirstlane(m);
+        const int c = pair - m * CLS;
+        const int ly = ly0 + c;
+        const int a = m >> 2;
+        const int b = m & 3;
+        bool live = c < ncls;
+        live = live && !(a == 1 && 2 * lx == H);           // kx = M/4 is its own mirror
+        live = live && !(ly == 0 && b >= 2);               // ky in {0, M/2} only
+        live = live && !(2 * ly == H && (b & 1));          // ky in {M/4, 3M/4} only
+        const int kx = a ? H - lx : lx;
+        int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
+        if (!live) ky = 0;  // harmless in-range address; nothing is stored
+        // s_ky < 0 exactly for the live members b = 2, 3 (ky in (M/2, M))
+        const bool perm = b >= 2;
+        C2<R>* colbase = spec + (size_t)kx * M;
+        const R* Pc = Ps + (size_t)odd * Eh * CLS + c;
+
+        // this lane's half of the orientation vector (every address is valid;
+        // dead lanes read row 0 and discard it)
+        C2<R> x[h];
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const int r0 = j, r1 = j + h;
+            const int a0 = perm ? (r0 == 0 ? 0 : N - r0) : r0;
+            const int a1 = perm ? N - r1 : r1;
+            const C2<R>* pl0 = colbase + (size_t)a0 * plane;  // wave-uniform
+            const C2<R>* pl1 = colbase + (size_t)a1 * plane;
+            const C2<R> v = odd ? pl1[ky] : pl0[ky];
+            x[j].x = live ? v.x : R(0);
+            x[j].y = live ? v.y : R(0);
+        }
+        // even lane: p = x_j + x_{j+h};  odd lane: q = x_j - x_{j+h}
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const R ox = swap_pair(x[j].x);
+            const R oy = swap_pair(x[j].y);
+            x[j] = odd ? cmk<R>(ox - x[j].x, oy - x[j].y) : cmk<R>(x[j].x + ox, x[j].y + oy);
+        }
+        C2<R> y[h];
+#pragma unroll
+        for (int j = 0; j < h; ++j) y[j] = cmk<R>(R(0), R(0));
+        {
+            int e = 0;
+#pragma unroll
+            for (int i = 0; i < h; ++i) {
+#pragma unroll
+                for (int j = i; j < h; ++j) {
+                    const R w = Pc[e * CLS];
+                    y[i].x += w * x[j].x;
+                    y[i].y += w * x[j].y;
+                    if (j != i) {
+                        y[j].x += w * x[i].x;
+                        y[j].y += w * x[i].y;
+                    }
+                    ++e;
+                }
+                // keep each row's LDS reads next to their use (bounded registers)
+                __builtin_amdgcn_sched_barrier(0);
+            }
+        }
+        // even lane: y_p + y_q -> x'_j;  odd lane: y_p - y_q -> x'_{j+h}
+#pragma unroll
+        for (int j = 0; j < h; ++j) {
+            const R ox = swap_pair(y[j].x);
+            const R oy = swap_pair(y[j].y);
+            y[j] = odd ? cmk<R>(ox - y[j].x, oy - y[j].y) : cmk<R>(y[j].x + ox, y[j].y + oy);
+        }
+        if (live) {
+#pragma unroll
+            for (int j = 0; j < h; ++j) {
+                const int r0 = j, r1 = j + h;
+                const int a0 = perm ? (r0 == 0 ? 0 : N - r0) : r0;
+                const int a1 = perm ? N - r1 : r1;
+                C2<R>* pl = colbase + (size_t)(odd ? a1 : a0) * plane;
+                pl[ky] = y[j];
+            }
+        }
+    }
+}
+
+// Classes per tile: the largest power of two <= 64 whose propagators fit in
+// 72 KB of LDS.
+template <class R, int N>
+constexpr int solve_cls() {
+    constexpr int h = N / 2;
+    constexpr int E = h * (h + 1);
+    int c = 64;
+    while (c > 1 && (long)E * c * (long)sizeof(R) > 72 * 1024) c >>= 1;
+    return c;
+}
+
+}  // namespace se2n

@@ -15,10 +15,11 @@
 
 #include "../../include/se2n.h"
 #include "se2n_internal.hpp"
+#include "se2n_host.hpp"
 
 using namespace se2n;
 
-namespace {
+namespace se2n {
 
 thread_local std::string g_last_error;
 
@@ -36,11 +37,7 @@ int hip_fail(hipError_t e, const char* what) {
     return fail(SE2N_EHIP, "%s: %s", what, hipGetErrorString(e));
 }
 
-#define SE2N_HIP(call, what)                          \
-    do {                                              \
-        hipError_t e_ = (call);                       \
-        if (e_ != hipSuccess) return hip_fail(e_, what); \
-    } while (0)
+void clear_error() { g_last_error.clear(); }
 
 bool is_2a3b(int M, int* twos, int* threes) {
     int a = 0, b = 0, m = M;
@@ -86,6 +83,26 @@ FftPlan make_fft_plan(int L, int M) {
     return p;
 }
 
+// Quarter table w_M^m = exp(-2 pi i m / M), m in [0, M/4], evaluated in
+// extended precision before rounding to R.
+template <class R>
+std::vector<C2<R>> quarter_twiddles(int M) {
+    const int n = M / 4 + 1;
+    std::vector<C2<R>> h(n);
+    for (int m = 0; m < n; ++m) {
+        const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)M;
+        h[m].x = (R)(double)cosl(a);
+        h[m].y = (R)(double)(-sinl(a));
+    }
+    return h;
+}
+template std::vector<C2<float>> quarter_twiddles<float>(int);
+template std::vector<C2<double>> quarter_twiddles<double>(int);
+
+}  // namespace se2n
+
+namespace {
+
 struct CacheKey {
     double T, beta;
     int n, scheme;
@@ -100,8 +117,6 @@ struct CacheEntry {
     void* dptr;
     size_t bytes;
 };
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -413,20 +428,11 @@ int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_s
     return SE2N_OK;
 }
 
-// Quarter table w_M^m = exp(-2 pi i m / M), m in [0, M/4], evaluated in
-// extended precision before rounding to the plan dtype.
 template <class R>
 int make_twiddles(se2n_plan p) {
-    const int M = p->M;
-    const int n = M / 4 + 1;
-    std::vector<C2<R>> h(n);
-    for (int m = 0; m < n; ++m) {
-        const long double a = 2.0L * 3.141592653589793238462643383279502884L * (long double)m / (long double)M;
-        h[m].x = (R)(double)cosl(a);
-        h[m].y = (R)(double)(-sinl(a));
-    }
-    SE2N_HIP(hipMalloc(&p->tw, (size_t)n * sizeof(C2<R>)), "hipMalloc twiddles");
-    SE2N_HIP(hipMemcpy(p->tw, h.data(), (size_t)n * sizeof(C2<R>), hipMemcpyHostToDevice), "twiddle upload");
+    const std::vector<C2<R>> h = quarter_twiddles<R>(p->M);
+    SE2N_HIP(hipMalloc(&p->tw, h.size() * sizeof(C2<R>)), "hipMalloc twiddles");
+    SE2N_HIP(hipMemcpy(p->tw, h.data(), h.size() * sizeof(C2<R>), hipMemcpyHostToDevice), "twiddle upload");
     return SE2N_OK;
 }
 

@@ -198,3 +198,135 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+
+# ---------------------------------------------------------------------------
+# Batched inpainting (FP32)
+# ---------------------------------------------------------------------------
+class _Item(ctypes.Structure):
+    _fields_ = [("M", _i), ("N", _i), ("n_steps", _i), ("scheme", _i), ("proj", _i), ("reserved", _i),
+                ("T", _d), ("beta", _d), ("sigma", _d),
+                ("f", _vp), ("mask", _vp), ("rmap_out", _vp), ("out", _vp)]
+
+
+class _Tune(ctypes.Structure):
+    _fields_ = [("wg_per_cu", _i), ("order", _i), ("row_groups", _i), ("reserved", _i)]
+
+
+_IP = ctypes.POINTER(_Item)
+_TP = ctypes.POINTER(_Tune)
+_lib.se2n_batch_workspace_bytes.argtypes = [_IP, _i]
+_lib.se2n_batch_workspace_bytes.restype = ctypes.c_size_t
+_lib.se2n_inpaint_batched.argtypes = [_IP, _i, _vp, _vp]
+_lib.se2n_batch_autotune.argtypes = [_IP, _i, _vp, _vp, _i, ctypes.c_char_p, _TP, ctypes.POINTER(_d)]
+_lib.se2n_batch_load_tune_table.argtypes = [ctypes.c_char_p]
+_lib.se2n_batch_set_tune.argtypes = [_IP, _i, _TP]
+_lib.se2n_batch_get_tune.argtypes = [_IP, _i, _TP]
+_lib.se2n_batch_tiles.argtypes = [_IP, _i, _TP, _i, ctypes.POINTER(_i), _i, ctypes.POINTER(_i)]
+_lib.se2n_batch_profile.argtypes = [_i]
+_lib.se2n_batch_profile_stats.argtypes = [ctypes.POINTER(KernelStat), _i, ctypes.POINTER(_i)]
+for _name in ("se2n_inpaint_batched", "se2n_batch_autotune", "se2n_batch_load_tune_table", "se2n_batch_set_tune",
+              "se2n_batch_get_tune", "se2n_batch_tiles", "se2n_batch_profile", "se2n_batch_profile_stats",
+              "se2n_batch_clear"):
+    getattr(_lib, _name).restype = _i
+
+
+class BatchItem:
+    """One image of a batched inpaint: float32 f and uint8 mask of shape (M, M) on one device.
+
+    out / rmap_out are allocated when not given."""
+
+    def __init__(self, f: torch.Tensor, mask: torch.Tensor, N: int, T: float, beta: float, n_steps: int,
+                 sigma: float = 2.0, scheme: str = "cn", proj: str = "max", out: torch.Tensor | None = None,
+                 rmap_out: torch.Tensor | None = None):
+        M = f.shape[0]
+        for name, t, dt in (("f", f, torch.float32), ("mask", mask, torch.uint8)):
+            if t.dtype != dt or tuple(t.shape) != (M, M) or not t.is_contiguous() or t.device.type != "cuda":
+                raise ValueError(f"{name} must be a contiguous {dt} CUDA tensor of shape ({M}, {M})")
+        self.f, self.mask = f, mask
+        self.M, self.N, self.T, self.beta, self.n_steps = int(M), int(N), float(T), float(beta), int(n_steps)
+        self.sigma, self.scheme, self.proj = float(sigma), scheme, proj
+        self.out = out if out is not None else torch.empty((M, M), dtype=torch.float32, device=f.device)
+        self.rmap_out = rmap_out if rmap_out is not None else torch.empty((M, M), dtype=torch.uint8, device=f.device)
+        for name, t, dt in (("out", self.out, torch.float32), ("rmap_out", self.rmap_out, torch.uint8)):
+            if t.dtype != dt or tuple(t.shape) != (M, M) or not t.is_contiguous() or t.device != f.device:
+                raise ValueError(f"{name} must be a contiguous {dt} tensor of shape ({M}, {M}) on {f.device}")
+
+    def _c(self) -> _Item:
+        return _Item(self.M, self.N, self.n_steps, _SCHEMES[self.scheme], _PROJ[self.proj], 0,
+                     self.T, self.beta, self.sigma, _ptr(self.f), _ptr(self.mask), _ptr(self.rmap_out),
+                     _ptr(self.out))
+
+
+def _items(items) -> tuple:
+    arr = (_Item * len(items))(*[it._c() for it in items])
+    return arr, len(items)
+
+
+def _tune_dict(t: _Tune) -> dict:
+    return {"wg_per_cu": t.wg_per_cu, "order": t.order, "row_groups": t.row_groups}
+
+
+def batch_workspace_bytes(items) -> int:
+    arr, n = _items(items)
+    b = int(_lib.se2n_batch_workspace_bytes(arr, n))
+    if b == 0:
+        raise Se2nError(-1, _lib.se2n_last_error().decode())
+    return b
+
+
+def batch_workspace(items) -> torch.Tensor:
+    return torch.empty(batch_workspace_bytes(items), dtype=torch.uint8, device=items[0].f.device)
+
+
+def inpaint_batched(items, workspace: torch.Tensor | None = None) -> list:
+    """Inpaint every item with one graph launch; returns [item.out]."""
+    arr, n = _items(items)
+    ws = workspace if workspace is not None else batch_workspace(items)
+    _check(_lib.se2n_inpaint_batched(arr, n, _ptr(ws), _vp(_stream())))
+    return [it.out for it in items]
+
+
+def batch_autotune(items, workspace: torch.Tensor | None = None, reps: int = 3,
+                   table_path: str | None = None) -> tuple:
+    """Time the candidate schedules, keep the fastest; returns (tune dict, ms per batch)."""
+    arr, n = _items(items)
+    ws = workspace if workspace is not None else batch_workspace(items)
+    t, ms = _Tune(), _d()
+    _check(_lib.se2n_batch_autotune(arr, n, _ptr(ws), _vp(_stream()), int(reps),
+                                    None if table_path is None else table_path.encode(), ctypes.byref(t),
+                                    ctypes.byref(ms)))
+    return _tune_dict(t), ms.value
+
+
+def batch_set_tune(items, wg_per_cu: int, order: int, row_groups: int) -> None:
+    arr, n = _items(items)
+    t = _Tune(int(wg_per_cu), int(order), int(row_groups), 0)
+    _check(_lib.se2n_batch_set_tune(arr, n, ctypes.byref(t)))
+
+
+def batch_get_tune(items) -> dict:
+    arr, n = _items(items)
+    t = _Tune()
+    _check(_lib.se2n_batch_get_tune(arr, n, ctypes.byref(t)))
+    return _tune_dict(t)
+
+
+def batch_load_tune_table(path: str) -> None:
+    _check(_lib.se2n_batch_load_tune_table(path.encode()))
+
+
+def batch_profile(enable: bool = True) -> None:
+    _check(_lib.se2n_batch_profile(1 if enable else 0))
+
+
+def batch_profile_stats() -> dict:
+    n = _i(0)
+    _check(_lib.se2n_batch_profile_stats(None, 0, ctypes.byref(n)))
+    arr = (KernelStat * max(n.value, 1))()
+    _check(_lib.se2n_batch_profile_stats(arr, n.value, ctypes.byref(n)))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+
+def batch_clear() -> None:
+    _check(_lib.se2n_batch_clear())

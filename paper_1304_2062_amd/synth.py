@@ -27,6 +27,9 @@ __all__ = [
     "mask_stripes",
     "mask_blotches",
     "make_case",
+    "BATCH_SIDES",
+    "batch_params",
+    "make_batch",
 ]
 
 
@@ -245,3 +248,35 @@ def make_case(name: str, seed: int | None = None, M: int | None = None) -> dict:
     else:
         raise ValueError(f"unknown case {name!r}")
     return dict(name=name, seed=seed, M=M, f=img, mask=mask.astype(np.uint8), sigma=2.0, **params)
+
+
+# Sides of the heterogeneous batch workload (all 2^a 3^b, a >= 3).
+BATCH_SIDES = (128, 192, 256, 384, 512, 768, 1024)
+
+
+def batch_params(count: int = 64, seed0: int = 1000, sides=BATCH_SIDES, Ns=(16, 24, 32),
+                 tau: float = 0.01) -> list[dict]:
+    """Parameters of a heterogeneous batch, image i drawn with seed seed0 + i:
+    M uniform over ``sides``, N uniform over ``Ns``, T ~ U[0.5, 4], n_steps =
+    round(T / tau), beta = 1, loss rate rho ~ U(0.5, 0.85)."""
+    out = []
+    for i in range(count):
+        rng = _rng(seed0 + i)
+        M = int(sides[rng.integers(len(sides))])
+        N = int(Ns[rng.integers(len(Ns))])
+        T = float(rng.uniform(0.5, 4.0))
+        rho = float(rng.uniform(0.5, 0.85))
+        out.append(dict(seed=seed0 + i, M=M, N=N, T=T, n_steps=max(1, int(round(T / tau))), beta=1.0,
+                        rho=rho, sigma=2.0))
+    return out
+
+
+def make_batch(count: int = 64, seed0: int = 1000, sides=BATCH_SIDES, Ns=(16, 24, 32),
+               tau: float = 0.01) -> list[dict]:
+    """``batch_params`` plus each image (the medium recipe) and its Bernoulli(rho) mask."""
+    out = []
+    for p in batch_params(count, seed0, sides, Ns, tau):
+        img = make_image(p["seed"], p["M"], "medium")
+        mask = mask_random(p["seed"] + 7919, p["M"], p["rho"]).astype(np.uint8)
+        out.append(dict(p, f=img, mask=mask))
+    return out
