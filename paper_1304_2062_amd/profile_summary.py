@@ -33,7 +33,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 
 def short_name(name: str) -> str:
     """Kernel name without the argument list and namespace."""
-    base = name.split("(")[0].replace("void ", "").replace("se2n::", "")
+    base = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "").replace("se2n::", "")
     return re.sub(r"\s+", "", base)
 
 
