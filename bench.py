@@ -227,6 +227,65 @@ def bench_batch(args) -> int:
     return 0
 
 
+def bench_corrector(args) -> int:
+    """The learned corrector: inference on a 1024^2 N=32 volume and a training
+    step on 16 volumes of 256^2 (per-kernel MFMA throughput), and the held-out
+    accuracy of the committed network at 1024^2 against the fine-step FP64
+    solve, beside the plain solves."""
+    import torch
+
+    from paper_1304_2062_amd import corrector, se2n
+
+    N = 32
+    net = se2n.Corrector(N)
+    net.load(os.path.join(ROOT, "paper_1304_2062_amd", "corrector_N32.npz"))
+    flop_conv = lambda M, B: 2.0 * 32 * 32 * 9 * M * M * B  # one 32->32 layer, padded channels
+    res = {}
+    for mode, M, B in (("inference", 1024, 1), ("training", 256, 16)):
+        x = torch.randn((B, N, M, M), device="cuda")
+        y = x + 0.01 * torch.randn_like(x)
+        fn = (lambda: net.forward(x)) if mode == "inference" else (lambda: net.gradients(x, y))
+        for _ in range(args.warmup):
+            fn()
+        net.profile(True)
+        for _ in range(args.steps):
+            fn()
+        st = net.profile_stats()
+        net.profile(False)
+        k = {}
+        for name, (n, tot) in st.items():
+            e = {"launches_per_step": n // args.steps, "ms_per_step": round(tot / args.steps, 5)}
+            if name in ("cnn_conv1", "cnn_conv2", "cnn_conv3", "cnn_dgrad", "cnn_wgrad"):
+                fl = flop_conv(M, B) * (n // args.steps)
+                e["TFLOP_s"] = round(fl / (tot / args.steps / 1e3) / 1e12, 1)
+            k[name] = e
+        res[mode] = {"M": M, "batch": B, "kernels": k,
+                     "ms_per_step": round(sum(v["ms_per_step"] for v in k.values()), 4)}
+        print(f"[bench] corrector {mode} M={M} B={B}: {res[mode]['ms_per_step']:.3f} ms", file=sys.stderr,
+              flush=True)
+        for name, v in sorted(k.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+            print(f"[bench]   {name:16s} {v['ms_per_step']:.4f} ms" +
+                  (f"  {v['TFLOP_s']:.0f} TFLOP/s" if "TFLOP_s" in v else ""), file=sys.stderr, flush=True)
+    ev = corrector.evaluate(net, M=1024, count=args.eval_images, log=lambda m: None)
+    print(f"[bench] 1024^2 held-out rel-L2 vs fine FP64: {ev['volume_rel_l2']}", file=sys.stderr, flush=True)
+    dom = res["inference"]["kernels"]["cnn_conv2"]
+    MFMA_BF16 = 2500.0
+    line = {
+        "metric": METRIC, "value": None, "unit": "voxel-steps/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": res["inference"]["ms_per_step"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16", "data": "synthetic",
+        "config": {"workload": "corrector: 3x3 conv N=32->32->32->N BF16 MFMA, inference 1024^2, training 16x256^2",
+                   "N": N},
+        "roofline": {"kernel": "cnn_conv2 (inference)", "bound": "mfma", "achieved": dom["TFLOP_s"],
+                     "peak": MFMA_BF16, "unit": "TFLOP/s", "frac": round(dom["TFLOP_s"] / MFMA_BF16, 4),
+                     "traffic": None},
+        "corrector": res, "evaluation_1024": ev, "cpu_baseline": None,
+    }
+    print(json.dumps(line))
+    net.close()
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -236,8 +295,10 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-crop", type=int, default=512)
     ap.add_argument("--no-fp64-check", action="store_true")
-    ap.add_argument("--workload", choices=("single", "batch"), default="single",
-                    help="single: the 2048^2 N=32 inpaint; batch: the 64-image heterogeneous batch")
+    ap.add_argument("--workload", choices=("single", "batch", "corrector"), default="single",
+                    help="single: the 2048^2 N=32 inpaint; batch: the 64-image heterogeneous batch; "
+                         "corrector: the learned corrector's kernels and accuracy")
+    ap.add_argument("--eval-images", type=int, default=4, help="corrector workload: held-out 1024^2 images")
     ap.add_argument("--autotune", action="store_true",
                     help="batch workload: run the autotuner and rewrite the committed schedule table")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
@@ -254,6 +315,8 @@ def main() -> int:
 
     if args.workload == "batch":
         return bench_batch(args)
+    if args.workload == "corrector":
+        return bench_corrector(args)
 
     if args.copy_calibration:
         src = torch.empty(args.copy_calibration, dtype=torch.uint8, device="cuda")

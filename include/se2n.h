@@ -283,6 +283,81 @@ int se2n_batch_profile_stats(se2n_kernel_stat *out, int capacity, int *count);
 /* Free every cached batch plan on every device (waits for the device). */
 int se2n_batch_clear(void);
 
+/* Sizes of a plan: *M, *N, *dtype (any may be NULL).  Errors: SE2N_EINVAL, SE2N_ESTATE. */
+int se2n_plan_info(se2n_plan plan, int *M, int *N, se2n_dtype *dtype);
+
+/* ------------------------------------------------------------------------
+ * Learned corrector (BF16 MFMA network; not from the paper)
+ * ------------------------------------------------------------------------
+ * A small residual network that maps the real-space volume psi[N][M][M]
+ * diffused with n_coarse Crank-Nicolson steps towards the volume a finer
+ * step count gives:  psi_out = psi + r(psi),  r = conv3(relu(conv2(relu(
+ * conv1(psi))))), each conv a 3x3 cross-correlation with circular padding
+ * (the grid is periodic, as the paper's discretisation), N -> 32 -> 32 -> N
+ * channels.  Weights and activations are bfloat16, products accumulate in
+ * FP32 (MFMA), parameters are kept in FP32 and trained with Adam by the
+ * library's own forward and backward kernels.  The fine-step plain solve is
+ * the reference the network is trained against and judged by.
+ *
+ * Parameter vector (27744 floats): for layers l = 1, 2, 3 the weights
+ * W_l[o][c][tap] (32 x 32 x 9, tap = (dy+1)*3 + (dx+1) for the input offset
+ * (dy, dx), output channel o, input channel c), then the biases b_l[o] (32).
+ * Channels are padded to 32; weights reading input channels >= N (layer 1)
+ * or writing output channels >= N (layer 3), and those biases, are held at
+ * zero.  1 <= N <= 32; M must be a multiple of 16.
+ * Volumes are FP32 device arrays [batch][N][M][M] (planar, as se2n_diffuse).
+ * A network may be used from one host thread / one stream at a time. */
+typedef struct se2n_cnn_s *se2n_cnn;
+
+/* Create a network with seeded He-normal weights in layers 1 and 2 and zero
+ * layer 3 (it starts as the identity map); Adam state zero.
+ * Errors: SE2N_EINVAL (null out, N out of range), SE2N_ENOMEM, SE2N_EHIP. */
+int se2n_cnn_create(se2n_cnn *out, int N, uint64_t seed);
+/* Waits for the device, frees the network.  Errors: SE2N_EINVAL. */
+int se2n_cnn_destroy(se2n_cnn cnn);
+/* Copy the FP32 parameters to host memory (synchronises the device).
+ * host may be NULL to query *count (27744).  Errors: SE2N_EINVAL (capacity). */
+int se2n_cnn_get_params(se2n_cnn cnn, float *host, int capacity, int *count);
+/* Replace the parameters from host memory (padded entries forced to zero)
+ * and reset the Adam state.  Errors: SE2N_EINVAL (count, non-finite). */
+int se2n_cnn_set_params(se2n_cnn cnn, const float *host, int count);
+/* Workspace bytes of se2n_cnn_forward (training = 0) or of the gradient and
+ * training calls (training = 1) for `batch` volumes of side M; 0 if invalid. */
+size_t se2n_cnn_workspace_bytes(se2n_cnn cnn, int M, int batch, int training);
+/* out = psi + r(psi) for `batch` volumes; out may equal psi.
+ * Errors: SE2N_EINVAL (M not a multiple of 16, null pointer), SE2N_EHIP. */
+int se2n_cnn_forward(se2n_cnn cnn, const float *psi, float *out, int M, int batch, void *workspace,
+                     void *stream);
+/* Gradient of the mean squared error between psi_coarse + r(psi_coarse) and
+ * psi_fine over all batch*N*M*M values, with respect to the parameter
+ * vector: grads (device, 27744 floats) and, if loss is non-NULL, the loss
+ * (device, one float).  Every sum runs in a fixed order (deterministic). */
+int se2n_cnn_gradients(se2n_cnn cnn, const float *psi_coarse, const float *psi_fine, int M, int batch,
+                       float *grads, float *loss, void *workspace, void *stream);
+/* One Adam step (bias-corrected, step counter kept by the network) with the
+ * given device gradient.  Errors: SE2N_EINVAL (lr < 0, betas outside [0, 1),
+ * eps <= 0). */
+int se2n_cnn_adam_step(se2n_cnn cnn, const float *grads, float lr, float beta1, float beta2, float eps,
+                       void *stream);
+/* se2n_cnn_gradients + se2n_cnn_adam_step (beta1 0.9, beta2 0.999, eps 1e-8);
+ * loss (device float) may be NULL. */
+int se2n_cnn_train_step(se2n_cnn cnn, const float *psi_coarse, const float *psi_fine, int M, int batch, float lr,
+                        float *loss, void *workspace, void *stream);
+/* Per-kernel timing of the network's launches, as se2n_profile / se2n_profile_stats. */
+int se2n_cnn_profile(se2n_cnn cnn, int enable);
+int se2n_cnn_profile_stats(se2n_cnn cnn, se2n_kernel_stat *out, int capacity, int *count);
+
+/* Workspace bytes of se2n_inpaint_corrected (0 if the plan is not FP32, N
+ * differs from the network's, or M is not a multiple of 16). */
+size_t se2n_corrected_workspace_bytes(se2n_plan plan, se2n_cnn cnn);
+/* Inpainting with the corrector: orient, lift to a real-space volume
+ * (in the workspace), diffuse with n_steps coarse steps, psi += r(psi),
+ * project.  rmap_out and out are [M][M] device arrays (uint8, float).
+ * Errors: as se2n_inpaint; SE2N_EUNSUPPORTED for FP64 plans. */
+int se2n_inpaint_corrected(se2n_plan plan, se2n_cnn cnn, const void *f, const uint8_t *mask, double sigma,
+                           double T, double beta, int n_steps, se2n_scheme scheme, se2n_proj mode,
+                           uint8_t *rmap_out, void *out, void *workspace, void *stream);
+
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *se2n_last_error(void);
 

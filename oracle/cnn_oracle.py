@@ -6,9 +6,12 @@ check and the benchmark's CPU-baseline leg may call this module.
 The corrector is a residual network on a real-space orientation volume
 psi[N][H][W]: three 3x3 convolutions with circular (periodic) padding,
 N -> 32 -> 32 -> N channels, ReLU after the first two, and the output added
-to the input.  Channels are carried padded to 32: input channels N..31 are
-zero, as are the weights that read them (layer 1) or write output channels
-N..31 (layer 3), so the padded network computes exactly the N-channel one.
+to the input.  The network sees the volume divided by its root mean square
+s (1 for an all-zero volume) and its output is scaled back by s, so it works
+in the same units whatever the image's intensity.  Channels are carried
+padded to 32: input channels N..31 are zero, as are the weights that read
+them (layer 1) or write output channels N..31 (layer 3), so the padded
+network computes exactly the N-channel one.
 
 Definitions (written out, no blocking or reordering):
 
@@ -16,13 +19,15 @@ Definitions (written out, no blocking or reordering):
 
 with indices taken modulo H and W, dy, dx in {-1, 0, 1};
 
-    a0 = x padded to 32 channels,  z1 = conv(a0, W1, b1),  a1 = relu(z1),
-    z2 = conv(a1, W2, b2),  a2 = relu(z2),  r = conv(a2, W3, b3)[:N],
-    out = x + r,  loss = mean over (images, N, H, W) of (out - target)^2.
+    s = sqrt(mean(x^2)),  a0 = x/s padded to 32 channels,
+    z1 = conv(a0, W1, b1),  a1 = relu(z1),  z2 = conv(a1, W2, b2),  a2 = relu(z2),
+    r = conv(a2, W3, b3)[:N],  out = x + s r,
+    loss = mean over (images, N, H, W) of ((out - target)/s)^2   (s per image).
 
 Gradients follow from the chain rule:
 
-    g3 = dloss/dr,  dW3[o, c, dy, dx] = sum_{y, x} g3[o, y, x] a2[c, y+dy, x+dx],
+    g3 = dloss/dr = 2 (out - target) / (s numel),
+    dW3[o, c, dy, dx] = sum_{y, x} g3[o, y, x] a2[c, y+dy, x+dx],
     db3[o] = sum g3[o],  da2[c, y, x] = sum_{o, dy, dx} W3[o, c, dy, dx] g3[o, y-dy, x-dx],
     g2 = da2 * [a2 > 0],  and likewise for layers 2 and 1.
 
@@ -110,19 +115,27 @@ def forward(x: np.ndarray, params: np.ndarray, bf16: bool = False) -> dict:
     (w1, b1), (w2, b2), (w3, b3) = unpack(params)
     if bf16:
         w1, w2, w3 = bf16_round(w1), bf16_round(w2), bf16_round(w3)
+    s = rms(x)
     a0 = np.zeros((CP,) + x.shape[1:])
-    a0[:N] = _r(x, bf16)
+    a0[:N] = _r(x / s, bf16)
     z1 = conv3x3(a0, w1, b1)
     a1 = _r(np.maximum(z1, 0.0), bf16)
     z2 = conv3x3(a1, w2, b2)
     a2 = _r(np.maximum(z2, 0.0), bf16)
     r = conv3x3(a2, w3, b3)[:N]
-    return dict(a0=a0, a1=a1, a2=a2, r=r, out=x + r, w=(w1, w2, w3))
+    return dict(s=s, a0=a0, a1=a1, a2=a2, r=r, out=x + s * r, w=(w1, w2, w3))
+
+
+def rms(x) -> float:
+    """Root mean square of a volume; 1 for an all-zero volume."""
+    v = float(np.sqrt(np.mean(np.asarray(x, dtype=np.float64) ** 2)))
+    return v if v > 0.0 else 1.0
 
 
 def loss_and_grads(xs, targets, params: np.ndarray, bf16: bool = False) -> tuple[float, np.ndarray]:
-    """Mean squared error of out against target over a batch, and its gradient
-    with respect to the parameter vector (chain rule as in the module docstring)."""
+    """Mean squared error of out against target, each image in units of its
+    input's RMS, over a batch, and its gradient with respect to the parameter
+    vector (chain rule as in the module docstring)."""
     xs = [np.asarray(x, dtype=np.float64) for x in xs]
     targets = [np.asarray(t, dtype=np.float64) for t in targets]
     numel = sum(x.size for x in xs)
@@ -132,7 +145,7 @@ def loss_and_grads(xs, targets, params: np.ndarray, bf16: bool = False) -> tuple
         N = x.shape[0]
         fw = forward(x, params, bf16)
         w1, w2, w3 = fw["w"]
-        diff = fw["out"] - t
+        diff = (fw["out"] - t) / fw["s"]
         loss += float(np.sum(diff * diff))
         g3 = np.zeros((CP,) + x.shape[1:])
         g3[:N] = _r(2.0 * diff / numel, bf16)

@@ -476,6 +476,16 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     return SE2N_OK;
 }
 
+int se2n_plan_info(se2n_plan p, int* M, int* N, se2n_dtype* dtype) {
+    g_last_error.clear();
+    const int rc = check_plan(p);
+    if (rc) return rc;
+    if (M) *M = p->M;
+    if (N) *N = p->N;
+    if (dtype) *dtype = p->dt;
+    return SE2N_OK;
+}
+
 int se2n_plan_destroy(se2n_plan p) {
     g_last_error.clear();
     if (!p) return fail(SE2N_EINVAL, "plan is NULL");

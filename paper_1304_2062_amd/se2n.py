@@ -330,3 +330,167 @@ def batch_profile_stats() -> dict:
 
 def batch_clear() -> None:
     _check(_lib.se2n_batch_clear())
+
+
+# ---------------------------------------------------------------------------
+# Learned corrector (BF16 MFMA network)
+# ---------------------------------------------------------------------------
+_FP = ctypes.POINTER(ctypes.c_float)
+_lib.se2n_plan_info.argtypes = [_vp, ctypes.POINTER(_i), ctypes.POINTER(_i), ctypes.POINTER(_i)]
+_lib.se2n_cnn_create.argtypes = [ctypes.POINTER(_vp), _i, ctypes.c_uint64]
+_lib.se2n_cnn_destroy.argtypes = [_vp]
+_lib.se2n_cnn_get_params.argtypes = [_vp, _FP, _i, ctypes.POINTER(_i)]
+_lib.se2n_cnn_set_params.argtypes = [_vp, _FP, _i]
+_lib.se2n_cnn_workspace_bytes.argtypes = [_vp, _i, _i, _i]
+_lib.se2n_cnn_workspace_bytes.restype = ctypes.c_size_t
+_lib.se2n_cnn_forward.argtypes = [_vp, _vp, _vp, _i, _i, _vp, _vp]
+_lib.se2n_cnn_gradients.argtypes = [_vp, _vp, _vp, _i, _i, _vp, _vp, _vp, _vp]
+_lib.se2n_cnn_adam_step.argtypes = [_vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]
+_lib.se2n_cnn_train_step.argtypes = [_vp, _vp, _vp, _i, _i, ctypes.c_float, _vp, _vp, _vp]
+_lib.se2n_cnn_profile.argtypes = [_vp, _i]
+_lib.se2n_cnn_profile_stats.argtypes = [_vp, ctypes.POINTER(KernelStat), _i, ctypes.POINTER(_i)]
+_lib.se2n_corrected_workspace_bytes.argtypes = [_vp, _vp]
+_lib.se2n_corrected_workspace_bytes.restype = ctypes.c_size_t
+_lib.se2n_inpaint_corrected.argtypes = [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp]
+for _name in ("se2n_plan_info", "se2n_cnn_create", "se2n_cnn_destroy", "se2n_cnn_get_params", "se2n_cnn_set_params",
+              "se2n_cnn_forward", "se2n_cnn_gradients", "se2n_cnn_adam_step", "se2n_cnn_train_step",
+              "se2n_cnn_profile", "se2n_cnn_profile_stats", "se2n_inpaint_corrected"):
+    getattr(_lib, _name).restype = _i
+
+CNN_PARAMS = 3 * (32 * 32 * 9 + 32)
+
+
+class Corrector:
+    """The learned corrector for N orientations: psi -> psi + r(psi) on FP32
+    volumes [N][M][M] or batches [B][N][M][M] (M a multiple of 16)."""
+
+    def __init__(self, N: int, seed: int = 0, device: int | None = None):
+        self.N = int(N)
+        self.device = torch.device("cuda", torch.cuda.current_device() if device is None else int(device))
+        h = _vp()
+        with torch.cuda.device(self.device):
+            _check(_lib.se2n_cnn_create(ctypes.byref(h), self.N, int(seed)))
+        self._h = h
+        self._ws = {}
+
+    def _vol(self, t: torch.Tensor, name: str) -> tuple:
+        if t.dim() == 3:
+            t = t.unsqueeze(0)
+        if (t.dim() != 4 or t.shape[1] != self.N or t.shape[2] != t.shape[3] or t.dtype != torch.float32
+                or t.device != self.device or not t.is_contiguous()):
+            raise ValueError(f"{name} must be a contiguous float32 [B][{self.N}][M][M] (or [{self.N}][M][M]) "
+                             f"tensor on {self.device}")
+        return t, int(t.shape[0]), int(t.shape[2])
+
+    def workspace(self, M: int, batch: int, training: bool) -> torch.Tensor:
+        key = (int(M), int(batch), bool(training))
+        if key not in self._ws:
+            n = int(_lib.se2n_cnn_workspace_bytes(self._h, key[0], key[1], int(key[2])))
+            if n == 0:
+                raise Se2nError(-1, _lib.se2n_last_error().decode())
+            self._ws[key] = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._ws[key]
+
+    def params(self):
+        import numpy as np
+        n = _i(0)
+        _check(_lib.se2n_cnn_get_params(self._h, None, 0, ctypes.byref(n)))
+        a = np.empty(n.value, dtype=np.float32)
+        _check(_lib.se2n_cnn_get_params(self._h, a.ctypes.data_as(_FP), n.value, ctypes.byref(n)))
+        return a
+
+    def set_params(self, a) -> None:
+        import numpy as np
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        _check(_lib.se2n_cnn_set_params(self._h, a.ctypes.data_as(_FP), int(a.size)))
+
+    def forward(self, psi: torch.Tensor, out: torch.Tensor | None = None) -> torch.Tensor:
+        v, B, M = self._vol(psi, "psi")
+        if out is None:
+            out = torch.empty_like(psi)
+        o, _, _ = self._vol(out, "out")
+        _check(_lib.se2n_cnn_forward(self._h, _ptr(v), _ptr(o), M, B, _ptr(self.workspace(M, B, False)),
+                                     _vp(_stream())))
+        return out
+
+    def gradients(self, coarse: torch.Tensor, fine: torch.Tensor) -> tuple:
+        c, B, M = self._vol(coarse, "coarse")
+        f, _, _ = self._vol(fine, "fine")
+        grads = torch.empty(CNN_PARAMS, dtype=torch.float32, device=self.device)
+        loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(_lib.se2n_cnn_gradients(self._h, _ptr(c), _ptr(f), M, B, _ptr(grads), _ptr(loss),
+                                       _ptr(self.workspace(M, B, True)), _vp(_stream())))
+        return grads, loss
+
+    def adam_step(self, grads: torch.Tensor, lr: float, beta1: float = 0.9, beta2: float = 0.999,
+                  eps: float = 1e-8) -> None:
+        if grads.dtype != torch.float32 or grads.numel() != CNN_PARAMS or grads.device != self.device:
+            raise ValueError("grads must be a float32 device tensor of the parameter count")
+        _check(_lib.se2n_cnn_adam_step(self._h, _ptr(grads), float(lr), float(beta1), float(beta2), float(eps),
+                                       _vp(_stream())))
+
+    def train_step(self, coarse: torch.Tensor, fine: torch.Tensor, lr: float,
+                   loss: torch.Tensor | None = None) -> torch.Tensor:
+        c, B, M = self._vol(coarse, "coarse")
+        f, _, _ = self._vol(fine, "fine")
+        if loss is None:
+            loss = torch.empty(1, dtype=torch.float32, device=self.device)
+        _check(_lib.se2n_cnn_train_step(self._h, _ptr(c), _ptr(f), M, B, float(lr), _ptr(loss),
+                                        _ptr(self.workspace(M, B, True)), _vp(_stream())))
+        return loss
+
+    def profile(self, enable: bool = True) -> None:
+        _check(_lib.se2n_cnn_profile(self._h, 1 if enable else 0))
+
+    def profile_stats(self) -> dict:
+        n = _i(0)
+        _check(_lib.se2n_cnn_profile_stats(self._h, None, 0, ctypes.byref(n)))
+        arr = (KernelStat * max(n.value, 1))()
+        _check(_lib.se2n_cnn_profile_stats(self._h, arr, n.value, ctypes.byref(n)))
+        return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
+
+    def save(self, path: str) -> None:
+        """Parameters to a NumPy .npz (no pickled objects)."""
+        import numpy as np
+        np.savez(path, params=self.params(), N=np.int64(self.N))
+
+    def load(self, path: str) -> None:
+        import numpy as np
+        with np.load(path, allow_pickle=False) as z:
+            if int(z["N"]) != self.N:
+                raise ValueError(f"{path} holds a network for N={int(z['N'])}, not {self.N}")
+            self.set_params(z["params"])
+
+    def close(self) -> None:
+        if getattr(self, "_h", None) is not None:
+            _check(_lib.se2n_cnn_destroy(self._h))
+            self._h = None
+            self._ws = {}
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def inpaint_corrected(plan: Plan, cnn: Corrector, f: torch.Tensor, mask: torch.Tensor, T: float, beta: float,
+                      n_steps: int, sigma: float = 2.0, scheme: str = "cn", proj: str = "max",
+                      out: torch.Tensor | None = None, rmap_out: torch.Tensor | None = None,
+                      workspace: torch.Tensor | None = None):
+    """orient -> lift -> diffuse (n_steps) -> psi + r(psi) -> project.  Returns (out, rmap)."""
+    plan._image(f, "f")
+    plan._image(mask, "mask", torch.uint8)
+    if out is None:
+        out = torch.empty((plan.M, plan.M), dtype=torch.float32, device=plan.device)
+    if rmap_out is None:
+        rmap_out = torch.empty((plan.M, plan.M), dtype=torch.uint8, device=plan.device)
+    if workspace is None:
+        n = int(_lib.se2n_corrected_workspace_bytes(plan._h, cnn._h))
+        if n == 0:
+            raise Se2nError(-1, _lib.se2n_last_error().decode() or "plan and network do not match")
+        workspace = torch.empty(n, dtype=torch.uint8, device=plan.device)
+    _check(_lib.se2n_inpaint_corrected(plan._h, cnn._h, _ptr(f), _ptr(mask), float(sigma), float(T), float(beta),
+                                       int(n_steps), _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_out), _ptr(out),
+                                       _ptr(workspace), _vp(_stream())))
+    return out, rmap_out

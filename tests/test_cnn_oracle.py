@@ -130,3 +130,23 @@ def test_adam_closed_forms():
     v = 0.999 * 0.001 * g * g + 0.001 * g2 * g2
     want = p1 - lr * (m / (1 - 0.81)) / (np.sqrt(v / (1 - 0.999 ** 2)) + eps)
     assert np.allclose(p2, want, rtol=0, atol=1e-14)
+
+
+def test_scale_invariance():
+    """The network works in units of the input's RMS: scaling the input scales
+    the output (biases included), and the loss is unchanged."""
+    rng = np.random.default_rng(11)
+    N = 4
+    p = C.init_params(N, seed=12)
+    p[2 * C.NL:] = 0.05 * rng.standard_normal(C.NL)
+    p[2 * C.NL:2 * C.NL + C.NW].reshape(C.CP, C.CP, 3, 3)[N:] = 0.0
+    p[2 * C.NL + C.NW + N:] = 0.0
+    x = rng.standard_normal((N, 5, 5))
+    t = x + 0.1 * rng.standard_normal(x.shape)
+    out1 = C.forward(x, p)["out"]
+    out2 = C.forward(1e-3 * x, p)["out"]
+    assert np.max(np.abs(out2 - 1e-3 * out1)) < 1e-15
+    l1, g1 = C.loss_and_grads([x], [t], p)
+    l2, g2 = C.loss_and_grads([1e-3 * x], [1e-3 * t], p)
+    assert abs(l1 - l2) < 1e-12 * l1 and np.max(np.abs(g1 - g2)) < 1e-10 * np.max(np.abs(g1))
+    assert C.rms(np.zeros((2, 3, 3))) == 1.0
