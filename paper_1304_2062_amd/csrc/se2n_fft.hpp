@@ -178,6 +178,41 @@ __device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restric
 // Elements the LDS twiddle table occupies.
 __host__ __device__ constexpr int tw_elems(int M, bool full) { return full ? M : ((M / 4 + 1 + 7) & ~7); }
 
+// Multiply inputs r = 1 .. RADIX-1 of a butterfly by w^{r e} (conjugated for
+// the inverse).  Only w^e, w^{2e} (and w^{4e} for radix 8) are read from the
+// LDS table; the other powers are products of those, which saves LDS reads
+// at an error of a few ulps.
+template <class R, int RADIX, bool INV, bool TWFULL>
+__device__ __forceinline__ void apply_twiddles(C2<R>* v, const C2<R>* twq, int e, int M4) {
+    auto rd = [&](int m) {
+        C2<R> w = tw_get<R, TWFULL>(twq, m, M4);
+        if (INV) w.y = -w.y;
+        return w;
+    };
+    if constexpr (RADIX == 2) {
+        v[1] = cmul<R>(v[1], rd(e));
+    } else if constexpr (RADIX == 3) {
+        v[1] = cmul<R>(v[1], rd(e));
+        v[2] = cmul<R>(v[2], rd(2 * e));
+    } else if constexpr (RADIX == 4) {
+        const C2<R> w1 = rd(e), w2 = rd(2 * e);
+        v[1] = cmul<R>(v[1], w1);
+        v[2] = cmul<R>(v[2], w2);
+        v[3] = cmul<R>(v[3], cmul<R>(w1, w2));
+    } else {
+        static_assert(RADIX == 8, "radix 2, 3, 4 or 8");
+        const C2<R> w1 = rd(e), w2 = rd(2 * e), w4 = rd(4 * e);
+        const C2<R> w3 = cmul<R>(w1, w2);
+        v[1] = cmul<R>(v[1], w1);
+        v[2] = cmul<R>(v[2], w2);
+        v[3] = cmul<R>(v[3], w3);
+        v[4] = cmul<R>(v[4], w4);
+        v[5] = cmul<R>(v[5], cmul<R>(w1, w4));
+        v[6] = cmul<R>(v[6], cmul<R>(w2, w4));
+        v[7] = cmul<R>(v[7], cmul<R>(w3, w4));
+    }
+}
+
 // One Stockham stage, in place.  `nbatch` transforms of length L start at
 // buf + t*bstride.  Butterfly j of a transform reads x[j + r L/RADIX],
 // multiplies input r by w_{Ns RADIX}^{r (j mod Ns)}, and writes output r to
@@ -219,15 +254,7 @@ __device__ __forceinline__ void fft_stage(C2<R>* buf, const FftStage& s, int nba
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * nthr;
         if (b < total) {
-            if (Ns > 1) {
-                const int e = __mul24(kk[i], twstep);
-#pragma unroll
-                for (int r = 1; r < RADIX; ++r) {
-                    C2<R> w = tw_get<R, TWFULL>(twq, r * e, M4);
-                    if (INV) w.y = -w.y;
-                    v[i][r] = cmul<R>(v[i][r], w);
-                }
-            }
+            if (Ns > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v[i], twq, __mul24(kk[i], twstep), M4);
             dft<R, RADIX, INV>(v[i]);
 #pragma unroll
             for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * Ns)] = v[i][r];
@@ -313,15 +340,7 @@ __device__ __forceinline__ void fft_stage_static(C2<R>* buf, const C2<R>* twq, i
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * NTHR;
         if (TOTAL % NTHR == 0 || b < TOTAL) {
-            if (NS > 1) {
-                const int e = kk[i] * TWSTEP;
-#pragma unroll
-                for (int r = 1; r < RADIX; ++r) {
-                    C2<R> w = tw_get<R, TWFULL>(twq, r * e, M4);
-                    if (INV) w.y = -w.y;
-                    v[i][r] = cmul<R>(v[i][r], w);
-                }
-            }
+            if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v[i], twq, kk[i] * TWSTEP, M4);
             dft<R, RADIX, INV>(v[i]);
 #pragma unroll
             for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * NS)] = v[i][r];

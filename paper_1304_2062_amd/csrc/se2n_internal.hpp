@@ -55,6 +55,9 @@ struct LaunchGeom {
     int ocols;        // columns per orientation column workgroup
     int ocol_threads;
     int ocol_ept;
+    int pcols;        // columns per paired inverse column workgroup (even: pairs kx, M/2-kx)
+    int pcol_threads;
+    int pcol_ept;
     int xcd_pair;     // pair adjacent row blocks on one XCD (row passes)
     int tw_full;      // row passes: full-period twiddle table in LDS (else the quarter table)
     int tw_full_col;  // column passes: the same choice
@@ -67,6 +70,7 @@ struct GeomCore {
     int rows, row_threads, row_ept;
     int cols, col_threads, col_ept;
     int ocols, ocol_threads, ocol_ept;
+    int pcols, pcol_threads, pcol_ept;
     int tw_full, tw_full_col;
 };
 
@@ -95,6 +99,8 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     fft_threads_of(g.cols * M, g.col_threads, g.col_ept);
     g.ocols = target / (2 * M) > 1 ? target / (2 * M) : 1;
     fft_threads_of(2 * g.ocols * M, g.ocol_threads, g.ocol_ept);
+    g.pcols = g.cols >= 2 ? (g.cols & ~1) : 2;
+    fft_threads_of(g.pcols * M, g.pcol_threads, g.pcol_ept);
     // full-period twiddle table for the row passes when it fits beside the row
     // buffer; a column workgroup transforms only a few columns, for which
     // expanding the full table would cost as much as the transform
@@ -137,10 +143,18 @@ hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftP
                              const C2<R>* tw, double sigma, hipStream_t st);
 template <class R>
 hipError_t launch_solve(C2<R>* spec, const R* P, int M, int N, hipStream_t st);
+// paired: the inverse column pass already applied the pairing step of the
+// real inverse transform (launch_col_inv_paired)
 template <class R>
 hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U* enc, uint8_t* rmap,
                           int M, int nslices, int N, R out_scale, const LaunchGeom& g,
-                          int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st);
+                          int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st,
+                          bool paired = false);
+// Inverse column FFT of column pairs (kx, M/2-kx) of every slice, followed by
+// the pairing step of the real inverse row transform.
+template <class R>
+hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g, const FftPlan& planM,
+                                 const C2<R>* tw, hipStream_t st);
 template <class R>
 hipError_t launch_fill_enc(typename Enc<R>::U* enc, long n, hipStream_t st);
 template <class R>

@@ -100,7 +100,7 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
                                  neg_two_pi2_sigma2_over_M2, scale, threadIdx.x);
 }
 
-template <class R, int DST, int EPT, bool TWF, int MS>
+template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED>
 __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                           int M_, int nslices, int slices_per_group, int rows_, int xcd_pair, int N,
@@ -117,8 +117,22 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
-    row_inv_tile<R, DST, EPT, TWF, MS>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N, out_scale,
-                                       planH, tw, buf, threadIdx.x);
+    row_inv_tile<R, DST, EPT, TWF, MS, PAIRED>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N,
+                                               out_scale, planH, tw, buf, threadIdx.x);
+}
+
+// Paired inverse column pass: one tile of column pairs per workgroup.
+template <class R, int EPT, int MS>
+__global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spec, int M_, int pcols_, FftPlan planM,
+                                                         const C2<R>* __restrict__ twg) {
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int nthr = MS ? GC.pcol_threads : (int)blockDim.x;
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
+    C2<R>* buf = tw + tw_elems(M, false);
+    load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr);
+    col_inv_paired_tile<R, EPT, MS>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x);
 }
 
 // ---------------------------------------------------------------------------
@@ -414,15 +428,45 @@ hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftP
 }
 
 template <class R>
+hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g, const FftPlan& planM,
+                                 const C2<R>* tw, hipStream_t st) {
+    const int P = g.pcols / 2;
+    const int npair = M / 4 + 1;
+    const dim3 grid((unsigned)(N * ((npair + P - 1) / P)));
+    const size_t lds = tw_bytes<R>(M, false) + (size_t)lds_padded_size(g.pcols * M) * sizeof(C2<R>);
+    const GeomCore c = geom_core<R>(M);
+    const bool fixed = static_size<R>(M, g) != 0 && g.pcols == c.pcols && g.pcol_threads == c.pcol_threads &&
+                       c.pcol_ept == 8;
+#define SE2N_PCOL(E, MSV) \
+    hipLaunchKernelGGL((k_col_inv_paired<R, E, MSV>), grid, dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw)
+    if (fixed && M == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0);
+    else if (fixed && M == 1024) SE2N_PCOL(8, kStatic<R> ? 1024 : 0);
+    else if (fixed && M == 512) SE2N_PCOL(8, kStatic<R> ? 512 : 0);
+    else if (g.pcol_ept == 8) SE2N_PCOL(8, 0);
+    else SE2N_PCOL(16, 0);
+#undef SE2N_PCOL
+    return hipGetLastError();
+}
+
+template <class R>
 hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U* enc, uint8_t* rmap,
                           int M, int nslices, int N, R out_scale, const LaunchGeom& g,
-                          int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st) {
+                          int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st,
+                          bool paired) {
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
     dim3 grid((M / g.rows) * groups);
     const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 2)) * sizeof(C2<R>);
-#define SE2N_ROWINV(D, E, W, MSV)                                                                            \
-    hipLaunchKernelGGL((k_row_inv<R, D, E, W, MSV>), grid, dim3(g.row_threads), lds, st, spec, out, enc, rmap,   \
-                       M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH, tw)
+#define SE2N_ROWINV(D, E, W, MSV)                                                                              \
+    do {                                                                                                       \
+        if (paired)                                                                                            \
+            hipLaunchKernelGGL((k_row_inv<R, D, E, W, MSV, true>), grid, dim3(g.row_threads), lds, st, spec, out, \
+                               enc, rmap, M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH,  \
+                               tw);                                                                            \
+        else                                                                                                   \
+            hipLaunchKernelGGL((k_row_inv<R, D, E, W, MSV, false>), grid, dim3(g.row_threads), lds, st, spec, out, \
+                               enc, rmap, M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH,  \
+                               tw);                                                                            \
+    } while (0)
 #define SE2N_ROWINV_E(D)                                                    \
     if (static_size<R>(M, g) == 2048) SE2N_ROWINV(D, 8, true, kStatic<R> ? 2048 : 0);        \
     else if (static_size<R>(M, g) == 1024) SE2N_ROWINV(D, 8, true, kStatic<R> ? 1024 : 0);   \
@@ -496,7 +540,9 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
                                              const C2<R>*, double, hipStream_t);                       \
     template hipError_t launch_row_inv<R>(int, const C2<R>*, R*, typename Enc<R>::U*, uint8_t*, int,   \
                                           int, int, R, const LaunchGeom&, int, const FftPlan&,         \
-                                          const C2<R>*, hipStream_t);                                  \
+                                          const C2<R>*, hipStream_t, bool);                            \
+    template hipError_t launch_col_inv_paired<R>(C2<R>*, int, int, const LaunchGeom&, const FftPlan&,  \
+                                                 const C2<R>*, hipStream_t);                           \
     template hipError_t launch_fill_enc<R>(typename Enc<R>::U*, long, hipStream_t);                    \
     template hipError_t launch_decode_enc<R>(const typename Enc<R>::U*, R*, long, hipStream_t);        \
     template hipError_t launch_lift<R>(const R*, const uint8_t*, const uint8_t*, R*, int, int,         \

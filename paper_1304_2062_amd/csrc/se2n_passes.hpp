@@ -165,6 +165,70 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
 }
 
 // ---------------------------------------------------------------------------
+// Inverse column pass on column pairs, then the pairing step of the real
+// inverse row transform.  Tile `tile` of slice r = tile / tiles_per_slice
+// holds the pairs (k, H-k), k = p0 .. p0+np-1 of that slice (H = M/2, pairs
+// k = 0 .. H/2).  After the inverse FFT along y of both columns, for every y
+//   Z[k]   = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]),
+//   Z[H-k] = (X[H-k] + conj X[k]) + i w_M^{-(H-k)} (X[H-k] - conj X[k])
+// overwrite columns k and H-k (column H is left alone: the row pass reads
+// Z[0 .. H-1] only).  The inverse FFT_H of Z along x is then M (x[2n] + i x[2n+1]).
+// ---------------------------------------------------------------------------
+template <class R, int EPT, int MS>
+__device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, int M_, int pcols_, int nthr_,
+                                                    int tile, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
+                                                    int tid) {
+    constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    const int M = MS ? MS : M_;
+    const int pc = MS ? GC.pcols : pcols_;
+    const int nthr = MS ? GC.pcol_threads : nthr_;
+    const int H = M >> 1;
+    const int K = H + 1;
+    const int M4 = M >> 2;
+    const int P = pc >> 1;
+    const int npair = H / 2 + 1;
+    const int tps = (npair + P - 1) / P;
+    const int r = tile / tps;
+    const int p0 = (tile - r * tps) * P;
+    const int np = min(P, npair - p0);
+    C2<R>* base = spec + (size_t)r * K * M;
+    const float inv_M = 1.0f / (float)M;
+    const int nel = 2 * np * M;
+    for (int e = tid; e < nel; e += nthr) {
+        const int cc = fdiv(e, inv_M);
+        const int y = e - cc * M;
+        const int k = p0 + (cc >> 1);
+        const int kx = (cc & 1) ? H - k : k;
+        buf[lds_pad(e)] = base[(size_t)kx * M + y];
+    }
+    __syncthreads();
+    if constexpr (MS != 0) {
+        if (np == P) fft_static<R, true, false, MS, GC.pcols, MS, GC.pcol_threads, MS>(buf, tw, tid);
+        else fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
+    } else {
+        fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
+    }
+    for (int e = tid; e < np * M; e += nthr) {
+        const int q = fdiv(e, inv_M);
+        const int y = e - q * M;
+        const int k = p0 + q;
+        const int kk = H - k;
+        const C2<R> a = buf[lds_pad(2 * q * M + y)];
+        const C2<R> b = buf[lds_pad((2 * q + 1) * M + y)];
+        const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
+        const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
+        const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, false>(tw, k, M4)), da);
+        base[(size_t)k * M + y] = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
+        if (k != 0 && kk != k) {
+            const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
+            const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
+            const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, false>(tw, kk, M4)), db);
+            base[(size_t)kk * M + y] = cmk<R>(sb.x - tb.y, sb.y + tb.x);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // Orientation: column FFT of the corrupted image's row spectrum F[kx][ky]
 // (slice 0) for kx in [c0, c0 + ncb), multiplication by the smoothed
 // central-difference symbols and inverse column FFTs.  Writes G_x into
@@ -219,7 +283,7 @@ __device__ __forceinline__ void col_orient_tile(C2<R>* __restrict__ spec, int M,
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int DST, int EPT, bool TWF, int MS>
+template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED = false>
 __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* __restrict__ out,
                                              typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                                              int M_, int rows_, int nthr_, int rb, int s_begin, int s_end, int N,
@@ -253,22 +317,24 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const int row_t = tid & (rows - 1);
     const int kx_t = tid >> rshift;
     const int kstep = nthr >> rshift;
+    const int KL = PAIRED ? H : K;       // columns the transform reads
     C2<R> pre[MAXL];
-#define SE2N_FETCH(SL)                                                                      \
-    do {                                                                                   \
-        const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;    \
-        _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < K) pre[i] = \
-            in_[(size_t)(i * kstep) * M];                                                   \
+#define SE2N_FETCH(SL)                                                                       \
+    do {                                                                                    \
+        const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;     \
+        _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < KL) pre[i] = \
+            in_[(size_t)(i * kstep) * M];                                                    \
     } while (0)
     SE2N_FETCH(s_begin);
     for (int s = s_begin; s < s_end; ++s) {
 #pragma unroll
         for (int i = 0; i < MAXL; ++i) {
             const int kx = kx_t + i * kstep;
-            if (kx < K) buf[lds_pad(row_t * S + kx)] = pre[i];
+            if (kx < KL) buf[lds_pad(row_t * S + kx)] = pre[i];
         }
         __syncthreads();
         if (s + 1 < s_end) SE2N_FETCH(s + 1);
+        if constexpr (!PAIRED) {
         // pairing step of the real inverse transform:
         //   Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]),  k < H
         const int npair = H / 2 + 1;
@@ -289,6 +355,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
             if (kk != k) buf[lds_pad(row * S + kk)] = cmk<R>(sb.x - tb.y, sb.y + tb.x);
         }
         __syncthreads();
+        }
         if constexpr (MS != 0)
             fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
         else

@@ -214,6 +214,9 @@ LaunchGeom make_geom(int M, int N) {
     g.ocols = c.ocols;
     g.ocol_threads = c.ocol_threads;
     g.ocol_ept = c.ocol_ept;
+    g.pcols = c.pcols;
+    g.pcol_threads = c.pcol_threads;
+    g.pcol_ept = c.pcol_ept;
     g.tw_full = c.tw_full;
     g.tw_full_col = c.tw_full_col;
     const int row_blocks = M / c.rows;
@@ -244,7 +247,10 @@ int check_geom(const LaunchGeom& g, int M) {
         2 * g.ocols * M <= g.ocol_ept * g.ocol_threads &&
         (size_t)(tw_elems(M, g.tw_full) + lds_padded_size(g.rows * (H + 2))) * cs <= lds_max &&
         (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(2 * g.ocols * M)) * cs <= lds_max &&
-        (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(g.cols * M)) * cs <= lds_max;
+        (size_t)(tw_elems(M, g.tw_full_col) + lds_padded_size(g.cols * M)) * cs <= lds_max &&
+        g.pcols >= 2 && g.pcols % 2 == 0 && g.pcol_threads >= 1 && g.pcol_threads <= 1024 &&
+        g.pcols * M <= g.pcol_ept * g.pcol_threads &&
+        (size_t)(tw_elems(M, false) + lds_padded_size(g.pcols * M)) * cs <= lds_max;
     return ok ? SE2N_OK : fail(SE2N_EUNSUPPORTED, "internal launch geometry invalid for M=%d", M);
 }
 
@@ -339,6 +345,8 @@ int orient_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, uint
 }
 
 // spec holds the forward half spectrum of all slices; propagate it in place.
+// The inverse column pass runs on column pairs and leaves the pairing step
+// of the real inverse row transform done (the row pass is then `paired`).
 template <class R>
 int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
@@ -346,7 +354,7 @@ int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
     SE2N_TIMED(p, "col_fft_fwd", st, launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st),
                "forward column FFT");
     SE2N_TIMED(p, "solve", st, launch_solve<R>(spec, (const R*)P, p->M, p->N, st), "per-mode solve");
-    SE2N_TIMED(p, "col_fft_inv", st, launch_col_fft<R>(true, spec, ncols, p->M, p->geom, p->planM, tw, st),
+    SE2N_TIMED(p, "col_fft_inv", st, launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st),
                "inverse column FFT");
     return SE2N_OK;
 }
@@ -360,21 +368,21 @@ int project_spec(se2n_plan p, const C2<R>* spec, typename Enc<R>::U* enc, se2n_p
     if (mode == SE2N_PROJ_MEAN) {
         SE2N_TIMED(p, "row_inv_mean", st,
                    launch_row_inv<R>(DST_SUM, spec, out, nullptr, nullptr, M, N, N, R(1) / (R)N, p->geom, N,
-                                     p->planH, tw, st),
+                                     p->planH, tw, st, true),
                    "inverse row pass (mean)");
         return SE2N_OK;
     }
     if (p->geom.inv_slices >= N) {
         SE2N_TIMED(p, "row_inv_max", st,
                    launch_row_inv<R>(DST_MAX, spec, out, nullptr, nullptr, M, N, N, R(1), p->geom, N, p->planH,
-                                     tw, st),
+                                     tw, st, true),
                    "inverse row pass (max)");
         return SE2N_OK;
     }
     SE2N_TIMED(p, "fill_max", st, launch_fill_enc<R>(enc, MM, st), "clear max buffer");
     SE2N_TIMED(p, "row_inv_max", st,
                launch_row_inv<R>(DST_MAX, spec, nullptr, enc, nullptr, M, N, N, R(1), p->geom,
-                                 p->geom.inv_slices, p->planH, tw, st),
+                                 p->geom.inv_slices, p->planH, tw, st, true),
                "inverse row pass (max)");
     SE2N_TIMED(p, "decode_max", st, launch_decode_enc<R>(enc, out, MM, st), "decode max buffer");
     return SE2N_OK;
@@ -423,7 +431,7 @@ int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_s
     if (rc) return rc;
     SE2N_TIMED(p, "row_inv_volume", st,
                launch_row_inv<R>(DST_VOLUME, w.spec, psi, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
-                                 p->geom.inv_slices, p->planH, tw, st),
+                                 p->geom.inv_slices, p->planH, tw, st, true),
                "inverse row FFT");
     return SE2N_OK;
 }
