@@ -111,10 +111,13 @@ __device__ __forceinline__ void dft(C2<R>* v) {
 }
 
 // LDS position of logical element i of a transform buffer: one complex of
-// padding after every 16 keeps the strided writes of the early Stockham
-// stages (stride radix * 8 or 16 bytes) spread over the banks.
-__device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
-__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> 4) + 1; }
+// padding after every 32 spreads the strided writes of the early Stockham
+// stages over the banks (every 16 and every 8 measured slower on gfx950).
+#ifndef SE2N_LDS_PAD_SHIFT
+#define SE2N_LDS_PAD_SHIFT 5
+#endif
+__device__ __forceinline__ int lds_pad(int i) { return i + (i >> SE2N_LDS_PAD_SHIFT); }
+__host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> SE2N_LDS_PAD_SHIFT) + 1; }
 
 // Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal (inv = 1/d
 // rounded to float): (n + 1/2) inv lies at least 1/(2d) away from an integer,
@@ -139,14 +142,22 @@ struct FftPlan {
     FftStage st[12];
 };
 
+// LDS position of twiddle m: one complex of padding after every 2^SHIFT.  The
+// middle Stockham stages read w^{r k twstep} with twstep a power of two, so
+// without padding every lane of a wave falls in the same few banks.
+#ifndef SE2N_TW_PAD_SHIFT
+#define SE2N_TW_PAD_SHIFT 3
+#endif
+__host__ __device__ constexpr int tw_pos(int m) { return m + (m >> SE2N_TW_PAD_SHIFT); }
+
 // Twiddle w_M^m = exp(-2 pi i m / M), m in [0, M), from the LDS table: the
 // full period (FULL) or the quarter r in [0, M/4] with
 // w_M^{a M/4 + r} = (-i)^a w_M^r.
 template <class R, bool FULL>
 __device__ __forceinline__ C2<R> tw_get(const C2<R>* tw, int m, int M4) {
-    if (FULL) return tw[m];
+    if (FULL) return tw[tw_pos(m)];
     const int a = (m >= M4) + (m >= 2 * M4) + (m >= 3 * M4);
-    const C2<R> w = tw[m - __mul24(a, M4)];
+    const C2<R> w = tw[tw_pos(m - __mul24(a, M4))];
     if (a == 0) return w;
     if (a == 1) return cmk<R>(w.y, -w.x);
     if (a == 2) return cmk<R>(-w.x, -w.y);
@@ -160,7 +171,7 @@ template <class R>
 __device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restrict__ q, int M4, bool full,
                                               int tid, int nthr) {
     if (!full) {
-        for (int i = tid; i <= M4; i += nthr) dst[i] = q[i];
+        for (int i = tid; i <= M4; i += nthr) dst[tw_pos(i)] = q[i];
         return;
     }
     for (int m = tid; m < 4 * M4; m += nthr) {
@@ -171,12 +182,15 @@ __device__ __forceinline__ void load_twiddles(C2<R>* dst, const C2<R>* __restric
         else if (a == 1) v = cmk<R>(w.y, -w.x);
         else if (a == 2) v = cmk<R>(-w.x, -w.y);
         else v = cmk<R>(-w.y, w.x);
-        dst[m] = v;
+        dst[tw_pos(m)] = v;
     }
 }
 
-// Elements the LDS twiddle table occupies.
-__host__ __device__ constexpr int tw_elems(int M, bool full) { return full ? M : ((M / 4 + 1 + 7) & ~7); }
+// Elements the LDS twiddle table occupies (a multiple of 8: what follows
+// stays 64-byte aligned).
+__host__ __device__ constexpr int tw_elems(int M, bool full) {
+    return (tw_pos(full ? M - 1 : M / 4) + 1 + 7) & ~7;
+}
 
 // Multiply inputs r = 1 .. RADIX-1 of a butterfly by w^{r e} (conjugated for
 // the inverse).  Only w^e, w^{2e} (and w^{4e} for radix 8) are read from the

@@ -89,7 +89,10 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     const int cs = (int)sizeof(R) * 2;
     const int target = sizeof(R) == 4 ? 4096 : 2048;  // complex elements per FFT workgroup
     const int H = M / 2;
-    int rows = 64 / cs;                                // 64-byte segments per (slice, kx)
+#ifndef SE2N_ROW_SEG_BYTES
+#define SE2N_ROW_SEG_BYTES 64
+#endif
+    int rows = SE2N_ROW_SEG_BYTES / cs;                // contiguous bytes per (slice, kx) segment
     while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
     g.rows = rows;
     fft_threads_of(rows * H, g.row_threads, g.row_ept);
@@ -104,7 +107,7 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     // full-period twiddle table for the row passes when it fits beside the row
     // buffer; a column workgroup transforms only a few columns, for which
     // expanding the full table would cost as much as the transform
-    g.tw_full = (long)M * cs + (long)lds_padded_size(rows * (H + 2)) * cs <= 150 * 1024 ? 1 : 0;
+    g.tw_full = (long)tw_elems(M, true) * cs + (long)lds_padded_size(rows * (H + 2)) * cs <= 150 * 1024 ? 1 : 0;
     g.tw_full_col = 0;
     return g;
 }

@@ -2,6 +2,7 @@
 // propagator cache, workspace layout and the C ABI of include/se2n.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -202,7 +203,7 @@ struct ProfScope {
     } while (0)
 
 template <class R>
-LaunchGeom make_geom(int M, int N) {
+LaunchGeom make_geom(int M, int N, int num_cu) {
     const GeomCore c = geom_core<R>(M);
     LaunchGeom g{};
     g.rows = c.rows;
@@ -220,11 +221,18 @@ LaunchGeom make_geom(int M, int N) {
     g.tw_full = c.tw_full;
     g.tw_full_col = c.tw_full_col;
     const int row_blocks = M / c.rows;
-    int groups = (1024 + row_blocks - 1) / row_blocks;
-    if (groups > N) groups = N;
-    if (groups < 1) groups = 1;
+    // slice groups of the row passes: the fewest that give every compute unit
+    // a workgroup (a row pass workgroup fills a CU's registers); fewer groups
+    // read the lift sources fewer times and combine fewer maxima through
+    // atomics (SE2N_ROW_GROUPS / SE2N_INV_GROUPS override the choice)
+    int groups = (num_cu + row_blocks - 1) / row_blocks;
+    int inv_groups = groups;
+    if (const char* v = std::getenv("SE2N_ROW_GROUPS")) groups = std::atoi(v);
+    if (const char* v = std::getenv("SE2N_INV_GROUPS")) inv_groups = std::atoi(v);
+    groups = std::max(1, std::min(groups, N));
+    inv_groups = std::max(1, std::min(inv_groups, N));
     g.row_slices = (N + groups - 1) / groups;
-    g.inv_slices = g.row_slices;
+    g.inv_slices = (N + inv_groups - 1) / inv_groups;
     g.xcd_pair = 1;
     if (const char* v = std::getenv("SE2N_TW_FULL")) g.tw_full = std::atoi(v) != 0 && g.tw_full;
     if (const char* v = std::getenv("SE2N_XCD_PAIR")) g.xcd_pair = std::atoi(v);
@@ -463,15 +471,18 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     p->N = N;
     p->dt = dtype;
     (void)hipGetDevice(&p->device);
+    int num_cu = 0;
+    if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || num_cu < 1)
+        num_cu = 256;
     p->planH = make_fft_plan(M / 2, M);
     p->planM = make_fft_plan(M, M);
     int rc;
     if (dtype == SE2N_F32) {
-        p->geom = make_geom<float>(M, N);
+        p->geom = make_geom<float>(M, N, num_cu);
         rc = check_geom<float>(p->geom, M);
         if (!rc) rc = make_twiddles<float>(p);
     } else {
-        p->geom = make_geom<double>(M, N);
+        p->geom = make_geom<double>(M, N, num_cu);
         rc = check_geom<double>(p->geom, M);
         if (!rc) rc = make_twiddles<double>(p);
     }

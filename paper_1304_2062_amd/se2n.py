@@ -13,7 +13,9 @@ import os
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libse2n.so")
+# SE2N_LIB names another build of the library (e.g. one compiled with other
+# tuning constants); by default the in-tree build next to this file.
+LIB_PATH = os.environ.get("SE2N_LIB") or os.path.join(_HERE, "libse2n.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(
