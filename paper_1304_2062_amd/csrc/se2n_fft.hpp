@@ -372,4 +372,81 @@ __device__ __forceinline__ void fft_static(C2<R>* buf, const C2<R>* twq, int tid
     }
 }
 
+// Radix of the last stage of a length-L transform, and the outputs each of
+// NTHR threads produces in it (the thread's output slots).
+__host__ __device__ constexpr int static_last_radix(int L) {
+    int s = 0;
+    while (static_radix(L, s + 1) != 0) ++s;
+    return static_radix(L, s);
+}
+__host__ __device__ constexpr int static_out_slots(int L, int NBATCH, int NTHR) {
+    return (L / static_last_radix(L) * NBATCH + NTHR - 1) / NTHR * static_last_radix(L);
+}
+
+// Transform t and position n of output slot `slot` of thread tid in the last
+// stage; false if the slot is unused.
+template <int L, int NBATCH, int NTHR>
+__device__ __forceinline__ bool static_out_pos(int tid, int slot, int& t, int& n) {
+    constexpr int RADIX = static_last_radix(L);
+    constexpr int NB = L / RADIX;  // = NS of the last stage
+    const int i = slot / RADIX, r = slot - (slot / RADIX) * RADIX;
+    const int b = tid + i * NTHR;
+    t = b / NB;
+    n = (b - t * NB) + r * NB;
+    return b < NB * NBATCH;
+}
+
+// The transforms of fft_static, except that the last stage hands each output
+// to f(slot, t, n, value) (slot = i*RADIX + r of the thread's butterfly i,
+// output r; transform t, position n) instead of writing it to LDS.  No
+// barrier follows the last stage: every thread has read its inputs before
+// the stage's own barrier, so the caller may refill the buffer at once.
+template <class R, int RADIX, bool INV, bool TWFULL, int L, int NS, int NBATCH, int BSTRIDE, int NTHR, int M, class F>
+__device__ __forceinline__ void fft_stage_static_out(C2<R>* buf, const C2<R>* twq, int tid, F&& f) {
+    constexpr int NB = L / RADIX;
+    constexpr int TOTAL = NB * NBATCH;
+    constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+    constexpr int TWSTEP = M / (NS * RADIX);
+    constexpr int M4 = M / 4;
+    static_assert(NS * RADIX == L, "the output stage is the last one");
+    C2<R> v[MAXB][RADIX];
+    int tt[MAXB], kk[MAXB];
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * NTHR;
+        if (TOTAL % NTHR == 0 || b < TOTAL) {
+            const int t = b / NB;
+            const int j = b - t * NB;
+            const int ib = t * BSTRIDE + j;
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * NB)];
+            tt[i] = t;
+            kk[i] = j;  // q = 0 in the last stage: k = j
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * NTHR;
+        if (TOTAL % NTHR == 0 || b < TOTAL) {
+            if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v[i], twq, kk[i] * TWSTEP, M4);
+            dft<R, RADIX, INV>(v[i]);
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) f(i * RADIX + r, tt[i], kk[i] + r * NS, v[i][r]);
+        }
+    }
+}
+
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S = 0, int NS = 1,
+          class F>
+__device__ __forceinline__ void fft_static_out(C2<R>* buf, const C2<R>* twq, int tid, F&& f) {
+    constexpr int RADIX = static_radix(L, S);
+    if constexpr (static_radix(L, S + 1) == 0) {
+        fft_stage_static_out<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(buf, twq, tid, f);
+    } else {
+        fft_stage_static<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(buf, twq, tid);
+        fft_static_out<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(buf, twq, tid, f);
+    }
+}
+
 }  // namespace se2n

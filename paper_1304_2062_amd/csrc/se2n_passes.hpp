@@ -356,43 +356,55 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
         }
         __syncthreads();
         }
-        if constexpr (MS != 0)
-            fft_static<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
-        else
+        // consume output element i (row, pixel pair n) of this slice
+        auto take = [&](int i, int row, int n, C2<R> z) {
+            if (DST == DST_VOLUME) {
+                *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
+                    cmk<R>(z.x * out_scale, z.y * out_scale);
+            } else if (DST == DST_MAX) {
+                acc[i].x = fmax(acc[i].x, z.x);
+                acc[i].y = fmax(acc[i].y, z.y);
+            } else if (DST == DST_SUM) {
+                acc[i].x += z.x;
+                acc[i].y += z.y;
+            } else {  // DST_ORIENT
+                if (s == 0) acc[i] = z;
+                else acc2[i] = z;
+            }
+        };
+        if constexpr (MS != 0) {
+            // the last stage's outputs go straight to the accumulators
+            static_assert(static_out_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one accumulator per output");
+            fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
+                buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+        } else {
             fft_lds<R, true, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * nthr;
-            if (e < nel) {
-                int row, n;
-                split_index(tid, i, nthr, H, inv_H, row, n);
-                const C2<R> z = buf[lds_pad(row * S + n)];
-                if (DST == DST_VOLUME) {
-                    *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
-                        cmk<R>(z.x * out_scale, z.y * out_scale);
-                } else if (DST == DST_MAX) {
-                    acc[i].x = fmax(acc[i].x, z.x);
-                    acc[i].y = fmax(acc[i].y, z.y);
-                } else if (DST == DST_SUM) {
-                    acc[i].x += z.x;
-                    acc[i].y += z.y;
-                } else {  // DST_ORIENT
-                    if (s == 0) acc[i] = z;
-                    else acc2[i] = z;
+            for (int i = 0; i < EPT; ++i) {
+                const int e = tid + i * nthr;
+                if (e < nel) {
+                    int row, n;
+                    split_index(tid, i, nthr, H, inv_H, row, n);
+                    take(i, row, n, buf[lds_pad(row * S + n)]);
                 }
             }
+            __syncthreads();
         }
-        __syncthreads();
     }
 #undef SE2N_FETCH
 
     if (DST == DST_VOLUME) return;
 #pragma unroll
     for (int i = 0; i < EPT; ++i) {
-        const int e = tid + i * nthr;
-        if (e < nel) {
-            int row, n;
+        int row, n;
+        bool valid;
+        if constexpr (MS != 0) {
+            valid = static_out_pos<MS / 2, GC.rows, GC.row_threads>(tid, i, row, n);
+        } else {
+            valid = tid + i * nthr < nel;
             split_index(tid, i, nthr, H, inv_H, row, n);
+        }
+        if (valid) {
             const size_t p = (size_t)(y0 + row) * M + 2 * n;
             if (DST == DST_MAX) {
                 if (enc) {
