@@ -372,6 +372,50 @@ __device__ __forceinline__ void fft_static(C2<R>* buf, const C2<R>* twq, int tid
     }
 }
 
+// Input slots of the first stage: thread tid's butterfly i reads positions
+// n = j + r*NB (r < RADIX) of transform t; slot = i*RADIX + r.
+__host__ __device__ constexpr int static_in_slots(int L, int NBATCH, int NTHR) {
+    return (L / static_radix(L, 0) * NBATCH + NTHR - 1) / NTHR * static_radix(L, 0);
+}
+
+template <int L, int NBATCH, int NTHR>
+__device__ __forceinline__ bool static_in_pos(int tid, int slot, int& t, int& n) {
+    constexpr int RADIX = static_radix(L, 0);
+    constexpr int NB = L / RADIX;
+    const int i = slot / RADIX, r = slot - (slot / RADIX) * RADIX;
+    const int b = tid + i * NTHR;
+    t = b / NB;
+    n = (b - t * NB) + r * NB;
+    return b < NB * NBATCH;
+}
+
+// The transforms of fft_static with the first stage's inputs taken from
+// g(slot) (see static_in_pos) instead of LDS.  The caller guarantees that no
+// thread still reads the buffer (the first stage writes it at once).
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, class G>
+__device__ __forceinline__ void fft_static_in(C2<R>* buf, const C2<R>* twq, int tid, G&& g) {
+    constexpr int RADIX = static_radix(L, 0);
+    constexpr int NB = L / RADIX;
+    constexpr int TOTAL = NB * NBATCH;
+    constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int b = tid + i * NTHR;
+        if (TOTAL % NTHR == 0 || b < TOTAL) {
+            const int t = b / NB;
+            const int j = b - t * NB;
+            C2<R> v[RADIX];
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) v[r] = g(i * RADIX + r);
+            dft<R, RADIX, INV>(v);  // first stage: no twiddles (Ns = 1)
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) buf[lds_pad(t * BSTRIDE + j * RADIX + r)] = v[r];
+        }
+    }
+    __syncthreads();
+    fft_static<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, 1, RADIX>(buf, twq, tid);
+}
+
 // Radix of the last stage of a length-L transform, and the outputs each of
 // NTHR threads produces in it (the thread's output slots).
 __host__ __device__ constexpr int static_last_radix(int L) {

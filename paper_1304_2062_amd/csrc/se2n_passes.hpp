@@ -63,20 +63,30 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
     const int nel = rows * H;
     const float inv_H = 1.0f / (float)H;
 
-    // Lift sources are read once per tile and kept in registers.
+    // Lift sources are read once per tile and kept in registers: element i
+    // of the thread is (row, pixel pair n) of its first-stage butterfly inputs
+    // (fixed-size transforms, which take them from registers) or of the
+    // natural order e = tid + i*nthr (else).
+    auto elem = [&](int i, int& row, int& n) {
+        if constexpr (MS != 0) {
+            static_assert(static_in_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one register per input");
+            return static_in_pos<MS / 2, GC.rows, GC.row_threads>(tid, i, row, n);
+        } else {
+            split_index(tid, i, nthr, H, inv_H, row, n);
+            return tid + i * nthr < nel;
+        }
+    };
     R fc0[EPT], fc1[EPT];
     uint8_t rm0[EPT], rm1[EPT];
     if (SRC != SRC_VOLUME) {
 #pragma unroll
         for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * nthr;
             fc0[i] = R(0);
             fc1[i] = R(0);
             rm0[i] = 0xff;
             rm1[i] = 0xff;
-            if (e < nel) {
-                int row, n;
-                split_index(tid, i, nthr, H, inv_H, row, n);
+            int row, n;
+            if (elem(i, row, n)) {
                 const size_t p = (size_t)(y0 + row) * M + 2 * n;
                 const C2<R> fv = *reinterpret_cast<const C2<R>*>(f + p);
                 const uint16_t mv = *reinterpret_cast<const uint16_t*>(mask + p);
@@ -92,14 +102,12 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
     }
 
     for (int s = s_begin; s < s_end; ++s) {
-#pragma unroll
-        for (int i = 0; i < EPT; ++i) {
-            const int e = tid + i * nthr;
-            if (e < nel) {
-                C2<R> z;
+        // input element i of this slice (zero where unused)
+        auto input = [&](int i) {
+            C2<R> z = cmk<R>(R(0), R(0));
+            int row, n;
+            if (elem(i, row, n)) {
                 if (SRC == SRC_VOLUME) {
-                    int row, n;
-                    split_index(tid, i, nthr, H, inv_H, row, n);
                     z = *reinterpret_cast<const C2<R>*>(vol + ((size_t)s * M + y0 + row) * M + 2 * n);
                 } else if (SRC == SRC_LIFT) {
                     z.x = (rm0[i] == s) ? fc0[i] : R(0);
@@ -108,16 +116,20 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
                     z.x = fc0[i];
                     z.y = fc1[i];
                 }
-                int row, n;
-                split_index(tid, i, nthr, H, inv_H, row, n);
-                buf[lds_pad(row * S + n)] = z;
             }
-        }
-        __syncthreads();
-        if constexpr (MS != 0)
-            fft_static<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid);
-        else
+            return z;
+        };
+        if constexpr (MS != 0) {
+            fft_static_in<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid, input);
+        } else {
+#pragma unroll
+            for (int i = 0; i < EPT; ++i) {
+                int row, n;
+                if (elem(i, row, n)) buf[lds_pad(row * S + n)] = input(i);
+            }
+            __syncthreads();
             fft_lds<R, false, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
+        }
         // unpack the real transform and write (r, kx, y0..y0+rows) segments
         const int nout = rows * K;
         C2<R>* out = spec + (size_t)s * K * M + y0;
