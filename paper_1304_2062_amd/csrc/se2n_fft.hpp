@@ -378,22 +378,27 @@ __host__ __device__ constexpr int static_in_slots(int L, int NBATCH, int NTHR) {
     return (L / static_radix(L, 0) * NBATCH + NTHR - 1) / NTHR * static_radix(L, 0);
 }
 
-template <int L, int NBATCH, int NTHR>
+// Butterfly b of the first stage is (transform t, butterfly j): t = b / NB
+// (ROWFAST false: consecutive threads walk one transform) or t = b % NBATCH
+// (ROWFAST true: consecutive threads walk the transforms, which makes the
+// slots of 8 consecutive lanes one contiguous run of a transposed layout).
+template <int L, int NBATCH, int NTHR, bool ROWFAST = false>
 __device__ __forceinline__ bool static_in_pos(int tid, int slot, int& t, int& n) {
     constexpr int RADIX = static_radix(L, 0);
     constexpr int NB = L / RADIX;
     const int i = slot / RADIX, r = slot - (slot / RADIX) * RADIX;
     const int b = tid + i * NTHR;
-    t = b / NB;
-    n = (b - t * NB) + r * NB;
+    const int j = ROWFAST ? b / NBATCH : b - (b / NB) * NB;
+    t = ROWFAST ? b - j * NBATCH : b / NB;
+    n = j + r * NB;
     return b < NB * NBATCH;
 }
 
-// The transforms of fft_static with the first stage's inputs taken from
-// g(slot) (see static_in_pos) instead of LDS.  The caller guarantees that no
-// thread still reads the buffer (the first stage writes it at once).
-template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, class G>
-__device__ __forceinline__ void fft_static_in(C2<R>* buf, const C2<R>* twq, int tid, G&& g) {
+// First stage of fft_static with its inputs taken from g(slot) (see
+// static_in_pos) instead of LDS, followed by a barrier.  The caller
+// guarantees that no thread still reads the buffer.
+template <class R, bool INV, int L, int NBATCH, int BSTRIDE, int NTHR, bool ROWFAST, class G>
+__device__ __forceinline__ void fft_static_first(C2<R>* buf, int tid, G&& g) {
     constexpr int RADIX = static_radix(L, 0);
     constexpr int NB = L / RADIX;
     constexpr int TOTAL = NB * NBATCH;
@@ -402,8 +407,8 @@ __device__ __forceinline__ void fft_static_in(C2<R>* buf, const C2<R>* twq, int 
     for (int i = 0; i < MAXB; ++i) {
         const int b = tid + i * NTHR;
         if (TOTAL % NTHR == 0 || b < TOTAL) {
-            const int t = b / NB;
-            const int j = b - t * NB;
+            const int j = ROWFAST ? b / NBATCH : b - (b / NB) * NB;
+            const int t = ROWFAST ? b - j * NBATCH : b / NB;
             C2<R> v[RADIX];
 #pragma unroll
             for (int r = 0; r < RADIX; ++r) v[r] = g(i * RADIX + r);
@@ -413,7 +418,13 @@ __device__ __forceinline__ void fft_static_in(C2<R>* buf, const C2<R>* twq, int 
         }
     }
     __syncthreads();
-    fft_static<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, 1, RADIX>(buf, twq, tid);
+}
+
+// fft_static with the first stage's inputs from g(slot).
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, class G>
+__device__ __forceinline__ void fft_static_in(C2<R>* buf, const C2<R>* twq, int tid, G&& g) {
+    fft_static_first<R, INV, L, NBATCH, BSTRIDE, NTHR, false>(buf, tid, g);
+    fft_static<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, 1, static_radix(L, 0)>(buf, twq, tid);
 }
 
 // Radix of the last stage of a length-L transform, and the outputs each of

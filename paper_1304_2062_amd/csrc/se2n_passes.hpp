@@ -331,14 +331,34 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const int kstep = nthr >> rshift;
     const int KL = PAIRED ? H : K;       // columns the transform reads
     C2<R> pre[MAXL];
-#define SE2N_FETCH(SL)                                                                       \
-    do {                                                                                    \
-        const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;     \
-        _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < KL) pre[i] = \
-            in_[(size_t)(i * kstep) * M];                                                    \
+    // Fixed-size paired transforms take the first stage's inputs straight
+    // from the prefetch registers: slot i holds (row t, column n) of the
+    // thread's first-stage butterfly, rows fastest across lanes so that 8
+    // lanes read one 64-byte (slice, column) segment.
+    constexpr bool DIRECT = MS != 0 && PAIRED;
+    if constexpr (DIRECT)
+        static_assert(static_in_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one register per input");
+#define SE2N_FETCH(SL)                                                                                  \
+    do {                                                                                               \
+        if constexpr (DIRECT) {                                                                        \
+            _Pragma("unroll") for (int i = 0; i < EPT; ++i) {                                          \
+                int t_, n_;                                                                            \
+                if (static_in_pos<MS / 2, GC.rows, GC.row_threads, true>(tid, i, t_, n_))              \
+                    pre[i] = spec[(size_t)(SL) * K * M + (size_t)n_ * M + y0 + t_];                    \
+            }                                                                                          \
+        } else {                                                                                       \
+            const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;            \
+            _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < KL) pre[i] =        \
+                in_[(size_t)(i * kstep) * M];                                                          \
+        }                                                                                              \
     } while (0)
     SE2N_FETCH(s_begin);
     for (int s = s_begin; s < s_end; ++s) {
+      if constexpr (DIRECT) {
+        fft_static_first<R, true, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, true>(
+            buf, tid, [&](int i) { return pre[i]; });
+        if (s + 1 < s_end) SE2N_FETCH(s + 1);
+      } else {
 #pragma unroll
         for (int i = 0; i < MAXL; ++i) {
             const int kx = kx_t + i * kstep;
@@ -368,6 +388,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
         }
         __syncthreads();
         }
+      }
         // consume output element i (row, pixel pair n) of this slice
         auto take = [&](int i, int row, int n, C2<R> z) {
             if (DST == DST_VOLUME) {
@@ -384,7 +405,13 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
                 else acc2[i] = z;
             }
         };
-        if constexpr (MS != 0) {
+        if constexpr (DIRECT) {
+            // stages 2.. with the last stage's outputs going to the accumulators
+            constexpr int R0 = static_radix(MS / 2, 0);
+            static_assert(static_out_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one accumulator per output");
+            fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
+                buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+        } else if constexpr (MS != 0) {
             // the last stage's outputs go straight to the accumulators
             static_assert(static_out_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one accumulator per output");
             fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
