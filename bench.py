@@ -62,7 +62,7 @@ def algorithmic_bytes(M: int, N: int, real: int = 4) -> dict:
 ROCPROF_NAME = {
     "lift_row_fwd": r"k_row_fwd<float,0,",
     "col_fft_fwd": r"k_col_fft<float,false,",
-    "col_fft_inv": r"k_col_fft<float,true,",
+    "col_fft_inv": r"k_col_inv_paired<float,",
     "solve": r"k_solve<float,",
     "row_inv_max": r"k_row_inv<float,0,",
 }
