@@ -293,7 +293,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--beta", type=float, default=1.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-crop", type=int, default=512)
+    ap.add_argument("--cpu-crop", type=int, default=1024)
     ap.add_argument("--no-fp64-check", action="store_true")
     ap.add_argument("--workload", choices=("single", "batch", "corrector"), default="single",
                     help="single: the 2048^2 N=32 inpaint; batch: the 64-image heterogeneous batch; "
