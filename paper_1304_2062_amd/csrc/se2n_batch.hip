@@ -20,13 +20,14 @@ namespace se2n {
 namespace {
 
 constexpr int BT = kBatchThreads;
-// the fixed-size bodies assume their own thread counts: they must be BT
-static_assert(geom_core<float>(1024).row_threads == BT && geom_core<float>(1024).col_threads == BT,
-              "fixed-size row/column bodies for M=1024 need 512 threads");
-static_assert(geom_core<float>(512).row_threads == BT && geom_core<float>(512).col_threads == BT,
-              "fixed-size row/column bodies for M=512 need 512 threads");
-static_assert(geom_core<float>(1024).tw_full == 1 && geom_core<float>(512).tw_full == 1,
-              "fixed-size row bodies use the full twiddle table");
+
+// Threads of the row and column kernels of a size class (MS = 0: generic).
+template <int MS>
+constexpr int row_nt() { return MS ? geom_core<float>(MS).row_threads : BT; }
+template <int MS>
+constexpr int col_nt() { return MS ? geom_core<float>(MS).col_threads : BT; }
+static_assert(row_nt<1024>() <= BT && row_nt<768>() <= BT && row_nt<192>() <= BT && col_nt<192>() <= BT,
+              "no batched kernel exceeds the launch bound");
 
 using C = C2<float>;
 
@@ -46,9 +47,9 @@ __device__ __forceinline__ const BItem& item_of(const BItem* __restrict__ items,
 // Expand the image's quarter table into LDS unless it is already there.
 // Called right after a barrier, so no thread still reads the old table.
 template <bool FULL>
-__device__ __forceinline__ void ensure_twiddles(C* tw, const C* src, int M, const C*& cur) {
+__device__ __forceinline__ void ensure_twiddles(C* tw, const C* src, int M, const C*& cur, int nthr) {
     if (src != cur) {
-        load_twiddles<float>(tw, src, M >> 2, FULL, threadIdx.x, BT);
+        load_twiddles<float>(tw, src, M >> 2, FULL, threadIdx.x, nthr);
         cur = src;
     }
 }
@@ -80,7 +81,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         const int M = MS ? MS : uni(d.M);
         C* buf = tw + tw_elems(M, true);
         __syncthreads();
-        ensure_twiddles<true>(tw, uni(d.tw), M, cur);
+        ensure_twiddles<true>(tw, uni(d.tw), M, cur, row_nt<MS>());
         row_fwd_tile<float, SRC, 8, true, MS>(uni(d.f), uni(d.mask), SRC == SRC_LIFT ? uni(d.rmap) : nullptr, nullptr,
                                               uni(d.spec), M, uni(d.rows), BT, tl.y, tl.z, tl.w, d.planH, tw, buf,
                                               opaque_tid());
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         C* buf = tw + tw_elems(M, false);
         const long ncols = (long)uni(d.N) * (M / 2 + 1);
         __syncthreads();
-        ensure_twiddles<false>(tw, uni(d.tw), M, cur);
+        ensure_twiddles<false>(tw, uni(d.tw), M, cur, col_nt<MS>());
         col_fft_tile<float, INV, 8, false, MS>(uni(d.spec), ncols, M, uni(d.cols), BT, tl.y, d.planM, tw, buf,
                                                opaque_tid());
     }
@@ -117,7 +118,7 @@ __global__ __launch_bounds__(BT) void kb_col_orient(const BItem* __restrict__ it
         const int M = uni(d.M);
         C* buf = tw + tw_elems(M, false);
         __syncthreads();
-        ensure_twiddles<false>(tw, uni(d.tw), M, cur);
+        ensure_twiddles<false>(tw, uni(d.tw), M, cur, BT);
         col_orient_tile<float, 8, false>(uni(d.spec), M, uni(d.ocols), BT, tl.y, d.planM, tw, buf, uni(d.ocoef),
                                          uni(d.oscale), opaque_tid());
     }
@@ -139,7 +140,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         const int N = uni(d.N);
         C* buf = tw + tw_elems(M, true);
         __syncthreads();
-        ensure_twiddles<true>(tw, uni(d.tw), M, cur);
+        ensure_twiddles<true>(tw, uni(d.tw), M, cur, row_nt<MS>());
         unsigned* enc = (DST == DST_MAX && uni(d.groups) > 1) ? uni(d.enc) : nullptr;
         const float sc = DST == DST_SUM ? 1.0f / (float)N : 1.0f;
         row_inv_tile<float, DST, 8, true, MS>(uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
@@ -188,50 +189,60 @@ struct SolveCfg {
 };
 
 // Calls f(kernel pointer, threads) for the kernel of a pass; `cls` selects
-// the size class of the row and column kernels (0 generic, 1: M = 512,
-// 2: M = 1024), N the solve instance.
+// the size class of the row and column kernels (kBatchSides), N the solve
+// instance.
+#define SE2N_BY_CLASS(KT, NT)                                                          \
+    switch (cls) {                                                                     \
+        case 1: return f((const void*)KT(128), NT<128>());                             \
+        case 2: return f((const void*)KT(192), NT<192>());                             \
+        case 3: return f((const void*)KT(256), NT<256>());                             \
+        case 4: return f((const void*)KT(384), NT<384>());                             \
+        case 5: return f((const void*)KT(512), NT<512>());                             \
+        case 6: return f((const void*)KT(768), NT<768>());                             \
+        case 7: return f((const void*)KT(1024), NT<1024>());                           \
+        default: return f((const void*)KT(0), NT<0>());                                \
+    }
+static_assert(kBatchClasses == 8 && kBatchSides[1] == 128 && kBatchSides[7] == 1024, "class table");
+
 template <class F>
 hipError_t with_kernel(int kind, int N, int cls, F&& f) {
-#define SE2N_BY_CLASS(K)                                        \
-    (cls == 2 ? (const void*)K<1024> : cls == 1 ? (const void*)K<512> : (const void*)K<0>)
     switch (kind) {
         case BK_ORIENT_ROW: {
 #define K_(m) kb_row_fwd<SRC_IMAGE, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
         case BK_LIFT_ROW: {
 #define K_(m) kb_row_fwd<SRC_LIFT, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
         case BK_ORIENT_COL: return f((const void*)kb_col_orient, BT);
         case BK_ORIENT_INV: {
 #define K_(m) kb_row_inv<DST_ORIENT, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
         case BK_ROW_INV_MAX: {
 #define K_(m) kb_row_inv<DST_MAX, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
         case BK_ROW_INV_MEAN: {
 #define K_(m) kb_row_inv<DST_SUM, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
         case BK_COL_FWD: {
 #define K_(m) kb_col_fft<false, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, col_nt)
 #undef K_
         }
         case BK_COL_INV: {
 #define K_(m) kb_col_fft<true, m>
-            return f(cls == 2 ? (const void*)K_(1024) : cls == 1 ? (const void*)K_(512) : (const void*)K_(0), BT);
+            SE2N_BY_CLASS(K_, col_nt)
 #undef K_
         }
-#undef SE2N_BY_CLASS
         case BK_FILL: return f((const void*)kb_enc<false>, BT);
         case BK_DECODE: return f((const void*)kb_enc<true>, BT);
         case BK_SOLVE:
@@ -251,6 +262,7 @@ hipError_t with_kernel(int kind, int N, int cls, F&& f) {
         default: return hipErrorInvalidValue;
     }
 }
+#undef SE2N_BY_CLASS
 
 }  // namespace
 

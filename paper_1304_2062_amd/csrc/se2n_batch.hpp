@@ -44,14 +44,21 @@ enum BatchKind {
     BK_COUNT
 };
 
-constexpr int kBatchThreads = 512;  // block size of every batched FFT / elementwise kernel
+constexpr int kBatchThreads = 512;  // block size of the generic and elementwise batched kernels
 constexpr int kBatchMaxM = 1024;    // largest M the batched kernels are built for
 
 // Threads per block of a pass (the solve's depends on N).
 int batch_threads(int kind, int N);
-// Size class of the row and column kernels: 2 for M = 1024, 1 for M = 512
-// (bodies compiled for that side), 0 for every other side.
-inline int batch_class(int M) { return M == 1024 ? 2 : (M == 512 ? 1 : 0); }
+// Size classes of the batched row and column kernels: class c > 0 runs the
+// bodies compiled for side kBatchSides[c] (with that side's own thread
+// counts), class 0 the generic body for every other side.
+constexpr int kBatchClasses = 8;
+constexpr int kBatchSides[kBatchClasses] = {0, 128, 192, 256, 384, 512, 768, 1024};
+inline int batch_class(int M) {
+    for (int c = 1; c < kBatchClasses; ++c)
+        if (kBatchSides[c] == M) return c;
+    return 0;
+}
 
 // Launch one pass (size class `cls`, solve instance N): `grid` workgroups
 // walk tiles[0..ntiles) with stride grid.

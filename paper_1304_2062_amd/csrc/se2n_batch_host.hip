@@ -460,7 +460,7 @@ int build_schedule(BatchPlan& bp) {
             if (!all.empty()) parts.push_back(Part{kind, 0, 0, std::move(all)});
             return;
         }
-        for (int cls = 2; cls >= 0; --cls) {
+        for (int cls = kBatchClasses - 1; cls >= 0; --cls) {
             const int kinds[2] = {kind == BK_ROW_INV_MAX ? BK_ROW_INV_MAX : kind,
                                   kind == BK_ROW_INV_MAX ? BK_ROW_INV_MEAN : -1};
             for (int k : kinds) {

@@ -67,20 +67,23 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
     // of the thread is (row, pixel pair n) of its first-stage butterfly inputs
     // (fixed-size transforms, which take them from registers) or of the
     // natural order e = tid + i*nthr (else).
+    // registers per thread: EPT, or the first stage's input slots if more
+    constexpr int NIN = MS != 0 && static_in_slots(MS ? MS / 2 : 8, GC.rows, GC.row_threads) > EPT
+                            ? static_in_slots(MS ? MS / 2 : 8, GC.rows, GC.row_threads)
+                            : EPT;
     auto elem = [&](int i, int& row, int& n) {
         if constexpr (MS != 0) {
-            static_assert(static_in_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one register per input");
             return static_in_pos<MS / 2, GC.rows, GC.row_threads>(tid, i, row, n);
         } else {
             split_index(tid, i, nthr, H, inv_H, row, n);
             return tid + i * nthr < nel;
         }
     };
-    R fc0[EPT], fc1[EPT];
-    uint8_t rm0[EPT], rm1[EPT];
+    R fc0[NIN], fc1[NIN];
+    uint8_t rm0[NIN], rm1[NIN];
     if (SRC != SRC_VOLUME) {
 #pragma unroll
-        for (int i = 0; i < EPT; ++i) {
+        for (int i = 0; i < NIN; ++i) {
             fc0[i] = R(0);
             fc1[i] = R(0);
             rm0[i] = 0xff;
@@ -313,9 +316,13 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const int nel = rows * H;
     const float inv_H = 1.0f / (float)H;
 
-    C2<R> acc[EPT], acc2[EPT];
+    // accumulators per thread: EPT, or the last stage's output slots if more
+    constexpr int NOUT = MS != 0 && static_out_slots(MS ? MS / 2 : 8, GC.rows, GC.row_threads) > EPT
+                             ? static_out_slots(MS ? MS / 2 : 8, GC.rows, GC.row_threads)
+                             : EPT;
+    C2<R> acc[NOUT], acc2[NOUT];
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
+    for (int i = 0; i < NOUT; ++i) {
         const R init = (DST == DST_MAX) ? -INFINITY : R(0);
         acc[i] = cmk<R>(init, init);
         acc2[i] = cmk<R>(R(0), R(0));
@@ -337,11 +344,11 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     // lanes read one 64-byte (slice, column) segment.
     constexpr bool DIRECT = MS != 0 && PAIRED;
     if constexpr (DIRECT)
-        static_assert(static_in_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one register per input");
+        static_assert(static_in_slots(MS / 2, GC.rows, GC.row_threads) <= MAXL, "one register per input");
 #define SE2N_FETCH(SL)                                                                                  \
     do {                                                                                               \
         if constexpr (DIRECT) {                                                                        \
-            _Pragma("unroll") for (int i = 0; i < EPT; ++i) {                                          \
+            _Pragma("unroll") for (int i = 0; i < static_in_slots(MS / 2, GC.rows, GC.row_threads); ++i) { \
                 int t_, n_;                                                                            \
                 if (static_in_pos<MS / 2, GC.rows, GC.row_threads, true>(tid, i, t_, n_))              \
                     pre[i] = spec[(size_t)(SL) * K * M + (size_t)n_ * M + y0 + t_];                    \
@@ -408,12 +415,10 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
         if constexpr (DIRECT) {
             // stages 2.. with the last stage's outputs going to the accumulators
             constexpr int R0 = static_radix(MS / 2, 0);
-            static_assert(static_out_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one accumulator per output");
             fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
                 buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
         } else if constexpr (MS != 0) {
             // the last stage's outputs go straight to the accumulators
-            static_assert(static_out_slots(MS / 2, GC.rows, GC.row_threads) == EPT, "one accumulator per output");
             fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
                 buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
         } else {
@@ -434,7 +439,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
 
     if (DST == DST_VOLUME) return;
 #pragma unroll
-    for (int i = 0; i < EPT; ++i) {
+    for (int i = 0; i < NOUT; ++i) {
         int row, n;
         bool valid;
         if constexpr (MS != 0) {
