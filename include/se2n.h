@@ -262,10 +262,13 @@ int se2n_batch_get_tune(const se2n_item *items, int count, se2n_tune *out);
  *   pass 1 orientation columns  {item, first column kx, 0, 0}
  *   pass 2 orientation inverse  {item, row block, 0, 2}
  *   pass 3 lift + row FFT       {item, row block, first slice, end slice}
- *   pass 4 column FFT (fwd and inverse share it) {item, first column, 0, 0}
+ *   pass 4 forward column FFT   {item, first column, 0, 0}
  *   pass 5 per-mode propagation {item, lx, first ly, N}
  *   pass 6 inverse rows         {item, row block, first slice, end slice}
  *   pass 7 max clear / decode   {item, first pixel, pixel count, 0}
+ *   pass 8 inverse column FFT on column pairs (k, M/2-k) with the pairing
+ *          step of the real inverse row transform
+ *                               {item, slice * blocks + pair block, 0, 0}
  * tiles may be NULL to query *ntiles only; at most `capacity` tiles are
  * written.  Host only, no device work.
  * Errors: SE2N_EINVAL. */

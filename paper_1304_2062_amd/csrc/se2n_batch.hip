@@ -26,6 +26,8 @@ template <int MS>
 constexpr int row_nt() { return MS ? geom_core<float>(MS).row_threads : BT; }
 template <int MS>
 constexpr int col_nt() { return MS ? geom_core<float>(MS).col_threads : BT; }
+template <int MS>
+constexpr int pcol_nt() { return MS ? geom_core<float>(MS).pcol_threads : BT; }
 static_assert(row_nt<1024>() <= BT && row_nt<768>() <= BT && row_nt<192>() <= BT && col_nt<192>() <= BT,
               "no batched kernel exceeds the launch bound");
 
@@ -107,6 +109,25 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
     }
 }
 
+// Inverse column pass on column pairs with the pairing step of the real
+// inverse row transform (tile = linear pair-block index within the image).
+template <int MS>
+__global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb_col_inv_paired(
+    const BItem* __restrict__ items, const int4* __restrict__ tiles, int ntiles) {
+    extern __shared__ unsigned char smem_raw[];
+    C* tw = reinterpret_cast<C*>(smem_raw);
+    const C* cur = nullptr;
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        const int M = MS ? MS : uni(d.M);
+        C* buf = tw + tw_elems(M, false);
+        __syncthreads();
+        ensure_twiddles<false>(tw, uni(d.tw), M, cur, pcol_nt<MS>());
+        col_inv_paired_tile<float, 8, MS>(uni(d.spec), M, uni(d.pcols), BT, tl.y, d.planM, tw, buf, opaque_tid());
+    }
+}
+
 __global__ __launch_bounds__(BT) void kb_col_orient(const BItem* __restrict__ items, const int4* __restrict__ tiles,
                                                     int ntiles) {
     extern __shared__ unsigned char smem_raw[];
@@ -127,7 +148,7 @@ __global__ __launch_bounds__(BT) void kb_col_orient(const BItem* __restrict__ it
 // Inverse row pass: orientation binning (DST_ORIENT), max projection
 // (DST_MAX: written directly with one slice group, else combined through the
 // item's atomic buffer) or mean projection (DST_SUM, one slice group).
-template <int DST, int MS>
+template <int DST, int MS, bool PAIRED = false>
 __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb_row_inv(const BItem* __restrict__ items, const int4* __restrict__ tiles,
                                                  int ntiles) {
     extern __shared__ unsigned char smem_raw[];
@@ -143,7 +164,7 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         ensure_twiddles<true>(tw, uni(d.tw), M, cur, row_nt<MS>());
         unsigned* enc = (DST == DST_MAX && uni(d.groups) > 1) ? uni(d.enc) : nullptr;
         const float sc = DST == DST_SUM ? 1.0f / (float)N : 1.0f;
-        row_inv_tile<float, DST, 8, true, MS>(uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
+        row_inv_tile<float, DST, 8, true, MS, PAIRED>(uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
                                               DST == DST_ORIENT ? uni(d.rmap) : nullptr, M, uni(d.rows), BT, tl.y,
                                               tl.z, tl.w, N, sc, d.planH, tw, buf, opaque_tid());
     }
@@ -224,12 +245,12 @@ hipError_t with_kernel(int kind, int N, int cls, F&& f) {
 #undef K_
         }
         case BK_ROW_INV_MAX: {
-#define K_(m) kb_row_inv<DST_MAX, m>
+#define K_(m) kb_row_inv<DST_MAX, m, true>
             SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
         case BK_ROW_INV_MEAN: {
-#define K_(m) kb_row_inv<DST_SUM, m>
+#define K_(m) kb_row_inv<DST_SUM, m, true>
             SE2N_BY_CLASS(K_, row_nt)
 #undef K_
         }
@@ -239,8 +260,8 @@ hipError_t with_kernel(int kind, int N, int cls, F&& f) {
 #undef K_
         }
         case BK_COL_INV: {
-#define K_(m) kb_col_fft<true, m>
-            SE2N_BY_CLASS(K_, col_nt)
+#define K_(m) kb_col_inv_paired<m>
+            SE2N_BY_CLASS(K_, pcol_nt)
 #undef K_
         }
         case BK_FILL: return f((const void*)kb_enc<false>, BT);

@@ -197,6 +197,18 @@ std::vector<Tile> raw_tiles(const std::vector<Shape>& sh, const se2n_tune& t, in
                         out.push_back({make_int4(i, lx, ly, N), (double)std::min(cls, Q - ly) * 8.0 * N * N});
                 break;
             }
+            case 8: {
+                // inverse column pass on column pairs (k, H-k), k = 0 .. H/2,
+                // pcols/2 pairs per tile; the tile is the linear index
+                // slice * tiles_per_slice + pair block
+                const int P = g.pcols / 2;
+                const int tps = (H / 2 + 1 + P - 1) / P;
+                for (int tt = 0; tt < N * tps; ++tt) {
+                    const int np = std::min(P, H / 2 + 1 - (tt % tps) * P);
+                    out.push_back({make_int4(i, tt, 0, 0), (double)2 * np * M * lg2(M)});
+                }
+                break;
+            }
             case 7:
                 if (x.proj == SE2N_PROJ_MAX && groups_of(x, t) > 1) {
                     const int npx = M * M;
@@ -483,7 +495,7 @@ int build_schedule(BatchPlan& bp) {
     add_pass(BK_LIFT_ROW, 3);
     add_pass(BK_COL_FWD, 4);
     add_pass(BK_SOLVE, 5);
-    add_pass(BK_COL_INV, 4);
+    add_pass(BK_COL_INV, 8);
     add_pass(BK_FILL, 7);
     add_pass(BK_ROW_INV_MAX, 6);
     add_pass(BK_DECODE, 7);
@@ -516,8 +528,10 @@ int build_schedule(BatchPlan& bp) {
                     need = (size_t)(tw_elems(M, true) + lds_padded_size(g.rows * (H + 2))) * sizeof(C2<float>);
                     break;
                 case BK_COL_FWD:
-                case BK_COL_INV:
                     need = (size_t)(tw_elems(M, false) + lds_padded_size(g.cols * M)) * sizeof(C2<float>);
+                    break;
+                case BK_COL_INV:
+                    need = (size_t)(tw_elems(M, false) + lds_padded_size(g.pcols * M)) * sizeof(C2<float>);
                     break;
                 case BK_ORIENT_COL:
                     need = (size_t)(tw_elems(M, false) + lds_padded_size(2 * g.ocols * M)) * sizeof(C2<float>);
@@ -620,6 +634,7 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         b.rows = g.rows;
         b.cols = g.cols;
         b.ocols = g.ocols;
+        b.pcols = g.pcols;
         b.proj = x.proj;
         b.groups = groups_of(x, bp.tune);
         b.Q = M / 4 + 1;
@@ -631,7 +646,8 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         // the invariants the batched bodies rely on (512 threads, 8 elements each)
         const int H = M / 2;
         if (g.rows * H > 8 * kBatchThreads || g.cols * M > 8 * kBatchThreads ||
-            2 * g.ocols * M > 8 * kBatchThreads || kBatchThreads % g.rows != 0 || g.tw_full != 1)
+            2 * g.ocols * M > 8 * kBatchThreads || g.pcols * M > 8 * kBatchThreads ||
+            kBatchThreads % g.rows != 0 || g.tw_full != 1)
             return fail(SE2N_EUNSUPPORTED, "item %d: no batched geometry for M=%d", i, M);
     }
     return build_schedule(bp);
@@ -875,7 +891,7 @@ int se2n_batch_tiles(const se2n_item* items, int count, const se2n_tune* tune, i
     int rc = check_items(items, count, false);
     if (rc) return rc;
     if (!ntiles) return fail(SE2N_EINVAL, "ntiles is NULL");
-    if (pass < 0 || pass > 7) return fail(SE2N_EINVAL, "pass must lie in [0, 7] (got %d)", pass);
+    if (pass < 0 || pass > 8) return fail(SE2N_EINVAL, "pass must lie in [0, 8] (got %d)", pass);
     if (tiles && capacity < 0) return fail(SE2N_EINVAL, "capacity must be >= 0");
     se2n_tune t = kDefaultTune;
     if (tune) {

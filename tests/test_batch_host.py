@@ -55,6 +55,11 @@ def geometry(M):
     return rows, cols, ocols
 
 
+def paired_cols(M):
+    _, cols, _ = geometry(M)
+    return cols & ~1 if cols >= 2 else 2
+
+
 def solve_classes(N):
     h = N // 2
     E = h * (h + 1)
@@ -120,6 +125,22 @@ def test_column_tiles_partition_every_column_run(lib, tune):
 
 
 @pytest.mark.parametrize("tune", TUNES)
+def test_paired_inverse_column_tiles_cover_every_pair_once(lib, tune):
+    """Pass 8: per slice the pairs (k, M/2-k), k = 0 .. M/4, in blocks of
+    pcols/2 pairs; tile = slice * blocks + block."""
+    arr = items_of(SPECS)
+    pc = tiles(lib, arr, 8, tune)
+    for i, (M, N, _) in enumerate(SPECS):
+        P = paired_cols(M) // 2
+        blocks = -(-(M // 4 + 1) // P)
+        got = sorted(t[1] for t in pc if t[0] == i)
+        assert got == list(range(N * blocks))
+        pairs = sorted({(tt // blocks, k) for tt in got
+                        for k in range((tt % blocks) * P, min((tt % blocks + 1) * P, M // 4 + 1))})
+        assert pairs == [(r, k) for r in range(N) for k in range(M // 4 + 1)]
+
+
+@pytest.mark.parametrize("tune", TUNES)
 def test_solve_tiles_cover_every_frequency_class_once(lib, tune):
     arr = items_of(SPECS)
     sol = tiles(lib, arr, 5, tune)
@@ -149,7 +170,7 @@ def test_clear_tiles_exist_exactly_for_max_items_with_slice_groups(lib, tune):
 
 def test_orders_are_permutations_and_largest_first_puts_big_images_first(lib):
     arr = items_of(SPECS)
-    for pass_ in range(8):
+    for pass_ in range(9):
         a = tiles(lib, arr, pass_, (2, 0, 2))
         b = tiles(lib, arr, pass_, (2, 1, 2))
         assert sorted(a) == sorted(b)
@@ -187,7 +208,7 @@ def test_bad_counts_tunes_and_passes(lib):
     n = ctypes.c_int(0)
     assert lib.se2n_batch_workspace_bytes(arr, 0) == 0
     assert lib.se2n_batch_workspace_bytes(None, 1) == 0
-    assert lib.se2n_batch_tiles(arr, 2, None, 8, None, 0, ctypes.byref(n)) == -1
+    assert lib.se2n_batch_tiles(arr, 2, None, 9, None, 0, ctypes.byref(n)) == -1
     assert lib.se2n_batch_tiles(arr, 2, ctypes.byref(Tune(17, 0, 1, 0)), 0, None, 0, ctypes.byref(n)) == -1
     assert lib.se2n_batch_tiles(arr, 2, ctypes.byref(Tune(1, 2, 1, 0)), 0, None, 0, ctypes.byref(n)) == -1
     assert lib.se2n_batch_tiles(arr, 2, ctypes.byref(Tune(1, 0, 0, 0)), 0, None, 0, ctypes.byref(n)) == -1
