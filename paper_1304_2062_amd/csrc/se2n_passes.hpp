@@ -209,12 +209,21 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
     C2<R>* base = spec + (size_t)r * K * M;
     const float inv_M = 1.0f / (float)M;
     const int nel = 2 * np * M;
+    // LDS column q < np holds column k = p0 + q, column np + q its partner
+    // H - k: the tile reads two contiguous runs, columns p0 .. p0+np-1 and
+    // H-p0-np+1 .. H-p0 (the self-paired column M/4 is read twice).
+    const int half = np * M;
+    const int c2 = H - p0 - np + 1;
     for (int e = tid; e < nel; e += nthr) {
-        const int cc = fdiv(e, inv_M);
-        const int y = e - cc * M;
-        const int k = p0 + (cc >> 1);
-        const int kx = (cc & 1) ? H - k : k;
-        buf[lds_pad(e)] = base[(size_t)kx * M + y];
+        if (e < half) {
+            buf[lds_pad(e)] = base[(size_t)p0 * M + e];
+        } else {
+            const int e2 = e - half;
+            const int cm = fdiv(e2, inv_M);           // memory column c2 + cm = H - p0 - q
+            const int y = e2 - cm * M;
+            const int q = np - 1 - cm;
+            buf[lds_pad(half + q * M + y)] = base[(size_t)c2 * M + e2];
+        }
     }
     __syncthreads();
     if constexpr (MS != 0) {
@@ -228,8 +237,8 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
         const int y = e - q * M;
         const int k = p0 + q;
         const int kk = H - k;
-        const C2<R> a = buf[lds_pad(2 * q * M + y)];
-        const C2<R> b = buf[lds_pad((2 * q + 1) * M + y)];
+        const C2<R> a = buf[lds_pad(q * M + y)];
+        const C2<R> b = buf[lds_pad(half + q * M + y)];
         const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
         const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
         const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, false>(tw, k, M4)), da);
