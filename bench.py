@@ -45,6 +45,7 @@ def algorithmic_bytes(M: int, N: int, real: int = 4) -> dict:
     h = N // 2
     table = Q * Q * h * (h + 1) * real
     return {
+        "orient_stencil": MM * real + 2 * MM,
         "orient_row_fwd": MM * real + MM + K * M * c,
         "orient_col": 3 * K * M * c,
         "orient_row_inv": 2 * K * M * c + MM,
@@ -112,7 +113,8 @@ def batch_algorithmic_bytes(params) -> dict:
     acc = {}
     for p in params:
         a = algorithmic_bytes(p["M"], p["N"], 4)
-        for k, b in (("b_orient_row_fwd", a["orient_row_fwd"]), ("b_orient_col", a["orient_col"]),
+        for k, b in (("b_orient_stencil", a["orient_stencil"]),
+                     ("b_orient_row_fwd", a["orient_row_fwd"]), ("b_orient_col", a["orient_col"]),
                      ("b_orient_row_inv", a["orient_row_inv"]), ("b_lift_row_fwd", a["lift_row_fwd"]),
                      ("b_col_fft_fwd", a["col_fft_fwd"]), ("b_col_fft_inv", a["col_fft_inv"]),
                      ("b_solve_N%d" % p["N"], a["solve"]), ("b_row_inv_max", a["row_inv_max"])):

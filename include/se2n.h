@@ -109,6 +109,27 @@ int se2n_precompute(se2n_plan plan, double T, double beta, int n_steps,
 int se2n_orient(se2n_plan plan, const void *f, const uint8_t *mask, double sigma,
                 uint8_t *rmap, void *workspace, void *stream);
 
+/* Which route se2n_orient (and se2n_inpaint without rmap_in) takes for sigma.
+ * Both multipliers of the orientation step factor into an x part and a y
+ * part, so the smoothed gradient is a separable circular convolution with
+ * their inverse DFTs.  FP32 plans use that stencil when both kernels' tails
+ * beyond some radius, or the whole circle, stay below 2^-26 of their
+ * absolute sums and a compiled radius (8 .. 32) covers it: *radius receives
+ * that compiled radius.  Otherwise (FP64 plans, wide or very narrow
+ * Gaussians on large grids) the FFT route runs and *radius is 0.  The taps
+ * are computed on the host in FP64, O(M^2) work, once per plan and sigma.
+ * Errors: SE2N_EINVAL (null radius, sigma <= 0), SE2N_ESTATE. */
+int se2n_orient_method(se2n_plan plan, double sigma, int *radius);
+
+/* The stencil's taps themselves (host only, no device needed): for side M
+ * (as se2n_plan_create) and sigma > 0, g[0..64] and d[0..64] receive the
+ * correlation weights of offsets j = -32 .. 32 (index j + 32) of the
+ * smoothing kernel and of the smoothed central difference, rounded to FP32,
+ * zero beyond the radius; *radius receives the compiled radius, or 0 when
+ * the stencil is not used at any precision (then g and d are untouched).
+ * Errors: SE2N_EINVAL (bad M, sigma, null pointer). */
+int se2n_orient_stencil_taps(int M, double sigma, float *g, float *d, int *radius);
+
 /* Lift: psi[r][y][x] = f[y][x]*(1-mask[y][x]) if rmap[y][x] == r, else 0.
  *   psi [N][M][M] real out.  rmap values must be < N (not checked on device:
  *   a larger value lifts the pixel to no orientation).
@@ -261,6 +282,8 @@ int se2n_batch_get_tune(const se2n_item *items, int count, se2n_tune *out);
  *   pass 0 orientation rows     {item, row block, 0, 1}
  *   pass 1 orientation columns  {item, first column kx, 0, 0}
  *   pass 2 orientation inverse  {item, row block, 0, 2}
+ *          (passes 0-2 hold the items whose orientation takes the FFT
+ *          route, see se2n_orient_method; pass 9 holds the others)
  *   pass 3 lift + row FFT       {item, row block, first slice, end slice}
  *   pass 4 forward column FFT   {item, first column, 0, 0}
  *   pass 5 per-mode propagation {item, lx, first ly, N}
@@ -269,6 +292,7 @@ int se2n_batch_get_tune(const se2n_item *items, int count, se2n_tune *out);
  *   pass 8 inverse column FFT on column pairs (k, M/2-k) with the pairing
  *          step of the real inverse row transform
  *                               {item, slice * blocks + pair block, 0, 0}
+ *   pass 9 orientation stencil  {item, 64 x 64 tile (row-major), radius, 0}
  * tiles may be NULL to query *ntiles only; at most `capacity` tiles are
  * written.  Host only, no device work.
  * Errors: SE2N_EINVAL. */

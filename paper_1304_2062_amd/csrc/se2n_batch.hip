@@ -13,6 +13,7 @@
 #include "se2n_batch.hpp"
 #include "se2n_fft.hpp"
 #include "se2n_internal.hpp"
+#include "se2n_orient.hpp"
 #include "se2n_passes.hpp"
 
 namespace se2n {
@@ -145,6 +146,23 @@ __global__ __launch_bounds__(BT) void kb_col_orient(const BItem* __restrict__ it
     }
 }
 
+// Orientation stencil over the tiles of images that share (M, sigma), hence
+// the taps.
+template <int RAD>
+__global__ __launch_bounds__(kOrientNT) void kb_orient_stencil(const BItem* __restrict__ items,
+                                                               const int4* __restrict__ tiles, int ntiles,
+                                                               OrientTaps taps) {
+    __shared__ float sa[orient_lds_floats<RAD>()];
+    __shared__ float sb[orient_lds_floats<RAD>()];
+    for (int t = blockIdx.x; t < ntiles; t += gridDim.x) {
+        const int4 tl = tiles[t];
+        const BItem& d = item_of(items, tl.x);
+        __syncthreads();
+        orient_stencil_tile<RAD>(uni(d.f), uni(d.mask), uni(d.rmap), uni(d.M), uni(d.N), tl.y, taps, sa, sb,
+                                 opaque_tid());
+    }
+}
+
 // Inverse row pass: orientation binning (DST_ORIENT), max projection
 // (DST_MAX: written directly with one slice group, else combined through the
 // item's atomic buffer) or mean projection (DST_SUM, one slice group).
@@ -264,6 +282,16 @@ hipError_t with_kernel(int kind, int N, int cls, F&& f) {
             SE2N_BY_CLASS(K_, pcol_nt)
 #undef K_
         }
+        case BK_ORIENT_STENCIL:
+            switch (cls) {
+                case 8: return f((const void*)kb_orient_stencil<8>, kOrientNT);
+                case 12: return f((const void*)kb_orient_stencil<12>, kOrientNT);
+                case 16: return f((const void*)kb_orient_stencil<16>, kOrientNT);
+                case 20: return f((const void*)kb_orient_stencil<20>, kOrientNT);
+                case 24: return f((const void*)kb_orient_stencil<24>, kOrientNT);
+                case 32: return f((const void*)kb_orient_stencil<32>, kOrientNT);
+                default: return hipErrorInvalidValue;
+            }
         case BK_FILL: return f((const void*)kb_enc<false>, BT);
         case BK_DECODE: return f((const void*)kb_enc<true>, BT);
         case BK_SOLVE:
@@ -297,10 +325,13 @@ int batch_threads(int kind, int N) {
 }
 
 hipError_t launch_batch(int kind, int N, int cls, const BItem* items, const int4* tiles, int ntiles, int grid,
-                        size_t lds, hipStream_t st) {
+                        size_t lds, hipStream_t st, const OrientTaps* taps) {
     if (ntiles <= 0) return hipSuccess;
+    if (kind == BK_ORIENT_STENCIL && !taps) return hipErrorInvalidValue;
+    OrientTaps tv{};
+    if (taps) tv = *taps;
     return with_kernel(kind, N, cls, [&](const void* fn, int threads) {
-        void* args[] = {(void*)&items, (void*)&tiles, (void*)&ntiles};
+        void* args[] = {(void*)&items, (void*)&tiles, (void*)&ntiles, (void*)&tv};
         return hipLaunchKernel(fn, dim3((unsigned)grid), dim3((unsigned)threads), args, lds, st);
     });
 }

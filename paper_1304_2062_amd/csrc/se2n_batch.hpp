@@ -41,6 +41,7 @@ enum BatchKind {
     BK_ROW_INV_MAX,
     BK_ROW_INV_MEAN,
     BK_DECODE,
+    BK_ORIENT_STENCIL,  // one launch per (M, sigma): `cls` is the radius, the taps are arguments
     BK_COUNT
 };
 
@@ -63,7 +64,7 @@ inline int batch_class(int M) {
 // Launch one pass (size class `cls`, solve instance N): `grid` workgroups
 // walk tiles[0..ntiles) with stride grid.
 hipError_t launch_batch(int kind, int N, int cls, const BItem* items, const int4* tiles, int ntiles, int grid,
-                        size_t lds, hipStream_t st);
+                        size_t lds, hipStream_t st, const OrientTaps* taps = nullptr);
 // Resident workgroups per compute unit of a pass's kernel with `lds` bytes.
 hipError_t batch_occupancy(int kind, int N, int cls, size_t lds, int* per_cu);
 

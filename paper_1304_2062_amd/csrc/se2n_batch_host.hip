@@ -22,6 +22,7 @@
 
 #include "../../include/se2n.h"
 #include "se2n_batch.hpp"
+#include "se2n_orient.hpp"
 #include "se2n_host.hpp"
 #include "se2n_internal.hpp"
 
@@ -161,15 +162,24 @@ std::vector<Tile> raw_tiles(const std::vector<Shape>& sh, const se2n_tune& t, in
         switch (pass) {
             case 0:
             case 2: {
+                if (orient_stencil_taps_cached(M, x.sigma, nullptr) > 0) break;
                 const int ns = pass == 0 ? 1 : 2;
                 for (int rb = 0; rb < nrb; ++rb)
                     out.push_back({make_int4(i, rb, 0, ns), (double)ns * g.rows * H * lg2(H)});
                 break;
             }
             case 1:
+                if (orient_stencil_taps_cached(M, x.sigma, nullptr) > 0) break;
                 for (int c = 0; c < K; c += g.ocols)
                     out.push_back({make_int4(i, c, 0, 0), 3.0 * std::min(g.ocols, K - c) * M * lg2(M)});
                 break;
+            case 9: {
+                const int rad = orient_stencil_taps_cached(M, x.sigma, nullptr);
+                if (rad == 0) break;
+                for (int tt = 0; tt < orient_tiles(M); ++tt)
+                    out.push_back({make_int4(i, tt, rad, 0), (double)kOrientTX * kOrientTY * (2 * rad + 1)});
+                break;
+            }
             case 3:
             case 6: {
                 const int grp = groups_of(x, t);
@@ -355,6 +365,7 @@ struct Launch {
     int ntiles, grid;
     size_t lds;
     size_t tile_off;  // into the plan's tile buffer, in int4
+    OrientTaps taps;  // BK_ORIENT_STENCIL only
 };
 
 const char* kind_name(int kind, int N) {
@@ -371,6 +382,7 @@ const char* kind_name(int kind, int N) {
         case BK_ROW_INV_MAX: return "b_row_inv_max";
         case BK_ROW_INV_MEAN: return "b_row_inv_mean";
         case BK_DECODE: return "b_decode_max";
+        case BK_ORIENT_STENCIL: return "b_orient_stencil";
         case BK_SOLVE:
             if (N >= 4 && N <= 64 && N % 2 == 0) {
                 const int k = N / 2;
@@ -451,17 +463,38 @@ int build_schedule(BatchPlan& bp) {
     struct Part {
         int kind, N, cls;
         std::vector<int4> tiles;
+        OrientTaps taps;
     };
     std::vector<Part> parts;
     auto add_pass = [&](int kind, int pass) {
         std::vector<int4> all = ordered_tiles(bp.shapes, bp.tune, pass);
+        if (kind == BK_ORIENT_STENCIL) {
+            // one launch per (M, sigma), largest sides first
+            std::vector<std::pair<int, double>> keys;
+            for (const int4& t : all) {
+                const std::pair<int, double> k(bp.shapes[t.x].M, bp.shapes[t.x].sigma);
+                if (std::find(keys.begin(), keys.end(), k) == keys.end()) keys.push_back(k);
+            }
+            std::stable_sort(keys.begin(), keys.end(),
+                             [](const std::pair<int, double>& a, const std::pair<int, double>& b) {
+                                 return a.first > b.first;
+                             });
+            for (const auto& k : keys) {
+                Part p{kind, 0, 0, {}, {}};
+                p.cls = orient_stencil_taps_cached(k.first, k.second, &p.taps);
+                for (const int4& t : all)
+                    if (bp.shapes[t.x].M == k.first && bp.shapes[t.x].sigma == k.second) p.tiles.push_back(t);
+                parts.push_back(std::move(p));
+            }
+            return;
+        }
         if (kind == BK_SOLVE) {
             std::vector<int> Ns;
             for (const int4& t : all)
                 if (std::find(Ns.begin(), Ns.end(), t.w) == Ns.end()) Ns.push_back(t.w);
             std::sort(Ns.begin(), Ns.end());
             for (int N : Ns) {
-                Part p{kind, N, 0, {}};
+                Part p{kind, N, 0, {}, {}};
                 for (const int4& t : all)
                     if (t.w == N) p.tiles.push_back(t);
                 parts.push_back(std::move(p));
@@ -469,7 +502,7 @@ int build_schedule(BatchPlan& bp) {
             return;
         }
         if (kind == BK_ORIENT_COL || kind == BK_FILL || kind == BK_DECODE) {
-            if (!all.empty()) parts.push_back(Part{kind, 0, 0, std::move(all)});
+            if (!all.empty()) parts.push_back(Part{kind, 0, 0, std::move(all), {}});
             return;
         }
         for (int cls = kBatchClasses - 1; cls >= 0; --cls) {
@@ -477,7 +510,7 @@ int build_schedule(BatchPlan& bp) {
                                   kind == BK_ROW_INV_MAX ? BK_ROW_INV_MEAN : -1};
             for (int k : kinds) {
                 if (k < 0) continue;
-                Part p{k, 0, cls, {}};
+                Part p{k, 0, cls, {}, {}};
                 for (const int4& t : all) {
                     const Shape& x = bp.shapes[t.x];
                     if (batch_class(x.M) != cls) continue;
@@ -489,6 +522,7 @@ int build_schedule(BatchPlan& bp) {
             }
         }
     };
+    add_pass(BK_ORIENT_STENCIL, 9);
     add_pass(BK_ORIENT_ROW, 0);
     add_pass(BK_ORIENT_COL, 1);
     add_pass(BK_ORIENT_INV, 2);
@@ -512,6 +546,7 @@ int build_schedule(BatchPlan& bp) {
         L.name = kind_name(p.kind, p.N);
         L.ntiles = (int)p.tiles.size();
         L.tile_off = flat.size();
+        L.taps = p.taps;
         // LDS: the largest need of the part's images
         size_t lds = 0;
         for (const int4& t : p.tiles) {
@@ -569,7 +604,8 @@ int build_schedule(BatchPlan& bp) {
     SE2N_HIP(hipStreamBeginCapture(bp.cap, hipStreamCaptureModeRelaxed), "begin graph capture");
     hipError_t le = hipSuccess;
     for (const Launch& L : bp.launches) {
-        le = launch_batch(L.kind, L.N, L.cls, bp.d_items, bp.d_tiles + L.tile_off, L.ntiles, L.grid, L.lds, bp.cap);
+        le = launch_batch(L.kind, L.N, L.cls, bp.d_items, bp.d_tiles + L.tile_off, L.ntiles, L.grid, L.lds, bp.cap,
+                          &L.taps);
         if (le != hipSuccess) break;
     }
     hipGraph_t g = nullptr;
@@ -703,7 +739,8 @@ int run_plan(BatchPlan& bp, const se2n_item* items, void* ws, hipStream_t st) {
         hipEvent_t a = new_event(), b = new_event();
         if (a) (void)hipEventRecord(a, st);
         const hipError_t e =
-            launch_batch(L.kind, L.N, L.cls, bp.d_items, bp.d_tiles + L.tile_off, L.ntiles, L.grid, L.lds, st);
+            launch_batch(L.kind, L.N, L.cls, bp.d_items, bp.d_tiles + L.tile_off, L.ntiles, L.grid, L.lds, st,
+                         &L.taps);
         if (b) (void)hipEventRecord(b, st);
         if (a && b) g_prof_pending.push_back({L.name, a, b});
         if (e != hipSuccess) return hip_fail(e, "batched kernel launch");
@@ -891,7 +928,7 @@ int se2n_batch_tiles(const se2n_item* items, int count, const se2n_tune* tune, i
     int rc = check_items(items, count, false);
     if (rc) return rc;
     if (!ntiles) return fail(SE2N_EINVAL, "ntiles is NULL");
-    if (pass < 0 || pass > 8) return fail(SE2N_EINVAL, "pass must lie in [0, 8] (got %d)", pass);
+    if (pass < 0 || pass > 9) return fail(SE2N_EINVAL, "pass must lie in [0, 9] (got %d)", pass);
     if (tiles && capacity < 0) return fail(SE2N_EINVAL, "capacity must be >= 0");
     se2n_tune t = kDefaultTune;
     if (tune) {

@@ -25,6 +25,15 @@ std::vector<C2<R>> quarter_twiddles(int M);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+struct OrientTaps;
+// Taps of the orientation stencil for side M and Gaussian width sigma: the
+// radius it needs (kernel tails below 2^-26 of each kernel's absolute sum,
+// or the whole circle), rounded up to a compiled radius.  Returns that
+// radius, or 0 when no compiled radius covers it (the FFT route is used).
+int orient_stencil_taps(int M, double sigma, OrientTaps* taps);
+// The same, remembered per (M, sigma) for the process (thread-safe); taps may be NULL.
+int orient_stencil_taps_cached(int M, double sigma, OrientTaps* taps);
+
 }  // namespace se2n
 
 #define SE2N_HIP(call, what)                                       \

@@ -167,6 +167,21 @@ hipError_t launch_lift(const R* f, const uint8_t* mask, const uint8_t* rmap, R* 
                        hipStream_t st);
 template <class R>
 hipError_t launch_project(const R* psi, R* out, int M, int N, bool mean, hipStream_t st);
+// Orientation map by a separable periodic stencil (FP32 plans).  The smoothed
+// central differences are g_x = d (x) g and g_y = g (x) d, where g is the
+// periodic smoothing kernel and d the smoothed central difference, both the
+// inverse DFT of the Fourier multipliers.  They are passed as correlation
+// weights: out[y] = sum_j t[j + r] in[y + j], j in [-r, r], r the compiled
+// radius (entries beyond the kernel's support are zero).
+constexpr int kOrientMaxRadius = 32;
+constexpr int kOrientRadii[] = {8, 12, 16, 20, 24, 32};
+struct OrientTaps {
+    float g[2 * kOrientMaxRadius + 1];
+    float d[2 * kOrientMaxRadius + 1];
+};
+hipError_t launch_orient_stencil(const float* f, const uint8_t* mask, uint8_t* rmap, int M, int N, int radius,
+                                 const OrientTaps& taps, hipStream_t st);
+
 template <class R>
 hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
                              hipStream_t st);

@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/se2n.h"
@@ -100,6 +101,97 @@ std::vector<C2<R>> quarter_twiddles(int M) {
 template std::vector<C2<float>> quarter_twiddles<float>(int);
 template std::vector<C2<double>> quarter_twiddles<double>(int);
 
+// The orientation step's two Fourier multipliers per axis: the Gaussian
+// G_k = exp(-2 pi^2 sigma^2 kbar^2 / M^2) (kbar = k wrapped to [-M/2, M/2))
+// and G_k times the central-difference symbol i sqrt(M) sin(2 pi k/M).
+// Their inverse DFTs, in FP64, are the smoothing kernel
+//     g[x] = (1/M) sum_k G_k cos(2 pi k x/M)
+// and the smoothed difference kernel
+//     d[x] = -(sqrt(M)/M) sum_k sin(2 pi k/M) G_k sin(2 pi k x/M),
+// (even and odd in x).  The convolution out = d (*) in becomes the
+// correlation out[y] = sum_j d[-j] in[y + j], hence the reflected taps.
+int orient_stencil_taps(int M, double sigma, OrientTaps* taps) {
+    const double two_pi = 6.283185307179586476925;
+    std::vector<double> G(M), c(M), s(M), g(M, 0.0), d(M, 0.0);
+    for (int k = 0; k < M; ++k) {
+        const double kb = (double)(((k + M / 2) % M) - M / 2);
+        G[k] = std::exp(-0.5 * two_pi * two_pi * sigma * sigma * kb * kb / ((double)M * M));
+        c[k] = std::cos(two_pi * k / M);
+        s[k] = std::sin(two_pi * k / M);
+    }
+    for (int x = 0; x <= M / 2; ++x) {
+        double sg = 0.0, sd = 0.0;
+        int idx = 0;  // k x mod M
+        for (int k = 0; k < M; ++k) {
+            sg += G[k] * c[idx];
+            sd += s[k] * G[k] * s[idx];
+            idx += x;
+            if (idx >= M) idx -= M;
+        }
+        g[x] = sg / M;
+        d[x] = -std::sqrt((double)M) / M * sd;
+        if (x > 0 && x < M - x) {
+            g[M - x] = g[x];
+            d[M - x] = -d[x];
+        }
+    }
+    // absolute mass at circular distance r, then the smallest radius whose
+    // dropped tail is below 2^-26 of the kernel's absolute sum
+    const int H = M / 2;
+    std::vector<double> mg(H + 1), md(H + 1);
+    double tg = 0.0, td = 0.0;
+    for (int r = 0; r <= H; ++r) {
+        mg[r] = std::fabs(g[r]) + ((r > 0 && r < M - r) ? std::fabs(g[M - r]) : 0.0);
+        md[r] = std::fabs(d[r]) + ((r > 0 && r < M - r) ? std::fabs(d[M - r]) : 0.0);
+        tg += mg[r];
+        td += md[r];
+    }
+    const double tol = std::ldexp(1.0, -26);
+    int need = H;  // the whole circle
+    double tail_g = 0.0, tail_d = 0.0;
+    for (int R = H; R >= 1; --R) {
+        tail_g += mg[R];
+        tail_d += md[R];
+        if (tail_g > tol * tg || tail_d > tol * td) break;
+        need = R - 1;
+    }
+    const bool circle = need >= H;
+    int rad = 0;
+    for (int rv : kOrientRadii) {
+        if (rv >= (circle ? H : need)) {
+            rad = rv;
+            break;
+        }
+    }
+    if (rad == 0) return 0;
+    std::memset(taps, 0, sizeof *taps);
+    const int lo = circle ? -(H - 1) : -need;
+    const int hi = circle ? H : need;
+    for (int j = lo; j <= hi; ++j) {
+        const int m = ((-j) % M + M) % M;
+        taps->g[j + rad] = (float)g[m];
+        taps->d[j + rad] = (float)d[m];
+    }
+    return rad;
+}
+
+int orient_stencil_taps_cached(int M, double sigma, OrientTaps* taps) {
+    static std::mutex mu;
+    static std::map<std::pair<int, uint64_t>, std::pair<int, OrientTaps>> memo;
+    uint64_t bits;
+    std::memcpy(&bits, &sigma, sizeof bits);
+    const auto key = std::make_pair(M, bits);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = memo.find(key);
+    if (it == memo.end()) {
+        std::pair<int, OrientTaps> v;
+        v.first = orient_stencil_taps(M, sigma, &v.second);
+        it = memo.emplace(key, v).first;
+    }
+    if (taps) *taps = it->second.second;
+    return it->second.first;
+}
+
 }  // namespace se2n
 
 namespace {
@@ -129,6 +221,11 @@ struct se2n_plan_s {
     FftPlan planH{}, planM{};
     LaunchGeom geom{};
     std::list<CacheEntry> cache;  // most recently used first
+    // orientation stencil taps for the last sigma (FP32 plans); radius 0 = FFT route
+    bool ot_valid = false;
+    double ot_sigma = 0.0;
+    int ot_radius = 0;
+    OrientTaps ot{};
     size_t cache_bytes = 0;
     size_t cache_limit = (size_t)16 << 30;
     std::mutex mu;
@@ -335,11 +432,35 @@ Ws<R> split_workspace(se2n_plan p, void* ws) {
     return w;
 }
 
+// Stencil radius for sigma (0: the FFT route) and a copy of its taps.  FP64
+// plans always take the FFT route: the periodic kernels' aliasing floor
+// (about exp(-pi^2 sigma^2 / 2)) keeps their tails above FP64 rounding.
+int orient_radius(se2n_plan p, double sigma, OrientTaps* taps) {
+    if (p->dt != SE2N_F32) return 0;
+    std::lock_guard<std::mutex> lock(p->mu);
+    if (!p->ot_valid || std::memcmp(&p->ot_sigma, &sigma, sizeof sigma) != 0) {
+        p->ot_radius = orient_stencil_taps(p->M, sigma, &p->ot);
+        p->ot_sigma = sigma;
+        p->ot_valid = true;
+    }
+    if (taps) *taps = p->ot;
+    return p->ot_radius;
+}
+
 template <class R>
 int orient_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, uint8_t* rmap, C2<R>* spec,
                 hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
     const int M = p->M;
+    if constexpr (std::is_same<R, float>::value) {
+        OrientTaps taps;
+        const int rad = orient_radius(p, sigma, &taps);
+        if (rad > 0) {
+            SE2N_TIMED(p, "orient_stencil", st, launch_orient_stencil(f, mask, rmap, M, p->N, rad, taps, st),
+                       "orientation stencil");
+            return SE2N_OK;
+        }
+    }
     SE2N_TIMED(p, "orient_row_fwd", st,
                launch_row_fwd<R>(SRC_IMAGE, f, mask, nullptr, nullptr, spec, M, 1, p->geom, p->planH, tw, st),
                "orient row pass");
@@ -548,6 +669,35 @@ int se2n_orient(se2n_plan p, const void* f, const uint8_t* mask, double sigma, u
         return orient_impl<float>(p, (const float*)f, mask, sigma, rmap, split_workspace<float>(p, workspace).spec, st);
     return orient_impl<double>(p, (const double*)f, mask, sigma, rmap, split_workspace<double>(p, workspace).spec,
                                st);
+}
+
+int se2n_orient_method(se2n_plan p, double sigma, int* radius) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!radius) return fail(SE2N_EINVAL, "null pointer argument");
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
+    *radius = orient_radius(p, sigma, nullptr);
+    return SE2N_OK;
+}
+
+int se2n_orient_stencil_taps(int M, double sigma, float* g, float* d, int* radius) {
+    g_last_error.clear();
+    if (!g || !d || !radius) return fail(SE2N_EINVAL, "null pointer argument");
+    if (M < 16 || M > 4096 || !is_2a3b(M, nullptr, nullptr) || M % 8 != 0)
+        return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 3 in [16, 4096] (got %d)", M);
+    if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
+    OrientTaps t;
+    const int rad = orient_stencil_taps(M, sigma, &t);
+    *radius = rad;
+    if (rad == 0) return SE2N_OK;
+    const int R = kOrientMaxRadius;
+    for (int j = -R; j <= R; ++j) {
+        const bool in = j >= -rad && j <= rad;
+        g[j + R] = in ? t.g[j + rad] : 0.0f;
+        d[j + R] = in ? t.d[j + rad] : 0.0f;
+    }
+    return SE2N_OK;
 }
 
 int se2n_lift(se2n_plan p, const void* f, const uint8_t* mask, const uint8_t* rmap, void* psi, void* stream) {

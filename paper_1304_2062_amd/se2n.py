@@ -35,6 +35,7 @@ _lib.se2n_workspace_bytes.argtypes = [_vp]
 _lib.se2n_workspace_bytes.restype = ctypes.c_size_t
 _lib.se2n_precompute.argtypes = [_vp, _d, _d, _i, _i, _vp]
 _lib.se2n_orient.argtypes = [_vp, _vp, _vp, _d, _vp, _vp, _vp]
+_lib.se2n_orient_method.argtypes = [_vp, _d, ctypes.POINTER(_i)]
 _lib.se2n_lift.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 _lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
 _lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
@@ -51,7 +52,7 @@ _lib.se2n_profile_stats.argtypes = [_vp, ctypes.POINTER(KernelStat), _i, ctypes.
 _lib.se2n_profile_stats.restype = _i
 _lib.se2n_last_error.restype = ctypes.c_char_p
 _lib.se2n_version.restype = ctypes.c_char_p
-for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_lift",
+for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_orient_method", "se2n_lift",
               "se2n_diffuse", "se2n_project", "se2n_inpaint"):
     getattr(_lib, _name).restype = _i
 
@@ -136,6 +137,12 @@ class Plan:
         _check(_lib.se2n_orient(self._h, _ptr(f), _ptr(mask), float(sigma), _ptr(rmap), _ptr(self.workspace()),
                                 _vp(_stream())))
         return rmap
+
+    def orient_radius(self, sigma: float = 2.0) -> int:
+        """Compiled radius of the orientation stencil for sigma, 0 for the FFT route."""
+        r = _i(0)
+        _check(_lib.se2n_orient_method(self._h, float(sigma), ctypes.byref(r)))
+        return r.value
 
     def lift(self, f: torch.Tensor, mask: torch.Tensor, rmap: torch.Tensor) -> torch.Tensor:
         self._image(f, "f")

@@ -32,16 +32,27 @@ def lib():
     return L
 
 
-def items_of(specs):
+def items_of(specs, sigmas=None):
     """specs: (M, N, proj) triples; pointers stay NULL (host-only calls)."""
     arr = (Item * len(specs))()
     for k, (M, N, proj) in enumerate(specs):
-        arr[k] = Item(M, N, 100, 0, proj, 0, 1.0, 1.0, 2.0, None, None, None, None)
+        sigma = 2.0 if sigmas is None else sigmas[k]
+        arr[k] = Item(M, N, 100, 0, proj, 0, 1.0, 1.0, sigma, None, None, None, None)
     return arr
 
 
 SPECS = [(16, 4, 0), (24, 6, 1), (128, 16, 0), (192, 24, 0), (384, 30, 1), (512, 32, 0), (768, 8, 0),
          (1024, 64, 0), (72, 10, 0)]
+# Gaussian widths: 6 at M >= 128 and 1 at M = 768 take the FFT route of the
+# orientation step, the others the stencil (6 at M = 24 keeps the whole circle)
+SIGMAS = [2.0, 6.0, 6.0, 2.0, 6.0, 2.0, 1.0, 2.0, 2.0]
+
+
+def stencil_radius(lib, M, sigma):
+    g = (ctypes.c_float * 65)()
+    r = ctypes.c_int(-1)
+    assert lib.se2n_orient_stencil_taps(M, ctypes.c_double(sigma), g, g, ctypes.byref(r)) == 0
+    return r.value
 
 
 def geometry(M):
@@ -91,7 +102,7 @@ TUNES = [(2, 0, 1), (0, 1, 1), (1, 0, 2), (4, 1, 4), (2, 0, 64)]
 
 @pytest.mark.parametrize("tune", TUNES)
 def test_row_tiles_cover_every_row_block_and_slice_once(lib, tune):
-    arr = items_of(SPECS)
+    arr = items_of(SPECS, SIGMAS)
     for pass_ in (0, 2, 3, 6):
         seen = {}
         for (i, rb, sb, se) in tiles(lib, arr, pass_, tune):
@@ -103,6 +114,8 @@ def test_row_tiles_cover_every_row_block_and_slice_once(lib, tune):
             rows, _, _ = geometry(M)
             ns = {0: 1, 2: 2}.get(pass_, N)
             want = {(i, rb, s) for rb in range(M // rows) for s in range(ns)}
+            if pass_ in (0, 2) and stencil_radius(lib, M, SIGMAS[i]) > 0:
+                want = set()  # orientation by the stencil (pass 9)
             got = {k for k in seen if k[0] == i}
             assert got == want, (pass_, M, N)
             if pass_ in (3, 6):
@@ -112,7 +125,7 @@ def test_row_tiles_cover_every_row_block_and_slice_once(lib, tune):
 
 @pytest.mark.parametrize("tune", TUNES)
 def test_column_tiles_partition_every_column_run(lib, tune):
-    arr = items_of(SPECS)
+    arr = items_of(SPECS, SIGMAS)
     col = tiles(lib, arr, 4, tune)
     ocol = tiles(lib, arr, 1, tune)
     for i, (M, N, _) in enumerate(SPECS):
@@ -121,7 +134,28 @@ def test_column_tiles_partition_every_column_run(lib, tune):
         starts = sorted(t[1] for t in col if t[0] == i)
         assert starts == list(range(0, N * K, cols))
         ostarts = sorted(t[1] for t in ocol if t[0] == i)
-        assert ostarts == list(range(0, K, ocols))
+        assert ostarts == ([] if stencil_radius(lib, M, SIGMAS[i]) > 0 else list(range(0, K, ocols)))
+
+
+@pytest.mark.parametrize("tune", TUNES)
+def test_stencil_tiles_cover_every_64_by_64_tile_of_stencil_items(lib, tune):
+    """Pass 9 holds exactly the items without FFT-route orientation passes, one
+    tile per 64 x 64 block of bins, with the item's compiled radius."""
+    arr = items_of(SPECS, SIGMAS)
+    st = tiles(lib, arr, 9, tune)
+    routes = 0
+    for i, (M, N, _) in enumerate(SPECS):
+        rad = stencil_radius(lib, M, SIGMAS[i])
+        mine = sorted(t[1:] for t in st if t[0] == i)
+        nt = -(-M // 64)
+        if rad > 0:
+            assert mine == [(tt, rad, 0) for tt in range(nt * nt)]
+            routes |= 1
+        else:
+            assert mine == []
+            assert any(t[0] == i for t in tiles(lib, arr, 0, tune))
+            routes |= 2
+    assert routes == 3  # both routes occur in this batch
 
 
 @pytest.mark.parametrize("tune", TUNES)
@@ -170,7 +204,7 @@ def test_clear_tiles_exist_exactly_for_max_items_with_slice_groups(lib, tune):
 
 def test_orders_are_permutations_and_largest_first_puts_big_images_first(lib):
     arr = items_of(SPECS)
-    for pass_ in range(9):
+    for pass_ in range(10):
         a = tiles(lib, arr, pass_, (2, 0, 2))
         b = tiles(lib, arr, pass_, (2, 1, 2))
         assert sorted(a) == sorted(b)
@@ -208,7 +242,7 @@ def test_bad_counts_tunes_and_passes(lib):
     n = ctypes.c_int(0)
     assert lib.se2n_batch_workspace_bytes(arr, 0) == 0
     assert lib.se2n_batch_workspace_bytes(None, 1) == 0
-    assert lib.se2n_batch_tiles(arr, 2, None, 9, None, 0, ctypes.byref(n)) == -1
+    assert lib.se2n_batch_tiles(arr, 2, None, 10, None, 0, ctypes.byref(n)) == -1
     assert lib.se2n_batch_tiles(arr, 2, ctypes.byref(Tune(17, 0, 1, 0)), 0, None, 0, ctypes.byref(n)) == -1
     assert lib.se2n_batch_tiles(arr, 2, ctypes.byref(Tune(1, 2, 1, 0)), 0, None, 0, ctypes.byref(n)) == -1
     assert lib.se2n_batch_tiles(arr, 2, ctypes.byref(Tune(1, 0, 0, 0)), 0, None, 0, ctypes.byref(n)) == -1

@@ -50,11 +50,16 @@ SMALL = [
 ]
 
 
+# sigma = 6 at M = 72 and 96 takes the FFT route of the orientation step, the
+# others the separable stencil: one batch holds both routes
+SIGMAS = [2.0, 2.0, 2.0, 2.0, 6.0, 6.0]
+
+
 def _small_params():
     out = []
     for k, p in enumerate(SMALL):
         seed = 500 + k
-        out.append(dict(p, seed=seed, sigma=2.0, f=synth.make_image(seed, p["M"], "small"),
+        out.append(dict(p, seed=seed, sigma=SIGMAS[k], f=synth.make_image(seed, p["M"], "small"),
                         mask=synth.mask_random(seed + 7919, p["M"], 0.4).astype(np.uint8)))
     return out
 
@@ -70,7 +75,7 @@ def test_small_batch_matches_the_fp64_oracle(se2n):
         rmap = it.rmap_out.cpu().numpy()
         assert rmap.max() < p["N"]
         f32 = p["f"].astype(np.float32).astype(np.float64)
-        ref, _ = O.inpaint(f32, p["mask"], p["N"], p["T"], p["beta"], p["n_steps"], sigma=2.0,
+        ref, _ = O.inpaint(f32, p["mask"], p["N"], p["T"], p["beta"], p["n_steps"], sigma=p["sigma"],
                            scheme=p["scheme"], proj=p["proj"], rmap=rmap)
         rel = _rel(it.out.cpu().numpy(), ref)
         _say(f"  M={p['M']} N={p['N']} {p['scheme']} {p['proj']}: rel {rel:.2e}")
@@ -83,8 +88,8 @@ def test_small_batch_orientation_matches_the_oracle_where_decided(se2n):
     se2n.inpaint_batched(items)
     torch.cuda.synchronize()
     for p, it in zip(params, items):
-        want, tie = O.orient(p["f"].astype(np.float32).astype(np.float64), p["mask"], p["N"], 2.0)
-        gx, gy = O.smoothed_gradient(p["f"].astype(np.float32).astype(np.float64), p["mask"], 2.0)
+        want, tie = O.orient(p["f"].astype(np.float32).astype(np.float64), p["mask"], p["N"], p["sigma"])
+        gx, gy = O.smoothed_gradient(p["f"].astype(np.float32).astype(np.float64), p["mask"], p["sigma"])
         mag = np.hypot(gx, gy)
         unc = 1e-5 * mag.max() / np.maximum(mag, 1e-300) * p["N"] / (2 * np.pi)
         decided = tie > np.maximum(1e-4, unc)
@@ -166,7 +171,7 @@ def test_autotune_keeps_results_and_writes_the_table(se2n, tmp_path):
     torch.cuda.synchronize()
     for p, it in zip(params, items):
         ref, _ = O.inpaint(p["f"].astype(np.float32).astype(np.float64), p["mask"], p["N"], p["T"], p["beta"],
-                           p["n_steps"], sigma=2.0, scheme=p["scheme"], proj=p["proj"],
+                           p["n_steps"], sigma=p["sigma"], scheme=p["scheme"], proj=p["proj"],
                            rmap=it.rmap_out.cpu().numpy())
         assert _rel(it.out.cpu().numpy(), ref) < TOL32
     se2n.batch_clear()
