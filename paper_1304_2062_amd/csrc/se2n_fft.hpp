@@ -492,6 +492,100 @@ __device__ __forceinline__ void fft_stage_static_out(C2<R>* buf, const C2<R>* tw
     }
 }
 
+// ---------------------------------------------------------------------------
+// The same fixed-size stages between two LDS buffers.  A stage reads `a` and
+// writes `b`, so no thread can overwrite what another still has to read:
+// one barrier per stage instead of two, and each thread computes a butterfly
+// as soon as its own loads arrive.
+// ---------------------------------------------------------------------------
+template <class R, int RADIX, bool INV, bool TWFULL, int L, int NS, int NBATCH, int BSTRIDE, int NTHR, int M>
+__device__ __forceinline__ void fft_stage_pp(const C2<R>* a, C2<R>* b, const C2<R>* twq, int tid) {
+    constexpr int NB = L / RADIX;
+    constexpr int TOTAL = NB * NBATCH;
+    constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+    constexpr int TWSTEP = M / (NS * RADIX);
+    constexpr int M4 = M / 4;
+#pragma unroll
+    for (int i = 0; i < MAXB; ++i) {
+        const int bf = tid + i * NTHR;
+        if (TOTAL % NTHR == 0 || bf < TOTAL) {
+            const int t = bf / NB;
+            const int j = bf - t * NB;
+            const int q = j / NS;
+            const int k = j - q * NS;
+            const int ib = t * BSTRIDE + j;
+            C2<R> v[RADIX];
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
+            if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, k * TWSTEP, M4);
+            dft<R, RADIX, INV>(v);
+            const int ob = t * BSTRIDE + q * NS * RADIX + k;
+#pragma unroll
+            for (int r = 0; r < RADIX; ++r) b[lds_pad(ob + r * NS)] = v[r];
+        }
+    }
+    __syncthreads();
+}
+
+// Stages S.. of the transform, the first reading `a`; returns the buffer
+// that holds the result.
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S, int NS>
+__device__ __forceinline__ C2<R>* fft_static_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid) {
+    constexpr int RADIX = static_radix(L, S);
+    if constexpr (RADIX == 0) {
+        return a;
+    } else {
+        fft_stage_pp<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(a, b, twq, tid);
+        return fft_static_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(b, a, twq, tid);
+    }
+}
+
+// fft_static_in on two buffers: the first stage's inputs come from g(slot)
+// and go to `a`; returns the buffer holding the result.  The caller
+// guarantees that no thread still reads `a`.
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, class G>
+__device__ __forceinline__ C2<R>* fft_static_in_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, G&& g) {
+    fft_static_first<R, INV, L, NBATCH, BSTRIDE, NTHR, false>(a, tid, g);
+    return fft_static_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, 1, static_radix(L, 0)>(a, b, twq, tid);
+}
+
+// fft_static_out on two buffers, from stage S reading `a`: the last stage
+// hands its outputs to f and is followed by no barrier.  Returns the buffer
+// the last stage read, which threads may still be reading on return; the
+// other one is free.
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S, int NS, class F>
+__device__ __forceinline__ C2<R>* fft_static_out_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, F&& f) {
+    constexpr int RADIX = static_radix(L, S);
+    if constexpr (static_radix(L, S + 1) == 0) {
+        constexpr int NB = L / RADIX;
+        constexpr int TOTAL = NB * NBATCH;
+        constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+        constexpr int TWSTEP = M / (NS * RADIX);
+        constexpr int M4 = M / 4;
+        static_assert(NS * RADIX == L, "the output stage is the last one");
+#pragma unroll
+        for (int i = 0; i < MAXB; ++i) {
+            const int bf = tid + i * NTHR;
+            if (TOTAL % NTHR == 0 || bf < TOTAL) {
+                const int t = bf / NB;
+                const int j = bf - t * NB;  // q = 0 in the last stage: k = j
+                const int ib = t * BSTRIDE + j;
+                C2<R> v[RADIX];
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
+                if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, j * TWSTEP, M4);
+                dft<R, RADIX, INV>(v);
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) f(i * RADIX + r, t, j + r * NS, v[r]);
+            }
+        }
+        return a;
+    } else {
+        fft_stage_pp<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(a, b, twq, tid);
+        return fft_static_out_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(b, a, twq, tid, f);
+    }
+}
+
 template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S = 0, int NS = 1,
           class F>
 __device__ __forceinline__ void fft_static_out(C2<R>* buf, const C2<R>* twq, int tid, F&& f) {

@@ -96,6 +96,13 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
     g.rows = rows;
     fft_threads_of(rows * H, g.row_threads, g.row_ept);
+#ifndef SE2N_ROW_MAX_THREADS
+#define SE2N_ROW_MAX_THREADS 1024
+#endif
+    if (g.row_threads > SE2N_ROW_MAX_THREADS && g.row_ept == 8) {  // 16 elements per thread, half the threads
+        g.row_ept = 16;
+        g.row_threads = (rows * H + 15) / 16;
+    }
     // the row passes walk (kx, row) pairs with thread t on row t mod rows
     g.row_threads = (g.row_threads + rows - 1) / rows * rows;
     g.cols = target / M > 1 ? target / M : 1;
@@ -107,9 +114,19 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
     // full-period twiddle table for the row passes when it fits beside the row
     // buffer; a column workgroup transforms only a few columns, for which
     // expanding the full table would cost as much as the transform
-    g.tw_full = (long)tw_elems(M, true) * cs + (long)lds_padded_size(rows * (H + 2)) * cs <= 150 * 1024 ? 1 : 0;
+#ifndef SE2N_ROW_LDS_BUDGET
+#define SE2N_ROW_LDS_BUDGET (150 * 1024)
+#endif
+    g.tw_full =
+        (long)tw_elems(M, true) * cs + (long)lds_padded_size(rows * (H + 2)) * cs <= SE2N_ROW_LDS_BUDGET ? 1 : 0;
     g.tw_full_col = 0;
     return g;
+}
+
+// Elements of one row-pass LDS buffer (rows x (M/2 + 2), padded), a multiple
+// of 8 so that a second buffer after it stays 64-byte aligned.
+__host__ __device__ constexpr int row_buf_elems(int M, int rows) {
+    return (lds_padded_size(rows * (M / 2 + 2)) + 7) & ~7;
 }
 
 // Workgroups are dispatched round-robin over the chip's 8 XCDs, each with its

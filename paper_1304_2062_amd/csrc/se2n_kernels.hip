@@ -69,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const
     const int s_end = min(nslices, s_begin + slices_per_group);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
     row_fwd_tile<R, SRC, EPT, TWF, MS>(f, mask, rmap, vol, spec, M, rows, nthr, rb, s_begin, s_end, planH, tw,
-                                       buf, threadIdx.x);
+                                       buf, threadIdx.x, MS ? buf + row_buf_elems(M, rows) : nullptr);
 }
 
 // Column pass: one tile of cols_per_block contiguous columns per workgroup.
@@ -118,7 +118,8 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
     const int s_end = min(nslices, s_begin + slices_per_group);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
     row_inv_tile<R, DST, EPT, TWF, MS, PAIRED>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N,
-                                               out_scale, planH, tw, buf, threadIdx.x);
+                                               out_scale, planH, tw, buf, threadIdx.x,
+                                               MS ? buf + row_buf_elems(M, rows) : nullptr);
 }
 
 // Paired inverse column pass: one tile of column pairs per workgroup.
@@ -344,11 +345,17 @@ static int static_size(int M, const LaunchGeom& g) {
     if (sizeof(R) != 4 || !g.static_ok) return 0;
     if (M != 512 && M != 1024 && M != 2048) return 0;
     const GeomCore c = geom_core<R>(M);
-    const bool same = g.rows == c.rows && g.row_threads == c.row_threads && g.row_ept == 8 && c.row_ept == 8 &&
+    const bool same = g.rows == c.rows && g.row_threads == c.row_threads && g.row_ept == c.row_ept &&
                       g.cols == c.cols && g.col_threads == c.col_threads && g.col_ept == 8 && c.col_ept == 8 &&
-                      g.tw_full == 1 && c.tw_full == 1 && g.tw_full_col == 0;
+                      g.tw_full == c.tw_full && g.tw_full_col == 0;
     return same ? M : 0;
 }
+
+// Elements per thread and twiddle table of the row kernels compiled for a fixed M.
+template <int M>
+constexpr int kRowEpt = geom_core<float>(M).row_ept;
+template <int M>
+constexpr bool kRowTwf = geom_core<float>(M).tw_full != 0;
 
 template <class R>
 static size_t tw_bytes(int M, bool full) {
@@ -361,14 +368,16 @@ hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_
                           const C2<R>* tw, hipStream_t st) {
     const int groups = (nslices + g.row_slices - 1) / g.row_slices;
     dim3 grid((M / g.rows) * groups);
-    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 2)) * sizeof(C2<R>);
+    // the kernels compiled for a fixed M run their stages between two row buffers
+    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) +
+                       (size_t)row_buf_elems(M, g.rows) * sizeof(C2<R>) * (kStatic<R> && static_size<R>(M, g) ? 2 : 1);
 #define SE2N_ROWFWD(S, E, W, MSV)                                                                          \
     hipLaunchKernelGGL((k_row_fwd<R, S, E, W, MSV>), grid, dim3(g.row_threads), lds, st, f, mask, rmap, vol,    \
                        spec, M, nslices, g.row_slices, g.rows, g.xcd_pair, planH, tw)
 #define SE2N_ROWFWD_E(S)                                                    \
-    if (static_size<R>(M, g) == 2048) SE2N_ROWFWD(S, 8, true, kStatic<R> ? 2048 : 0);        \
-    else if (static_size<R>(M, g) == 1024) SE2N_ROWFWD(S, 8, true, kStatic<R> ? 1024 : 0);   \
-    else if (static_size<R>(M, g) == 512) SE2N_ROWFWD(S, 8, true, kStatic<R> ? 512 : 0);     \
+    if (static_size<R>(M, g) == 2048) SE2N_ROWFWD(S, kRowEpt<2048>, kRowTwf<2048>, kStatic<R> ? 2048 : 0);        \
+    else if (static_size<R>(M, g) == 1024) SE2N_ROWFWD(S, kRowEpt<1024>, kRowTwf<1024>, kStatic<R> ? 1024 : 0);   \
+    else if (static_size<R>(M, g) == 512) SE2N_ROWFWD(S, kRowEpt<512>, kRowTwf<512>, kStatic<R> ? 512 : 0);     \
     else if (g.tw_full) {                                                   \
         if (g.row_ept == 8) SE2N_ROWFWD(S, 8, true, 0);                     \
         else SE2N_ROWFWD(S, 16, true, 0);                                   \
@@ -455,7 +464,9 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                           bool paired) {
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
     dim3 grid((M / g.rows) * groups);
-    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) + (size_t)lds_padded_size(g.rows * (M / 2 + 2)) * sizeof(C2<R>);
+    // the kernels compiled for a fixed M run their stages between two row buffers
+    const size_t lds = tw_bytes<R>(M, g.tw_full != 0) +
+                       (size_t)row_buf_elems(M, g.rows) * sizeof(C2<R>) * (kStatic<R> && static_size<R>(M, g) ? 2 : 1);
 #define SE2N_ROWINV(D, E, W, MSV)                                                                              \
     do {                                                                                                       \
         if (paired)                                                                                            \
@@ -468,9 +479,9 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                                tw);                                                                            \
     } while (0)
 #define SE2N_ROWINV_E(D)                                                    \
-    if (static_size<R>(M, g) == 2048) SE2N_ROWINV(D, 8, true, kStatic<R> ? 2048 : 0);        \
-    else if (static_size<R>(M, g) == 1024) SE2N_ROWINV(D, 8, true, kStatic<R> ? 1024 : 0);   \
-    else if (static_size<R>(M, g) == 512) SE2N_ROWINV(D, 8, true, kStatic<R> ? 512 : 0);     \
+    if (static_size<R>(M, g) == 2048) SE2N_ROWINV(D, kRowEpt<2048>, kRowTwf<2048>, kStatic<R> ? 2048 : 0);        \
+    else if (static_size<R>(M, g) == 1024) SE2N_ROWINV(D, kRowEpt<1024>, kRowTwf<1024>, kStatic<R> ? 1024 : 0);   \
+    else if (static_size<R>(M, g) == 512) SE2N_ROWINV(D, kRowEpt<512>, kRowTwf<512>, kStatic<R> ? 512 : 0);     \
     else if (g.tw_full) {                                                   \
         if (g.row_ept == 8) SE2N_ROWINV(D, 8, true, 0);                     \
         else SE2N_ROWINV(D, 16, true, 0);                                   \

@@ -50,7 +50,7 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
                                              const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
                                              C2<R>* __restrict__ spec, int M_, int rows_, int nthr_, int rb,
                                              int s_begin, int s_end, const FftPlan& planH, const C2<R>* tw,
-                                             C2<R>* buf, int tid) {
+                                             C2<R>* buf, int tid, C2<R>* buf2 = nullptr) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int rows = MS ? GC.rows : rows_;
@@ -104,6 +104,11 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
         }
     }
 
+    // Fixed-size transforms with a second buffer (buf2) run their stages
+    // between the two; bx is the buffer the next first stage may fill.
+    const bool pp = MS != 0 && buf2 != nullptr;
+    C2<R>* bx = buf;
+    C2<R>* by = buf2;
     for (int s = s_begin; s < s_end; ++s) {
         // input element i of this slice (zero where unused)
         auto input = [&](int i) {
@@ -122,8 +127,13 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
             }
             return z;
         };
+        C2<R>* res = buf;
         if constexpr (MS != 0) {
-            fft_static_in<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid, input);
+            if (pp)
+                res = fft_static_in_pp<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(bx, by, tw, tid,
+                                                                                                      input);
+            else
+                fft_static_in<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid, input);
         } else {
 #pragma unroll
             for (int i = 0; i < EPT; ++i) {
@@ -140,15 +150,21 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
         for (int e = tid; e < nout; e += nthr) {
             const int kx = e >> rshift;
             const int row = e & (rows - 1);
-            const C2<R> z1 = buf[lds_pad(row * S + (kx == H ? 0 : kx))];
-            const C2<R> z2 = buf[lds_pad(row * S + (kx == 0 ? 0 : H - kx))];
+            const C2<R> z1 = res[lds_pad(row * S + (kx == H ? 0 : kx))];
+            const C2<R> z2 = res[lds_pad(row * S + (kx == 0 ? 0 : H - kx))];
             const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
             // (z1 - conj z2)/(2i)
             const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
             const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
             out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R, TWF>(tw, kx, M4), od));
         }
-        __syncthreads();
+        if (pp) {
+            // the next first stage fills the buffer nobody reads any more
+            by = res;
+            bx = (res == buf) ? buf2 : buf;
+        } else {
+            __syncthreads();
+        }
     }
 }
 
@@ -312,7 +328,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
                                              typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                                              int M_, int rows_, int nthr_, int rb, int s_begin, int s_end, int N,
                                              R out_scale, const FftPlan& planH, const C2<R>* tw, C2<R>* buf,
-                                             int tid) {
+                                             int tid, C2<R>* buf2 = nullptr) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int rows = MS ? GC.rows : rows_;
@@ -368,11 +384,16 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
                 in_[(size_t)(i * kstep) * M];                                                          \
         }                                                                                              \
     } while (0)
+    // Fixed-size paired transforms with a second buffer (buf2) run their
+    // stages between the two; bx is the buffer the next first stage may fill.
+    const bool pp = DIRECT && buf2 != nullptr;
+    C2<R>* bx = buf;
+    C2<R>* by = buf2;
     SE2N_FETCH(s_begin);
     for (int s = s_begin; s < s_end; ++s) {
       if constexpr (DIRECT) {
         fft_static_first<R, true, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, true>(
-            buf, tid, [&](int i) { return pre[i]; });
+            pp ? bx : buf, tid, [&](int i) { return pre[i]; });
         if (s + 1 < s_end) SE2N_FETCH(s + 1);
       } else {
 #pragma unroll
@@ -424,8 +445,16 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
         if constexpr (DIRECT) {
             // stages 2.. with the last stage's outputs going to the accumulators
             constexpr int R0 = static_radix(MS / 2, 0);
-            fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
-                buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+            if (pp) {
+                C2<R>* last = fft_static_out_pp<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
+                    bx, by, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+                // the last stage may still be reading `last`: the next first stage fills the other one
+                by = last;
+                bx = (last == buf) ? buf2 : buf;
+            } else {
+                fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
+                    buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+            }
         } else if constexpr (MS != 0) {
             // the last stage's outputs go straight to the accumulators
             fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
