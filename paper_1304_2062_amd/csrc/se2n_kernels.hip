@@ -84,8 +84,11 @@ __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M_, int cols
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
     C2<R>* buf = tw + tw_elems(M, TWF);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
-    col_fft_tile<R, INV, EPT, TWF, MS>(spec, ncols, M, cols_per_block, nthr, (long)blockIdx.x * cols_per_block,
-                                      planM, tw, buf, threadIdx.x);
+    // tiles from the last slice to the first: the row pass before this one
+    // wrote the high slices last, and the memory-side cache still holds them
+    const long tile = (long)gridDim.x - 1 - (long)blockIdx.x;
+    col_fft_tile<R, INV, EPT, TWF, MS>(spec, ncols, M, cols_per_block, nthr, tile * cols_per_block, planM, tw, buf,
+                                      threadIdx.x);
 }
 
 template <class R, int EPT, bool TWF>

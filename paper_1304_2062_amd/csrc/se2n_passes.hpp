@@ -389,12 +389,15 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const bool pp = DIRECT && buf2 != nullptr;
     C2<R>* bx = buf;
     C2<R>* by = buf2;
-    SE2N_FETCH(s_begin);
-    for (int s = s_begin; s < s_end; ++s) {
+    // Slices are taken from the last to the first: the pass before this one
+    // wrote the high slices last, so they are the ones still held by the
+    // memory-side cache when this pass starts.
+    SE2N_FETCH(s_end - 1);
+    for (int s = s_end - 1; s >= s_begin; --s) {
       if constexpr (DIRECT) {
         fft_static_first<R, true, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, true>(
             pp ? bx : buf, tid, [&](int i) { return pre[i]; });
-        if (s + 1 < s_end) SE2N_FETCH(s + 1);
+        if (s > s_begin) SE2N_FETCH(s - 1);
       } else {
 #pragma unroll
         for (int i = 0; i < MAXL; ++i) {
@@ -402,7 +405,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
             if (kx < KL) buf[lds_pad(row_t * S + kx)] = pre[i];
         }
         __syncthreads();
-        if (s + 1 < s_end) SE2N_FETCH(s + 1);
+        if (s > s_begin) SE2N_FETCH(s - 1);
         if constexpr (!PAIRED) {
         // pairing step of the real inverse transform:
         //   Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]),  k < H
