@@ -582,7 +582,11 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             const int e = i / (CLS / VEC);
             const int c0 = (i - e * (CLS / VEC)) * VEC;
             v[k] = vec_t(0);
-            if (i < CH && c0 < ncls) v[k] = *reinterpret_cast<const vec_t*>(src + (size_t)e * Qs + c0);
+            // non-temporal: each propagator is read once per call, and keeping
+            // the table out of the caches leaves them to the spectrum, which
+            // the next pass reads again
+            if (i < CH && c0 < ncls)
+                v[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(src + (size_t)e * Qs + c0));
 #pragma unroll
             for (int q = 0; q < VEC; ++q)
                 if (c0 + q >= ncls) v[k][q] = R(0);
