@@ -292,7 +292,7 @@ int se2n_batch_get_tune(const se2n_item *items, int count, se2n_tune *out);
  *   pass 8 inverse column FFT on column pairs (k, M/2-k) with the pairing
  *          step of the real inverse row transform
  *                               {item, slice * blocks + pair block, 0, 0}
- *   pass 9 orientation stencil  {item, 64 x 64 tile (row-major), radius, 0}
+ *   pass 9 orientation stencil  {item, 128 x 32 tile (row-major), radius, 0}
  * tiles may be NULL to query *ntiles only; at most `capacity` tiles are
  * written.  Host only, no device work.
  * Errors: SE2N_EINVAL. */

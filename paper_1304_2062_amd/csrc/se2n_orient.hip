@@ -1,5 +1,5 @@
 // Orientation map of one image by the separable periodic stencil: one
-// workgroup per 64 x 64 tile of bins (the tile body and the reasoning behind
+// workgroup per 128 x 32 tile of bins (the tile body and the reasoning behind
 // it are in se2n_orient.hpp).
 #include "se2n_orient.hpp"
 
@@ -13,7 +13,10 @@ __global__ __launch_bounds__(kOrientNT) void k_orient_stencil(const float* __res
                                                               OrientTaps taps) {
     __shared__ float sa[orient_lds_floats<RAD>()];  // g (*)_y f_c
     __shared__ float sb[orient_lds_floats<RAD>()];  // d (*)_y f_c
-    orient_stencil_tile<RAD>(f, mask, rmap, M, N, (int)blockIdx.x, taps, sa, sb, (int)threadIdx.x);
+    // each XCD takes one contiguous band of tiles: the halo rows two tiles
+    // share are fetched through one L2
+    const int tile = xcd_contiguous((int)blockIdx.x, (int)gridDim.x);
+    orient_stencil_tile<RAD>(f, mask, rmap, M, N, tile, taps, sa, sb, (int)threadIdx.x);
 }
 
 }  // namespace

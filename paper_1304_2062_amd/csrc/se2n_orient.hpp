@@ -13,7 +13,7 @@
 // convolutions are short stencils; the host truncates them there (or keeps
 // the whole circle for small M) and passes the taps as kernel arguments.
 //
-// One workgroup makes a 64 x 64 tile of bins: a vertical pass (both kernels,
+// One workgroup makes a 128 x 32 tile of bins: a vertical pass (both kernels,
 // 8 rows per thread from a register window over global memory) writes the
 // two partial results for the tile's columns plus the horizontal halo to
 // LDS; a horizontal pass (16 columns per thread) finishes g_x and g_y and
@@ -28,8 +28,8 @@
 
 namespace se2n {
 
-constexpr int kOrientTX = 64;   // tile columns
-constexpr int kOrientTY = 64;   // tile rows
+constexpr int kOrientTX = 128;  // tile columns
+constexpr int kOrientTY = 32;   // tile rows
 constexpr int kOrientNT = 256;  // threads
 constexpr int kOrientCV = 8;    // rows per vertical item
 constexpr int kOrientCH = 16;   // columns per horizontal item
@@ -42,8 +42,7 @@ template <int RAD>
 constexpr int orient_lds_floats() { return kOrientTY * orient_lds_stride<RAD>(); }
 
 inline int orient_tiles(int M) {
-    const int t = (M + kOrientTX - 1) / kOrientTX;
-    return t * t;
+    return ((M + kOrientTX - 1) / kOrientTX) * ((M + kOrientTY - 1) / kOrientTY);
 }
 
 __device__ __forceinline__ int orient_wrap(int i, int M) {
@@ -51,7 +50,7 @@ __device__ __forceinline__ int orient_wrap(int i, int M) {
     return i < 0 ? i + M : i;
 }
 
-// Bins of tile `tile` (row-major over ceil(M/64)^2 tiles); sa and sb hold
+// Bins of tile `tile` (row-major over the tiles of the image); sa and sb hold
 // orient_lds_floats<RAD>() floats each.
 template <int RAD>
 __device__ __forceinline__ void orient_stencil_tile(const float* __restrict__ f, const uint8_t* __restrict__ mask,

@@ -138,18 +138,18 @@ def test_column_tiles_partition_every_column_run(lib, tune):
 
 
 @pytest.mark.parametrize("tune", TUNES)
-def test_stencil_tiles_cover_every_64_by_64_tile_of_stencil_items(lib, tune):
+def test_stencil_tiles_cover_every_128_by_32_tile_of_stencil_items(lib, tune):
     """Pass 9 holds exactly the items without FFT-route orientation passes, one
-    tile per 64 x 64 block of bins, with the item's compiled radius."""
+    tile per 128 x 32 block of bins, with the item's compiled radius."""
     arr = items_of(SPECS, SIGMAS)
     st = tiles(lib, arr, 9, tune)
     routes = 0
     for i, (M, N, _) in enumerate(SPECS):
         rad = stencil_radius(lib, M, SIGMAS[i])
         mine = sorted(t[1:] for t in st if t[0] == i)
-        nt = -(-M // 64)
+        nt = -(-M // 128) * -(-M // 32)
         if rad > 0:
-            assert mine == [(tt, rad, 0) for tt in range(nt * nt)]
+            assert mine == [(tt, rad, 0) for tt in range(nt)]
             routes |= 1
         else:
             assert mine == []
