@@ -136,7 +136,9 @@ __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spe
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
     C2<R>* buf = tw + tw_elems(M, false);
     load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr);
-    col_inv_paired_tile<R, EPT, MS>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x);
+    const int P = (MS ? GC.pcols : pcols_) / 2;
+    const int nslices = (int)gridDim.x / ((M / 4 + 1 + P - 1) / P);  // grid: slices x pair blocks
+    col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x, nslices);
 }
 
 // ---------------------------------------------------------------------------

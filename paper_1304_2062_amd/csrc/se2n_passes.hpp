@@ -205,10 +205,10 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
 // overwrite columns k and H-k (column H is left alone: the row pass reads
 // Z[0 .. H-1] only).  The inverse FFT_H of Z along x is then M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int EPT, int MS>
+template <class R, int EPT, int MS, bool HINTS = false>
 __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, int M_, int pcols_, int nthr_,
                                                     int tile, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
-                                                    int tid) {
+                                                    int tid, int nslices = 0) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int pc = MS ? GC.pcols : pcols_;
@@ -230,15 +230,39 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
     // H-p0-np+1 .. H-p0 (the self-paired column M/4 is read twice).
     const int half = np * M;
     const int c2 = H - p0 - np + 1;
+    // With HINTS (single-image pass, nslices slices): the input is read
+    // non-temporally (its last use), and the slices below nslices/2, which
+    // the inverse row pass reaches last (it walks slices downwards), are
+    // stored non-temporally, which leaves the memory-side cache to the rest.
+    typedef R v2_t __attribute__((ext_vector_type(2)));
+    auto ld = [&](const C2<R>* p) {
+        if constexpr (HINTS) {
+            const v2_t v = __builtin_nontemporal_load(reinterpret_cast<const v2_t*>(p));
+            return cmk<R>(v.x, v.y);
+        } else {
+            return *p;
+        }
+    };
+    const bool nts = HINTS && 2 * r < nslices;
+    auto st = [&](C2<R>* p, C2<R> v) {
+        if (nts) {
+            v2_t w;
+            w.x = v.x;
+            w.y = v.y;
+            __builtin_nontemporal_store(w, reinterpret_cast<v2_t*>(p));
+        } else {
+            *p = v;
+        }
+    };
     for (int e = tid; e < nel; e += nthr) {
         if (e < half) {
-            buf[lds_pad(e)] = base[(size_t)p0 * M + e];
+            buf[lds_pad(e)] = ld(base + (size_t)p0 * M + e);
         } else {
             const int e2 = e - half;
             const int cm = fdiv(e2, inv_M);           // memory column c2 + cm = H - p0 - q
             const int y = e2 - cm * M;
             const int q = np - 1 - cm;
-            buf[lds_pad(half + q * M + y)] = base[(size_t)c2 * M + e2];
+            buf[lds_pad(half + q * M + y)] = ld(base + (size_t)c2 * M + e2);
         }
     }
     __syncthreads();
@@ -258,12 +282,12 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
         const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
         const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
         const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, false>(tw, k, M4)), da);
-        base[(size_t)k * M + y] = cmk<R>(sa.x - ta.y, sa.y + ta.x);  // sa + i ta
+        st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
         if (k != 0 && kk != k) {
             const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
             const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
             const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, false>(tw, kk, M4)), db);
-            base[(size_t)kk * M + y] = cmk<R>(sb.x - tb.y, sb.y + tb.x);
+            st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
         }
     }
 }
