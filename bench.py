@@ -59,6 +59,26 @@ def algorithmic_bytes(M: int, N: int, real: int = 4) -> dict:
     }
 
 
+def solve_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
+    """Bytes the solve must move given the negligible-class flags ([Q][Q], 1 =
+    negligible): every mode of the half spectrum is written, only the modes of
+    live classes are read, and only live classes' propagators.  A class
+    (lx, ly) holds 2 columns kx (1 at lx = M/4) times 4 rows ky (2 at ly = 0
+    and ly = M/4) of every slice."""
+    K = M // 2 + 1
+    c = 2 * real
+    Q = M // 4 + 1
+    h = N // 2
+    nkx = np.full(Q, 2)
+    nkx[M // 4] = 1
+    nky = np.full(Q, 4)
+    nky[0] = 2
+    nky[M // 4] = 2
+    live = flags == 0
+    live_modes = int((np.outer(nkx, nky) * live).sum())
+    return N * K * M * c + N * live_modes * c + int(live.sum()) * h * (h + 1) * real
+
+
 # Names of the library's timed launches in rocprofv3's short kernel names.
 ROCPROF_NAME = {
     "lift_row_fwd": r"k_row_fwd<float,0,",
@@ -108,11 +128,14 @@ def cpu_baseline(case, crop: int) -> dict:
     }
 
 
-def batch_algorithmic_bytes(params) -> dict:
-    """Algorithmic bytes of each batched pass: the per-image figures summed over the batch."""
+def batch_algorithmic_bytes(params, flags=None) -> dict:
+    """Algorithmic bytes of each batched pass: the per-image figures summed over
+    the batch (the solve's from each image's negligible-class flags if given)."""
     acc = {}
-    for p in params:
+    for i, p in enumerate(params):
         a = algorithmic_bytes(p["M"], p["N"], 4)
+        if flags is not None:
+            a["solve"] = solve_bytes(p["M"], p["N"], flags[i], 4)
         for k, b in (("b_orient_stencil", a["orient_stencil"]),
                      ("b_orient_row_fwd", a["orient_row_fwd"]), ("b_orient_col", a["orient_col"]),
                      ("b_orient_row_inv", a["orient_row_inv"]), ("b_lift_row_fwd", a["lift_row_fwd"]),
@@ -197,7 +220,9 @@ def bench_batch(args) -> int:
         se2n.inpaint_batched(items, ws)
     stats = se2n.batch_profile_stats()
     se2n.batch_profile(False)
-    alg = batch_algorithmic_bytes(params)
+    # negligible-class flags of each image's parameters (the batch computes the same tables)
+    flags = [plans[(p["M"], p["N"])].propagator_flags(p["T"], p["beta"], p["n_steps"]) for p in params]
+    alg = batch_algorithmic_bytes(params, flags)
     kernels = {}
     for name, (launches, total) in stats.items():
         per_batch = total / args.steps
@@ -374,6 +399,12 @@ def main() -> int:
     stats = plan.profile_stats()
     plan.profile(False)
     alg = algorithmic_bytes(M, N, 4)
+    # the solve skips classes whose propagator is negligible at this T
+    flags = plan.propagator_flags(T, beta, n)
+    negligible = float(flags.mean())
+    alg["solve"] = solve_bytes(M, N, flags, 4)
+    print(f"[bench] negligible classes {negligible:.3f}; solve moves {alg['solve'] / 1e6:.0f} MB",
+          file=sys.stderr, flush=True)
     kernels = {}
     for name, (launches, total) in stats.items():
         avg = total / launches
@@ -426,6 +457,7 @@ def main() -> int:
             "M": M, "N": N, "beta": beta, "T": T, "n_steps": n, "sigma": sigma, "seed": case["seed"],
         },
         "rel_l2_vs_fp64": rel,
+        "solve_negligible_classes": negligible,
         "cold_ms": cold_ms,
         "precompute_ms": cold_stats.get("precompute", (0, None))[1],
         "roofline": roofline,

@@ -95,6 +95,19 @@ size_t se2n_workspace_bytes(se2n_plan plan);
 int se2n_precompute(se2n_plan plan, double T, double beta, int n_steps,
                     se2n_scheme scheme, void *stream);
 
+/* Frequency classes whose propagator is negligible for (T, beta, n_steps,
+ * scheme): every entry below 2^-30 (FP32 plans) or 2^-60 (FP64 plans).  Their
+ * modes are exactly zero at time T to within the rounding of the result
+ * (the dropped part of a mode is at most (N/2) 2^-30 of its input), so the
+ * diffusion writes zeros there without reading the mode or its propagator.
+ * flags [Q][Q] uint8 host buffer, Q = M/4 + 1 (class (lx, ly) at lx*Q + ly):
+ * 1 = negligible.  Computes the propagators on `stream` if they are not
+ * cached, then waits for the stream.  *Q receives M/4 + 1; flags may be
+ * NULL to query it, else capacity must be at least Q*Q.
+ * Errors: SE2N_EINVAL (bad parameters, capacity too small), SE2N_ENOMEM, SE2N_EHIP. */
+int se2n_propagator_flags(se2n_plan plan, double T, double beta, int n_steps,
+                          se2n_scheme scheme, void *stream, uint8_t *flags, long capacity, int *Q);
+
 /* Orientation map of the corrupted image (Sec. "A final inpainting algorithm
  * ...": Gaussian smoothing and gradient at the level of the FFT, nearest angle;
  * the gradient is taken on the corrupted image as the paper does).

@@ -654,7 +654,7 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         if (!bp.tables.count(tk)) {
             const size_t Q = (size_t)(M / 4 + 1), Qs = (size_t)table_stride<float>(M), h = (size_t)(x.N / 2);
             void* d = nullptr;
-            const hipError_t e = hipMalloc(&d, Q * Qs * h * (h + 1) * sizeof(float));
+            const hipError_t e = hipMalloc(&d, Q * Qs * h * (h + 1) * sizeof(float) + Q * Qs + 64);  // + class flags
             if (e != hipSuccess) return fail(SE2N_ENOMEM, "hipMalloc of a propagator table: %s", hipGetErrorString(e));
             bp.tables[tk] = d;
             SE2N_HIP(launch_precompute<float>((float*)d, M, x.N, x.beta, x.T, x.n, x.scheme, st),

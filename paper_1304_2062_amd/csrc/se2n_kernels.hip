@@ -230,6 +230,7 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     __syncthreads();
     const int Eh = h * (h + 1) / 2;
     const int E = 2 * Eh;
+    double pmax = 0.0;  // largest entry of the unscaled propagator, this thread's share
     for (int blk = 0; blk < 2; ++blk) {
         const double wrap = blk == 0 ? 1.0 : -1.0;
         for (int idx = tid; idx < hh; idx += 64) {
@@ -329,12 +330,20 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
             const int j = idx - i * h;
             if (j >= i) {
                 const int e = blk * Eh + i * h - i * (i - 1) / 2 + (j - i);
-                const double v = 0.5 * (Rs[i * h + j] + Rs[j * h + i]) * scale;
-                dst[(size_t)e * Qs] = (R)v;
+                const double u = 0.5 * (Rs[i * h + j] + Rs[j * h + i]);
+                pmax = fmax(pmax, fabs(u));
+                dst[(size_t)e * Qs] = (R)(u * scale);
             }
         }
         __syncthreads();
     }
+    // negligible-class flag (the workgroup is one wavefront): set when every
+    // entry of both blocks is below 2^-30 (FP32) or 2^-60 (FP64); the solve
+    // then writes zeros for the class's modes without reading them
+    for (int off = 32; off >= 1; off >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
+    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * E * Qs);
+    if (tid == 0) flags[(size_t)lx * Qs + ly] = pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
+    if (ly == Q - 1 && ly + 1 + tid < Qs) flags[(size_t)lx * Qs + ly + 1 + tid] = 0;  // row padding
 }
 
 // ---------------------------------------------------------------------------

@@ -587,6 +587,21 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
     constexpr int NT = 16 * CLS < 512 ? 16 * CLS : 512;  // blockDim.x: two lanes per mode
     const int nthr = NT;
     const int ncls = min(CLS, Q - ly0);
+    // One byte per class after the table (rows padded to Qs): 1 where the
+    // class's propagator is negligible (every entry below 2^-30 in FP32,
+    // 2^-60 in FP64, before the 1/(2M^2) scaling), so its modes are zero at
+    // time T to within the rounding of the result.
+    const uint8_t* __restrict__ flags =
+        reinterpret_cast<const uint8_t*>(P + (size_t)Q * E * Qs) + (size_t)lx * Qs + ly0;
+    // A thread's staging chunks all start at the same class (NT is a multiple
+    // of CLS/VEC) and its mode pairs all have the same class (NT/2 is a
+    // multiple of CLS): both flags are read once, ahead of the loads they gate.
+    const int cs0 = (tid % (CLS * (int)sizeof(R) / 16)) * (16 / (int)sizeof(R));
+    const int cm = (tid >> 1) % CLS;
+    static_assert(NT % (CLS * (int)sizeof(R) / 16) == 0 && (NT / 2) % CLS == 0, "fixed classes per thread");
+    const bool skip_chunk = sizeof(R) == 4 ? *reinterpret_cast<const uint32_t*>(flags + cs0) == 0x01010101u
+                                            : *reinterpret_cast<const uint16_t*>(flags + cs0) == 0x0101u;
+    const bool negligible = flags[cm] != 0;
     // Stage the block's propagators: 16-byte chunks, every load of a thread
     // issued before the first is waited on.  A chunk that starts inside the
     // block's classes lies inside the line-padded row; classes past the last
@@ -608,8 +623,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             v[k] = vec_t(0);
             // non-temporal: each propagator is read once per call, and keeping
             // the table out of the caches leaves them to the spectrum, which
-            // the next pass reads again
-            if (i < CH && c0 < ncls)
+            // the next pass reads again.  A chunk of negligible classes only
+            // (flag bytes all 1) is not read: its modes are set to zero below.
+            if (i < CH && c0 < ncls && !skip_chunk)
                 v[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(src + (size_t)e * Qs + c0));
 #pragma unroll
             for (int q = 0; q < VEC; ++q)
@@ -642,6 +658,7 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         live = live && !(a == 1 && 2 * lx == H);           // kx = M/4 is its own mirror
         live = live && !(ly == 0 && b >= 2);               // ky in {0, M/2} only
         live = live && !(2 * ly == H && (b & 1));          // ky in {M/4, 3M/4} only
+        const bool read = live && !negligible;             // negligible classes: zeros, nothing read
         const int kx = a ? H - lx : lx;
         int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
         if (!live) ky = 0;  // harmless in-range address; nothing is stored
@@ -650,8 +667,8 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         C2<R>* colbase = spec + (size_t)kx * M;
         const R* Pc = Ps + (size_t)odd * Eh * CLS + c;
 
-        // this lane's half of the orientation vector (every address is valid;
-        // dead lanes read row 0 and discard it)
+        // this lane's half of the orientation vector (lanes of dead or
+        // negligible modes read nothing and hold zeros)
         C2<R> x[h];
 #pragma unroll
         for (int j = 0; j < h; ++j) {
@@ -660,9 +677,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             const int a1 = perm ? N - r1 : r1;
             const C2<R>* pl0 = colbase + (size_t)a0 * plane;  // wave-uniform
             const C2<R>* pl1 = colbase + (size_t)a1 * plane;
-            const C2<R> v = odd ? pl1[ky] : pl0[ky];
-            x[j].x = live ? v.x : R(0);
-            x[j].y = live ? v.y : R(0);
+            C2<R> v = cmk<R>(R(0), R(0));
+            if (read) v = odd ? pl1[ky] : pl0[ky];
+            x[j] = v;
         }
         // even lane: p = x_j + x_{j+h};  odd lane: q = x_j - x_{j+h}
 #pragma unroll
@@ -700,7 +717,7 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             const R oy = swap_pair(y[j].y);
             y[j] = odd ? cmk<R>(ox - y[j].x, oy - y[j].y) : cmk<R>(y[j].x + ox, y[j].y + oy);
         }
-        if (live) {
+        if (live) {  // negligible classes store the zeros they were given
 #pragma unroll
             for (int j = 0; j < h; ++j) {
                 const int r0 = j, r1 = j + h;

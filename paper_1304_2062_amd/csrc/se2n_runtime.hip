@@ -251,7 +251,7 @@ struct se2n_plan_s {
         const size_t Q = (size_t)(M / 4 + 1);
         const size_t Qs = (size_t)(dt == SE2N_F32 ? table_stride<float>(M) : table_stride<double>(M));
         const size_t h = (size_t)(N / 2);
-        return Q * Qs * h * (h + 1) * real_size();
+        return Q * Qs * h * (h + 1) * real_size() + Q * Qs + 64;  // + one flag byte per class (padded rows)
     }
 };
 
@@ -655,6 +655,32 @@ int se2n_precompute(se2n_plan p, double T, double beta, int n_steps, se2n_scheme
     if (rc) return rc;
     const void* P = nullptr;
     return get_propagators(p, T, beta, n_steps, scheme, (hipStream_t)stream, &P);
+}
+
+int se2n_propagator_flags(se2n_plan p, double T, double beta, int n_steps, se2n_scheme scheme, void* stream,
+                          uint8_t* flags, long capacity, int* Q) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    rc = check_diffusion_params(T, beta, n_steps, scheme);
+    if (rc) return rc;
+    if (!Q) return fail(SE2N_EINVAL, "null pointer argument");
+    const int q = p->M / 4 + 1;
+    *Q = q;
+    if (!flags) return SE2N_OK;
+    if (capacity < (long)q * q) return fail(SE2N_EINVAL, "capacity %ld < Q*Q = %ld", capacity, (long)q * q);
+    const void* P = nullptr;
+    hipStream_t st = (hipStream_t)stream;
+    rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
+    if (rc) return rc;
+    const int N = p->N;
+    const size_t E = (size_t)(N / 2) * (N / 2 + 1);
+    const size_t Qs = (size_t)(p->dt == SE2N_F32 ? table_stride<float>(p->M) : table_stride<double>(p->M));
+    const uint8_t* dflags = (const uint8_t*)P + (size_t)q * E * Qs * p->real_size();
+    SE2N_HIP(hipMemcpy2DAsync(flags, (size_t)q, dflags, Qs, (size_t)q, (size_t)q, hipMemcpyDeviceToHost, st),
+             "copy of the class flags");
+    SE2N_HIP(hipStreamSynchronize(st), "hipStreamSynchronize after the flag copy");
+    return SE2N_OK;
 }
 
 int se2n_orient(se2n_plan p, const void* f, const uint8_t* mask, double sigma, uint8_t* rmap, void* workspace,

@@ -36,6 +36,7 @@ _lib.se2n_workspace_bytes.restype = ctypes.c_size_t
 _lib.se2n_precompute.argtypes = [_vp, _d, _d, _i, _i, _vp]
 _lib.se2n_orient.argtypes = [_vp, _vp, _vp, _d, _vp, _vp, _vp]
 _lib.se2n_orient_method.argtypes = [_vp, _d, ctypes.POINTER(_i)]
+_lib.se2n_propagator_flags.argtypes = [_vp, _d, _d, _i, _i, _vp, _vp, ctypes.c_long, ctypes.POINTER(_i)]
 _lib.se2n_lift.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 _lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
 _lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
@@ -52,7 +53,7 @@ _lib.se2n_profile_stats.argtypes = [_vp, ctypes.POINTER(KernelStat), _i, ctypes.
 _lib.se2n_profile_stats.restype = _i
 _lib.se2n_last_error.restype = ctypes.c_char_p
 _lib.se2n_version.restype = ctypes.c_char_p
-for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_orient_method", "se2n_lift",
+for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_orient_method", "se2n_propagator_flags", "se2n_lift",
               "se2n_diffuse", "se2n_project", "se2n_inpaint"):
     getattr(_lib, _name).restype = _i
 
@@ -137,6 +138,17 @@ class Plan:
         _check(_lib.se2n_orient(self._h, _ptr(f), _ptr(mask), float(sigma), _ptr(rmap), _ptr(self.workspace()),
                                 _vp(_stream())))
         return rmap
+
+    def propagator_flags(self, T: float, beta: float, n_steps: int, scheme: str = "cn"):
+        """[Q][Q] uint8 host array, Q = M/4 + 1: 1 where the class's propagator is negligible."""
+        import numpy as np
+        q = _i(0)
+        _check(_lib.se2n_propagator_flags(self._h, float(T), float(beta), int(n_steps), _SCHEMES[scheme],
+                                          _vp(_stream()), None, 0, ctypes.byref(q)))
+        out = np.zeros((q.value, q.value), dtype=np.uint8)
+        _check(_lib.se2n_propagator_flags(self._h, float(T), float(beta), int(n_steps), _SCHEMES[scheme],
+                                          _vp(_stream()), out.ctypes.data, out.size, ctypes.byref(q)))
+        return out
 
     def orient_radius(self, sigma: float = 2.0) -> int:
         """Compiled radius of the orientation stencil for sigma, 0 for the FFT route."""

@@ -209,3 +209,22 @@ def test_full_heterogeneous_batch_against_single_images(se2n):
         _say(f"  item {k} M={p['M']} N={p['N']}: rel vs single {rel:.2e}")
         assert rel < 1e-6
     se2n.batch_clear()
+
+
+def test_poisoned_workspace_leaks_nothing(se2n):
+    """Long diffusion times (many negligible classes, whose modes the solve
+    sets to zero without reading them) with the batch workspace filled with
+    NaN bytes: every item still equals the single-image path."""
+    params = [dict(p, T=4.0, n_steps=400) for p in _small_params()]
+    items = _items(se2n, params)
+    ws = se2n.batch_workspace(items)
+    ws.fill_(255)
+    se2n.inpaint_batched(items, ws)
+    torch.cuda.synchronize()
+    for p, it in zip(params, items):
+        got = it.out.cpu().numpy()
+        assert np.all(np.isfinite(got)), p["M"]
+        ref, rref = _single(se2n, p, None)
+        assert np.array_equal(it.rmap_out.cpu().numpy(), rref)
+        assert _rel(got, ref) < 1e-6, (p["M"], p["N"])
+    se2n.batch_clear()

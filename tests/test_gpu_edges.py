@@ -127,3 +127,80 @@ def test_zero_time_full_size_inpaint_is_the_lifted_maximum(se2n):
     _say(f"T=0 full size: max abs error {err:.3e}")
     assert err < 1e-5
     plan.close()
+
+
+def _oracle_blocks(M, N, lx, ly, T, beta, n):
+    """Unscaled periodic and antiperiodic blocks of the class propagator from the
+    oracle's per-mode Crank-Nicolson applied to the unit vectors."""
+    eye = np.eye(N, dtype=np.complex128)
+    P = O.diffuse_modes_cn(eye, M, [lx] * N, [ly] * N, beta, T, n).real.T  # column j = P e_j
+    h = N // 2
+    A, B = P[:h, :h], P[:h, h:]
+    return A + B, A - B
+
+
+@pytest.mark.parametrize("dtype,thr", [(torch.float32, 2.0 ** -30), (torch.float64, 2.0 ** -60)])
+def test_negligible_class_flags_match_the_oracle(se2n, dtype, thr):
+    """A class is flagged exactly when every entry of both blocks of its
+    propagator is below the threshold (classes within a factor 2 of it are
+    not judged: the two computations round differently)."""
+    M, N, T, beta, n = 128, 16, 4.0, 1.0, 400
+    plan = se2n.Plan(M, N, dtype)
+    flags = plan.propagator_flags(T, beta, n)
+    Q = M // 4 + 1
+    assert flags.shape == (Q, Q)
+    judged = mism = 0
+    for lx in range(Q):
+        for ly in range(Q):
+            p, q = _oracle_blocks(M, N, lx, ly, T, beta, n)
+            m = max(np.abs(p).max(), np.abs(q).max())
+            if thr / 2 < m < 2 * thr:
+                continue
+            judged += 1
+            mism += int(flags[lx, ly] != (m < thr))
+    frac = float(flags.mean())
+    _say(f"{dtype}: negligible classes {frac:.3f}, judged {judged}, mismatches {mism}")
+    assert mism == 0
+    assert judged > 0.9 * Q * Q
+    if dtype == torch.float32:
+        assert frac > 0.05  # the skip path is exercised (0.12 at this size and time)
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_inpaint_with_many_negligible_classes_matches_the_oracle(se2n, dtype):
+    """Long diffusion time: a large share of classes is skipped by the solve
+    (zeros written, nothing read) and the result still matches the oracle."""
+    M, N, T, beta, n = 128, 16, 4.0, 1.0, 400
+    f = synth.make_image(77, M, "small")
+    mask = synth.mask_random(78, M, 0.6).astype(np.uint8)
+    plan = se2n.Plan(M, N, dtype)
+    frac = float(plan.propagator_flags(T, beta, n).mean())
+    fin = f if dtype == torch.float64 else f.astype(np.float32).astype(np.float64)
+    out, rmap = plan.inpaint(_dev(fin, dtype), _dev(mask), T, beta, n)
+    torch.cuda.synchronize()
+    want, _ = O.inpaint(fin, mask, N, T, beta, n, rmap=rmap.cpu().numpy())
+    err = _rel(out.cpu().numpy(), want)
+    _say(f"{dtype}: negligible {frac:.3f}, rel-L2 {err:.3e}")
+    assert err < TOL[dtype]
+    plan.close()
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32])
+def test_poisoned_workspace_leaks_nothing(se2n, dtype):
+    """The solve writes zeros for the modes of negligible classes without
+    reading them: filling the workspace with NaN bytes first must not change
+    the result (no stale or skipped value reaches the output)."""
+    M, N, T, beta, n = 128, 16, 4.0, 1.0, 400
+    f = synth.make_image(91, M, "small")
+    mask = synth.mask_random(92, M, 0.5).astype(np.uint8)
+    fin = f if dtype == torch.float64 else f.astype(np.float32).astype(np.float64)
+    plan = se2n.Plan(M, N, dtype)
+    plan.workspace().fill_(255)
+    out, rmap = plan.inpaint(_dev(fin, dtype), _dev(mask), T, beta, n)
+    torch.cuda.synchronize()
+    got = out.cpu().numpy()
+    assert np.all(np.isfinite(got))
+    want, _ = O.inpaint(fin, mask, N, T, beta, n, rmap=rmap.cpu().numpy())
+    assert _rel(got, want) < TOL[dtype]
+    plan.close()
