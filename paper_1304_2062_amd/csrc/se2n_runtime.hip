@@ -677,9 +677,11 @@ int se2n_propagator_flags(se2n_plan p, double T, double beta, int n_steps, se2n_
     const size_t E = (size_t)(N / 2) * (N / 2 + 1);
     const size_t Qs = (size_t)(p->dt == SE2N_F32 ? table_stride<float>(p->M) : table_stride<double>(p->M));
     const uint8_t* dflags = (const uint8_t*)P + (size_t)q * E * Qs * p->real_size();
-    SE2N_HIP(hipMemcpy2DAsync(flags, (size_t)q, dflags, Qs, (size_t)q, (size_t)q, hipMemcpyDeviceToHost, st),
-             "copy of the class flags");
-    SE2N_HIP(hipStreamSynchronize(st), "hipStreamSynchronize after the flag copy");
+    // the precompute ran on `st`; copy the padded rows synchronously, then unpad
+    SE2N_HIP(hipStreamSynchronize(st), "hipStreamSynchronize before the flag copy");
+    std::vector<uint8_t> rows((size_t)q * Qs);
+    SE2N_HIP(hipMemcpy(rows.data(), dflags, rows.size(), hipMemcpyDeviceToHost), "copy of the class flags");
+    for (int lx = 0; lx < q; ++lx) std::memcpy(flags + (size_t)lx * q, rows.data() + (size_t)lx * Qs, (size_t)q);
     return SE2N_OK;
 }
 
