@@ -466,7 +466,7 @@ int build_schedule(BatchPlan& bp) {
         OrientTaps taps;
     };
     std::vector<Part> parts;
-    auto add_pass = [&](int kind, int pass) {
+    auto add_pass_fwd = [&](int kind, int pass) {
         std::vector<int4> all = ordered_tiles(bp.shapes, bp.tune, pass);
         if (kind == BK_ORIENT_STENCIL) {
             // one launch per (M, sigma), largest sides first
@@ -522,14 +522,25 @@ int build_schedule(BatchPlan& bp) {
             }
         }
     };
+    // reverse: the pass's launches and tiles run in the opposite order, so
+    // that it starts on the images the previous pass finished with (the
+    // memory-side cache still holds their most recent lines)
+    auto add_pass = [&](int kind, int pass, bool reverse = false) {
+        const size_t first = parts.size();
+        add_pass_fwd(kind, pass);
+        if (reverse) {
+            std::reverse(parts.begin() + first, parts.end());
+            for (size_t k = first; k < parts.size(); ++k) std::reverse(parts[k].tiles.begin(), parts[k].tiles.end());
+        }
+    };
     add_pass(BK_ORIENT_STENCIL, 9);
     add_pass(BK_ORIENT_ROW, 0);
     add_pass(BK_ORIENT_COL, 1);
     add_pass(BK_ORIENT_INV, 2);
     add_pass(BK_LIFT_ROW, 3);
-    add_pass(BK_COL_FWD, 4);
+    add_pass(BK_COL_FWD, 4, true);
     add_pass(BK_SOLVE, 5);
-    add_pass(BK_COL_INV, 8);
+    add_pass(BK_COL_INV, 8, true);
     add_pass(BK_FILL, 7);
     add_pass(BK_ROW_INV_MAX, 6);
     add_pass(BK_DECODE, 7);
