@@ -1,0 +1,56 @@
+"""Host logic of bench.py's roofline accounting (no GPU): the solve's bytes as a
+function of the negligible-class flags.  The members of the frequency classes
+must tile the half spectrum exactly once, checked here by brute force."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+
+
+def fold(k, M):
+    H, M4 = M // 2, M // 4
+    return k if k <= M4 else (H - k if k <= H else (k - H if k <= 3 * M4 else M - k))
+
+
+@pytest.mark.parametrize("M", [16, 24, 48, 64, 72, 128])
+def test_class_members_tile_the_half_spectrum(M):
+    """Every (kx, ky) of the half spectrum belongs to exactly one class, and the
+    member counts the accounting uses (2 or 1 columns, 4 or 2 rows) add up."""
+    Q = M // 4 + 1
+    count = np.zeros((Q, Q), dtype=np.int64)
+    for kx in range(M // 2 + 1):
+        for ky in range(M):
+            count[fold(kx, M), fold(ky, M)] += 1
+    nkx = np.full(Q, 2)
+    nkx[M // 4] = 1
+    nky = np.full(Q, 4)
+    nky[0] = 2
+    nky[M // 4] = 2
+    assert np.array_equal(count, np.outer(nkx, nky))
+
+
+@pytest.mark.parametrize("M,N", [(64, 8), (128, 16), (2048, 32)])
+def test_solve_bytes_limits_and_monotonicity(M, N):
+    Q = M // 4 + 1
+    K = M // 2 + 1
+    V = N * K * M * 8
+    full = bench.algorithmic_bytes(M, N, 4)["solve"]
+    assert bench.solve_bytes(M, N, np.zeros((Q, Q), np.uint8), 4) == full
+    assert bench.solve_bytes(M, N, np.ones((Q, Q), np.uint8), 4) == V  # only the zeros are written
+    rng = np.random.default_rng(M)
+    flags = (rng.random((Q, Q)) < 0.5).astype(np.uint8)
+    b = bench.solve_bytes(M, N, flags, 4)
+    assert V < b < full
+    # one more negligible class removes exactly its members' reads and its table entries
+    i, j = np.argwhere(flags == 0)[0]
+    more = flags.copy()
+    more[i, j] = 1
+    nk = (1 if i == M // 4 else 2) * (2 if j in (0, M // 4) else 4)
+    h = N // 2
+    assert b - bench.solve_bytes(M, N, more, 4) == N * nk * 8 + h * (h + 1) * 4
