@@ -38,9 +38,13 @@ def short_name(name: str) -> str:
 
 
 def kernel_source_hash() -> str:
-    """Hash of the device sources; a traffic record is valid only for these."""
+    """Hash of the sources the single-image path is built from (kernels, tile
+    bodies, FFT core, host runtime); a traffic record is valid only for these.
+    The batched and corrector sources do not enter it."""
     h = hashlib.sha256()
     for p in sorted(glob.glob(os.path.join(HERE, "csrc", "*"))):
+        if os.path.basename(p).startswith(("se2n_batch", "se2n_cnn")):
+            continue
         with open(p, "rb") as fh:
             h.update(os.path.basename(p).encode())
             h.update(fh.read())
