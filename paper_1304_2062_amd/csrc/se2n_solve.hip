@@ -14,10 +14,11 @@ template <class R, int N, int CLS, int WAVES>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_solve(
     C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q, int Qs) {
     extern __shared__ unsigned char smem_raw[];
-    // adjacent class blocks of one lx share the cache lines at the ends of
-    // their mirrored (reversed) ky runs: keep them on one XCD
+    // plain block order: negligible classes gather at large lx, so contiguous
+    // per-XCD bands of lx would leave the XCD holding the small lx with most
+    // of the work; interleaving spreads it evenly
     const int nb = (Q + CLS - 1) / CLS;
-    const int blk = xcd_contiguous(blockIdx.x, gridDim.x);
+    const int blk = blockIdx.x;
     const int lx = blk / nb;
     solve_tile<R, N, CLS>(spec, P, M, Q, Qs, lx, (blk - lx * nb) * CLS, reinterpret_cast<R*>(smem_raw),
                           threadIdx.x);
