@@ -215,7 +215,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
         const int4 tl = tiles[t];
         const BItem& d = item_of(items, tl.x);
         __syncthreads();
-        solve_tile<float, N, CLS>(uni(d.spec), uni(d.P), uni(d.M), uni(d.Q), uni(d.Qs), tl.y, tl.z, Ps,
+        solve_tile<float, N, CLS>(uni(d.spec), uni(d.P), uni(d.M), uni(d.Q), uni(d.FS), tl.y, tl.z, Ps,
                                   opaque_tid());
     }
 }

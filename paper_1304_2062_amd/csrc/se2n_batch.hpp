@@ -23,7 +23,7 @@ struct BItem {
     unsigned* enc;     // max-combining buffer [M][M] (workspace)
     const float* P;    // propagator table of (M, N, T, beta, n, scheme)
     const C2<float>* tw;  // quarter-wave twiddles of M
-    int M, N, K, rows, cols, ocols, pcols, proj, groups, Q, Qs;
+    int M, N, K, rows, cols, ocols, pcols, proj, groups, Q, FS;
     float ocoef, oscale;  // orientation: -2 pi^2 sigma^2 / M^2 and sqrt(M)/M^2
     FftPlan planH, planM;
 };

@@ -199,9 +199,7 @@ std::vector<Tile> raw_tiles(const std::vector<Shape>& sh, const se2n_tune& t, in
             }
             case 5: {
                 const int Q = M / 4 + 1;
-                int cls = 64;  // classes per tile of the solve instance for N
-                const int h = N / 2, E = h * (h + 1);
-                while (cls > 1 && (long)E * cls * 4 > 72 * 1024) cls >>= 1;
+                const int cls = solve_classes(N, 4);  // classes per tile of the solve instance for N
                 for (int lx = 0; lx < Q; ++lx)
                     for (int ly = 0; ly < Q; ly += cls)
                         out.push_back({make_int4(i, lx, ly, N), (double)std::min(cls, Q - ly) * 8.0 * N * N});
@@ -583,10 +581,7 @@ int build_schedule(BatchPlan& bp) {
                     need = (size_t)(tw_elems(M, false) + lds_padded_size(2 * g.ocols * M)) * sizeof(C2<float>);
                     break;
                 case BK_SOLVE: {
-                    const int h = x.N / 2, E = h * (h + 1);
-                    int cls = 64;
-                    while (cls > 1 && (long)E * cls * 4 > 72 * 1024) cls >>= 1;
-                    need = (size_t)E * cls * sizeof(float);
+                    need = (size_t)solve_lds_stride(x.N, 4) * solve_classes(x.N, 4) * sizeof(float);
                     break;
                 }
                 default:
@@ -663,9 +658,8 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         // propagators, one table per distinct parameter set (computed on the caller's stream)
         const TableKey tk{M, x.N, x.n, x.scheme, x.T, x.beta};
         if (!bp.tables.count(tk)) {
-            const size_t Q = (size_t)(M / 4 + 1), Qs = (size_t)table_stride<float>(M), h = (size_t)(x.N / 2);
             void* d = nullptr;
-            const hipError_t e = hipMalloc(&d, Q * Qs * h * (h + 1) * sizeof(float) + Q * Qs + 64);  // + class flags
+            const hipError_t e = hipMalloc(&d, table_bytes(M, x.N, 4));  // class-major propagators + class flags
             if (e != hipSuccess) return fail(SE2N_ENOMEM, "hipMalloc of a propagator table: %s", hipGetErrorString(e));
             bp.tables[tk] = d;
             SE2N_HIP(launch_precompute<float>((float*)d, M, x.N, x.beta, x.T, x.n, x.scheme, st),
@@ -685,7 +679,7 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         b.proj = x.proj;
         b.groups = groups_of(x, bp.tune);
         b.Q = M / 4 + 1;
-        b.Qs = table_stride<float>(M);
+        b.FS = flag_stride(M);
         b.ocoef = (float)(-2.0 * 9.869604401089358619 * x.sigma * x.sigma / ((double)M * M));
         b.oscale = (float)(std::sqrt((double)M) / ((double)M * M));
         b.planH = make_fft_plan(M / 2, M);

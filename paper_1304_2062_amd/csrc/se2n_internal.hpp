@@ -142,13 +142,43 @@ __host__ __device__ constexpr int xcd_contiguous(int i, int n) {
     return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-// Row stride (in elements) of the propagator table P[lx][element][ly]: the
-// M/4 + 1 classes of a row rounded up to a whole number of 128-byte lines,
-// so that a workgroup's contiguous run of classes touches no extra line.
-template <class R>
-__host__ __device__ constexpr int table_stride(int M) {
-    constexpr int line = 128 / (int)sizeof(R);
-    return (M / 4 + 1 + line - 1) / line * line;
+// Propagator table P[lx][ly][element], lx, ly in [0, M/4].  Class (lx, ly)
+// holds the packed upper triangles of its periodic and antiperiodic blocks,
+// (N/2)(N/2 + 1) reals, padded to whole 128-byte lines: the classes a solve
+// workgroup stages form one contiguous run, and a negligible class that is
+// skipped shares no line with a live one.
+__host__ __device__ constexpr int table_class_stride(int N, int rsize) {
+    const int line = 128 / rsize;
+    const int E = (N / 2) * (N / 2 + 1);
+    return (E + line - 1) / line * line;
+}
+
+// The negligible-class flags follow the table: one byte per class, rows of
+// M/4 + 1 bytes padded to 128.
+__host__ __device__ constexpr int flag_stride(int M) { return (M / 4 + 1 + 127) / 128 * 128; }
+
+// Bytes of a propagator table with its flags (and 64 bytes of slack).
+__host__ __device__ constexpr size_t table_bytes(int M, int N, int rsize) {
+    const size_t Q = (size_t)(M / 4 + 1);
+    return Q * Q * (size_t)table_class_stride(N, rsize) * (size_t)rsize + Q * (size_t)flag_stride(M) + 64;
+}
+
+// LDS layout of the propagators a solve workgroup stages: class c at c * S,
+// its periodic block at offset 0 and its antiperiodic block at the odd
+// offset OQ.  A wavefront reads one entry of 32 consecutive classes from
+// both blocks at once; with S = 2 (mod 4) in FP32 the even lanes' classes
+// fall in distinct even banks and the odd lanes' in distinct odd banks.
+__host__ __device__ constexpr int solve_q_offset(int N) { return ((N / 2) * (N / 2 + 1) / 2) | 1; }
+__host__ __device__ constexpr int solve_lds_stride(int N, int rsize) {
+    const int need = solve_q_offset(N) + (N / 2) * (N / 2 + 1) / 2;
+    return rsize == 4 ? need + (6 - need % 4) % 4 : (need | 1);
+}
+// Classes per solve workgroup: the largest power of two <= 64 whose staged
+// propagators fit in 72 KB of LDS.
+__host__ __device__ constexpr int solve_classes(int N, int rsize) {
+    int c = 64;
+    while (c > 1 && (long)solve_lds_stride(N, rsize) * c * rsize > 72 * 1024) c >>= 1;
+    return c;
 }
 
 template <class R>

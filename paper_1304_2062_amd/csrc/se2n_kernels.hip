@@ -204,7 +204,7 @@ __device__ void lds_copy(const double* A, double* B, int n, int tid) {
 }
 
 template <class R>
-__global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q, int Qs,
+__global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q, int FS,
                                                    double beta, double T, int nsteps, int scheme,
                                                    double scale) {
     extern __shared__ double sm[];
@@ -230,6 +230,7 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     __syncthreads();
     const int Eh = h * (h + 1) / 2;
     const int E = 2 * Eh;
+    const int CS = table_class_stride(N, (int)sizeof(R));
     double pmax = 0.0;  // largest entry of the unscaled propagator, this thread's share
     for (int blk = 0; blk < 2; ++blk) {
         const double wrap = blk == 0 ? 1.0 : -1.0;
@@ -324,7 +325,7 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
             }
         }
         // packed upper triangle, symmetrised, scaled, stored as R
-        R* dst = Ptab + (size_t)lx * E * Qs + ly;
+        R* dst = Ptab + ((size_t)lx * Q + ly) * CS;
         for (int idx = tid; idx < hh; idx += 64) {
             const int i = idx / h;
             const int j = idx - i * h;
@@ -332,7 +333,7 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
                 const int e = blk * Eh + i * h - i * (i - 1) / 2 + (j - i);
                 const double u = 0.5 * (Rs[i * h + j] + Rs[j * h + i]);
                 pmax = fmax(pmax, fabs(u));
-                dst[(size_t)e * Qs] = (R)(u * scale);
+                dst[e] = (R)(u * scale);
             }
         }
         __syncthreads();
@@ -341,9 +342,12 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     // entry of both blocks is below 2^-30 (FP32) or 2^-60 (FP64); the solve
     // then writes zeros for the class's modes without reading them
     for (int off = 32; off >= 1; off >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
-    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * E * Qs);
-    if (tid == 0) flags[(size_t)lx * Qs + ly] = pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
-    if (ly == Q - 1 && ly + 1 + tid < Qs) flags[(size_t)lx * Qs + ly + 1 + tid] = 0;  // row padding
+    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * Q * CS);
+    if (tid == 0) flags[(size_t)lx * FS + ly] = pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
+    if (ly == Q - 1)  // row padding
+        for (int j = ly + 1 + tid; j < FS; j += 64) flags[(size_t)lx * FS + j] = 0;
+    // the class's line padding
+    for (int e = E + tid; e < CS; e += 64) Ptab[((size_t)lx * Q + ly) * CS + e] = R(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -550,7 +554,7 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
     const size_t lds = (size_t)(6 * h * h + h) * sizeof(double);
     const double scale = 1.0 / (2.0 * (double)M * (double)M);
     hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q,
-                       table_stride<R>(M), beta,
+                       flag_stride(M), beta,
                        T, nsteps, scheme, scale);
     return hipGetLastError();
 }

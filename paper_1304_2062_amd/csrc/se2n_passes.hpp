@@ -558,7 +558,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
 // through the mirrored orientation index.
 //
 // A workgroup takes one lx and CLS consecutive ly, stages their propagators
-// in LDS once (a contiguous row of CLS values per element), and applies them
+// in LDS once (one contiguous run of the class-major table), and applies them
 // to all 8 members of each class.  Each mode is handled by a pair of adjacent
 // lanes: the even lane loads x_j and the odd lane x_{j+N/2} (j < N/2); one
 // DPP swap gives the even lane p = x_j + x_{j+N/2} and the odd lane
@@ -579,63 +579,69 @@ __device__ __forceinline__ double swap_pair(double v) {
 
 template <class R, int N, int CLS>
 __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q,
-                                           int Qs, int lx, int ly0, R* Ps, int tid) {
+                                           int FS, int lx, int ly0, R* Ps, int tid) {
     constexpr int h = N / 2;
     constexpr int Eh = h * (h + 1) / 2;
     constexpr int E = 2 * Eh;
+    constexpr int CS = table_class_stride(N, (int)sizeof(R));  // reals per class in the table
+    constexpr int S = solve_lds_stride(N, (int)sizeof(R));     // and in LDS
+    constexpr int OQ = solve_q_offset(N);                      // LDS offset of the antiperiodic block
+    static_assert(CLS <= 64, "one flag bit per class in a wavefront mask");
     const int H = M >> 1;
     constexpr int NT = 16 * CLS < 512 ? 16 * CLS : 512;  // blockDim.x: two lanes per mode
     const int nthr = NT;
     const int ncls = min(CLS, Q - ly0);
-    // One byte per class after the table (rows padded to Qs): 1 where the
+    // One byte per class after the table (rows of FS bytes): 1 where the
     // class's propagator is negligible (every entry below 2^-30 in FP32,
     // 2^-60 in FP64, before the 1/(2M^2) scaling), so its modes are zero at
-    // time T to within the rounding of the result.
-    const uint8_t* __restrict__ flags =
-        reinterpret_cast<const uint8_t*>(P + (size_t)Q * E * Qs) + (size_t)lx * Qs + ly0;
-    // A thread's staging chunks all start at the same class (NT is a multiple
-    // of CLS/VEC) and its mode pairs all have the same class (NT/2 is a
-    // multiple of CLS): both flags are read once, ahead of the loads they gate.
-    const int cs0 = (tid % (CLS * (int)sizeof(R) / 16)) * (16 / (int)sizeof(R));
-    const int cm = (tid >> 1) % CLS;
-    static_assert(NT % (CLS * (int)sizeof(R) / 16) == 0 && (NT / 2) % CLS == 0, "fixed classes per thread");
-    const bool skip_chunk = sizeof(R) == 4 ? *reinterpret_cast<const uint32_t*>(flags + cs0) == 0x01010101u
-                                            : *reinterpret_cast<const uint16_t*>(flags + cs0) == 0x0101u;
-    const bool negligible = flags[cm] != 0;
-    // Stage the block's propagators: 16-byte chunks, every load of a thread
-    // issued before the first is waited on.  A chunk that starts inside the
-    // block's classes lies inside the line-padded row; classes past the last
-    // one are zeroed.
+    // time T to within the rounding of the result.  Each wavefront gathers
+    // the block's flags into a mask, bit c for class ly0 + c; classes past
+    // the last one count as negligible (nothing is read for them).
+    uint64_t negm;
+    {
+        const uint8_t* __restrict__ flags =
+            reinterpret_cast<const uint8_t*>(P + (size_t)Q * Q * CS) + (size_t)lx * FS + ly0;
+        const int l = tid & 63;
+        negm = __ballot(l >= ncls || flags[l] != 0);
+    }
+    // Stage the block's propagators, class c at Ps + c * S: 16-byte chunks
+    // of the contiguous run, every load of a thread issued before the first
+    // is waited on.  Chunks of negligible classes are not read; they and the
+    // classes past the last one are zeroed (their modes are multiplied by
+    // zeros, never by stale LDS).
     {
         constexpr int VEC = 16 / (int)sizeof(R);
         typedef R vec_t __attribute__((ext_vector_type(VEC)));
-        constexpr int CH = E * CLS / VEC;  // CLS >= 8 is a multiple of VEC
+        constexpr int CPC = CS / VEC;  // chunks per class
+        constexpr int CH = CLS * CPC;
         constexpr int NST = (CH + NT - 1) / NT;
         constexpr int BATCH = NST < 8 ? NST : 8;  // loads in flight per thread
-        const R* __restrict__ src = P + (size_t)lx * E * Qs + ly0;
+        const R* __restrict__ src = P + ((size_t)lx * Q + ly0) * CS;
         for (int k0 = 0; k0 < NST; k0 += BATCH) {
-        vec_t v[BATCH];
+            vec_t v[BATCH];
 #pragma unroll
-        for (int k = 0; k < BATCH; ++k) {
-            const int i = tid + (k0 + k) * NT;
-            const int e = i / (CLS / VEC);
-            const int c0 = (i - e * (CLS / VEC)) * VEC;
-            v[k] = vec_t(0);
-            // non-temporal: each propagator is read once per call, and keeping
-            // the table out of the caches leaves them to the spectrum, which
-            // the next pass reads again.  A chunk of negligible classes only
-            // (flag bytes all 1) is not read: its modes are set to zero below.
-            if (i < CH && c0 < ncls && !skip_chunk)
-                v[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(src + (size_t)e * Qs + c0));
+            for (int k = 0; k < BATCH; ++k) {
+                const int i = tid + (k0 + k) * NT;
+                v[k] = vec_t(0);
+                // non-temporal: each propagator is read once per call, and
+                // keeping the table out of the caches leaves them to the
+                // spectrum, which the next pass reads again
+                if (i < CH && !((negm >> (i / CPC)) & 1))
+                    v[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(src + (size_t)i * VEC));
+            }
 #pragma unroll
-            for (int q = 0; q < VEC; ++q)
-                if (c0 + q >= ncls) v[k][q] = R(0);
-        }
+            for (int k = 0; k < BATCH; ++k) {
+                const int i = tid + (k0 + k) * NT;
+                if (i < CH) {
+                    const int c = i / CPC;
+                    const int f = (i - c * CPC) * VEC;
 #pragma unroll
-        for (int k = 0; k < BATCH; ++k) {
-            const int i = tid + (k0 + k) * NT;
-            if (i < CH) reinterpret_cast<vec_t*>(Ps)[i] = v[k];
-        }
+                    for (int q = 0; q < VEC; ++q) {
+                        const int e = f + q;
+                        if (e < E) Ps[c * S + (e < Eh ? e : e + (OQ - Eh))] = v[k][q];
+                    }
+                }
+            }
         }
     }
     __syncthreads();
@@ -658,14 +664,14 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         live = live && !(a == 1 && 2 * lx == H);           // kx = M/4 is its own mirror
         live = live && !(ly == 0 && b >= 2);               // ky in {0, M/2} only
         live = live && !(2 * ly == H && (b & 1));          // ky in {M/4, 3M/4} only
-        const bool read = live && !negligible;             // negligible classes: zeros, nothing read
+        const bool read = live && !((negm >> c) & 1);      // negligible classes: zeros, nothing read
         const int kx = a ? H - lx : lx;
         int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
         if (!live) ky = 0;  // harmless in-range address; nothing is stored
         // s_ky < 0 exactly for the live members b = 2, 3 (ky in (M/2, M))
         const bool perm = b >= 2;
         C2<R>* colbase = spec + (size_t)kx * M;
-        const R* Pc = Ps + (size_t)odd * Eh * CLS + c;
+        const R* Pc = Ps + c * S + odd * OQ;
 
         // this lane's half of the orientation vector (lanes of dead or
         // negligible modes read nothing and hold zeros)
@@ -697,7 +703,7 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             for (int i = 0; i < h; ++i) {
 #pragma unroll
                 for (int j = i; j < h; ++j) {
-                    const R w = Pc[e * CLS];
+                    const R w = Pc[e];
                     y[i].x += w * x[j].x;
                     y[i].y += w * x[j].y;
                     if (j != i) {
@@ -730,15 +736,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
     }
 }
 
-// Classes per tile: the largest power of two <= 64 whose propagators fit in
-// 72 KB of LDS.
 template <class R, int N>
 constexpr int solve_cls() {
-    constexpr int h = N / 2;
-    constexpr int E = h * (h + 1);
-    int c = 64;
-    while (c > 1 && (long)E * c * (long)sizeof(R) > 72 * 1024) c >>= 1;
-    return c;
+    return solve_classes(N, (int)sizeof(R));
 }
 
 }  // namespace se2n

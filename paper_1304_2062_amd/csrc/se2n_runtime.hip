@@ -247,12 +247,8 @@ struct se2n_plan_s {
     size_t enc_bytes() const { return align256((size_t)M * M * real_size()); }
     size_t rmap_bytes() const { return align256((size_t)M * M); }
     size_t workspace() const { return spec_bytes() + enc_bytes() + rmap_bytes(); }
-    size_t table_bytes() const {
-        const size_t Q = (size_t)(M / 4 + 1);
-        const size_t Qs = (size_t)(dt == SE2N_F32 ? table_stride<float>(M) : table_stride<double>(M));
-        const size_t h = (size_t)(N / 2);
-        return Q * Qs * h * (h + 1) * real_size() + Q * Qs + 64;  // + one flag byte per class (padded rows)
-    }
+    // class-major propagators + one flag byte per class (padded rows)
+    size_t table_bytes() const { return se2n::table_bytes(M, N, (int)real_size()); }
 };
 
 namespace {
@@ -673,15 +669,14 @@ int se2n_propagator_flags(se2n_plan p, double T, double beta, int n_steps, se2n_
     hipStream_t st = (hipStream_t)stream;
     rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
     if (rc) return rc;
-    const int N = p->N;
-    const size_t E = (size_t)(N / 2) * (N / 2 + 1);
-    const size_t Qs = (size_t)(p->dt == SE2N_F32 ? table_stride<float>(p->M) : table_stride<double>(p->M));
-    const uint8_t* dflags = (const uint8_t*)P + (size_t)q * E * Qs * p->real_size();
+    const int rs = (int)p->real_size();
+    const size_t FS = (size_t)flag_stride(p->M);
+    const uint8_t* dflags = (const uint8_t*)P + (size_t)q * q * table_class_stride(p->N, rs) * rs;
     // the precompute ran on `st`; copy the padded rows synchronously, then unpad
     SE2N_HIP(hipStreamSynchronize(st), "hipStreamSynchronize before the flag copy");
-    std::vector<uint8_t> rows((size_t)q * Qs);
+    std::vector<uint8_t> rows((size_t)q * FS);
     SE2N_HIP(hipMemcpy(rows.data(), dflags, rows.size(), hipMemcpyDeviceToHost), "copy of the class flags");
-    for (int lx = 0; lx < q; ++lx) std::memcpy(flags + (size_t)lx * q, rows.data() + (size_t)lx * Qs, (size_t)q);
+    for (int lx = 0; lx < q; ++lx) std::memcpy(flags + (size_t)lx * q, rows.data() + (size_t)lx * FS, (size_t)q);
     return SE2N_OK;
 }
 

@@ -12,15 +12,21 @@ namespace se2n {
 
 template <class R, int N, int CLS, int WAVES>
 __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) void k_solve(
-    C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q, int Qs) {
+    C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q, int FS) {
     extern __shared__ unsigned char smem_raw[];
-    // plain block order: negligible classes gather at large lx, so contiguous
-    // per-XCD bands of lx would leave the XCD holding the small lx with most
-    // of the work; interleaving spreads it evenly
+    // Workgroups go to the eight XCDs round-robin.  All class blocks of one lx
+    // run on XCD lx mod 8, one after another: adjacent blocks share the cache
+    // lines at the ends of their mirrored (descending) ky runs, which then
+    // come from that XCD's L2 once.  Interleaving lx over the XCDs, rather
+    // than giving each a band of lx, keeps their work even: the negligible
+    // classes, whose modes are not read, gather at large lx.  The grid is
+    // 8 * ceil(Q/8) * nb; workgroups past the last lx return at once.
     const int nb = (Q + CLS - 1) / CLS;
-    const int blk = blockIdx.x;
-    const int lx = blk / nb;
-    solve_tile<R, N, CLS>(spec, P, M, Q, Qs, lx, (blk - lx * nb) * CLS, reinterpret_cast<R*>(smem_raw),
+    const int s = blockIdx.x >> 3;
+    const int row = s / nb;
+    const int lx = (int)(blockIdx.x & 7) + 8 * row;
+    if (lx >= Q) return;
+    solve_tile<R, N, CLS>(spec, P, M, Q, FS, lx, (s - row * nb) * CLS, reinterpret_cast<R*>(smem_raw),
                           threadIdx.x);
 }
 
@@ -30,14 +36,12 @@ static hipError_t launch_solve_n(C2<R>* spec, const R* P, int M, hipStream_t st)
     // occupancy target: 4 waves/SIMD (<= 128 VGPRs) while a lane's half
     // vector and accumulator fit, else 2 (<= 256 VGPRs) rather than spill
     constexpr int WAVES = (N * (int)sizeof(R)) <= 160 ? 4 : 2;
-    constexpr int h = N / 2;
-    constexpr int E = h * (h + 1);
     const int Q = M / 4 + 1;
-    const dim3 grid((unsigned)(((Q + CLS - 1) / CLS) * Q));
+    const dim3 grid((unsigned)(8 * ((Q + 7) / 8) * ((Q + CLS - 1) / CLS)));
     const int threads = 16 * CLS < 512 ? 16 * CLS : 512;  // the kernel's NT
-    const size_t lds = (size_t)E * CLS * sizeof(R);
+    const size_t lds = (size_t)solve_lds_stride(N, (int)sizeof(R)) * CLS * sizeof(R);
     hipLaunchKernelGGL((k_solve<R, N, CLS, WAVES>), grid, dim3(threads), lds, st, spec, P, M, Q,
-                       table_stride<R>(M));
+                       flag_stride(M));
     return hipGetLastError();
 }
 
