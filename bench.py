@@ -59,24 +59,36 @@ def algorithmic_bytes(M: int, N: int, real: int = 4) -> dict:
     }
 
 
-def solve_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
-    """Bytes the solve must move given the negligible-class flags ([Q][Q], 1 =
-    negligible): every mode of the half spectrum is written, only the modes of
-    live classes are read, and only live classes' propagators.  A class
-    (lx, ly) holds 2 columns kx (1 at lx = M/4) times 4 rows ky (2 at ly = 0
-    and ly = M/4) of every slice."""
-    K = M // 2 + 1
-    c = 2 * real
+def live_modes(M: int, flags: np.ndarray) -> int:
+    """Modes of one slice of the half spectrum whose class is live ([Q][Q]
+    flags, 1 = negligible).  A class (lx, ly) holds 2 columns kx (1 at
+    lx = M/4) times 4 rows ky (2 at ly = 0 and ly = M/4)."""
     Q = M // 4 + 1
-    h = N // 2
     nkx = np.full(Q, 2)
     nkx[M // 4] = 1
     nky = np.full(Q, 4)
     nky[0] = 2
     nky[M // 4] = 2
-    live = flags == 0
-    live_modes = int((np.outer(nkx, nky) * live).sum())
-    return N * K * M * c + N * live_modes * c + int(live.sum()) * h * (h + 1) * real
+    return int((np.outer(nkx, nky) * (flags == 0)).sum())
+
+
+def solve_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
+    """Bytes the solve must move given the negligible-class flags: every mode
+    of the half spectrum is written, only the modes of live classes are read,
+    and only live classes' propagators."""
+    K = M // 2 + 1
+    c = 2 * real
+    h = N // 2
+    return N * K * M * c + N * live_modes(M, flags) * c + int((flags == 0).sum()) * h * (h + 1) * real
+
+
+def col_fwd_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
+    """Bytes the forward column pass must move when it leaves out the modes
+    of negligible classes (the solve overwrites them unread): the whole half
+    spectrum is read, only the live modes are written."""
+    K = M // 2 + 1
+    c = 2 * real
+    return N * K * M * c + N * live_modes(M, flags) * c
 
 
 # Names of the library's timed launches in rocprofv3's short kernel names.
@@ -399,10 +411,12 @@ def main() -> int:
     stats = plan.profile_stats()
     plan.profile(False)
     alg = algorithmic_bytes(M, N, 4)
-    # the solve skips classes whose propagator is negligible at this T
+    # the solve reads nothing of classes whose propagator is negligible at
+    # this T, and the forward column pass does not write their modes
     flags = plan.propagator_flags(T, beta, n)
     negligible = float(flags.mean())
     alg["solve"] = solve_bytes(M, N, flags, 4)
+    alg["col_fft_fwd"] = col_fwd_bytes(M, N, flags, 4)
     print(f"[bench] negligible classes {negligible:.3f}; solve moves {alg['solve'] / 1e6:.0f} MB",
           file=sys.stderr, flush=True)
     kernels = {}

@@ -157,6 +157,12 @@ __host__ __device__ constexpr int table_class_stride(int N, int rsize) {
 // M/4 + 1 bytes padded to 128.
 __host__ __device__ constexpr int flag_stride(int M) { return (M / 4 + 1 + 127) / 128 * 128; }
 
+// The flags of a table at P (the bytes after its propagators).
+__host__ __device__ inline const uint8_t* table_flags(const void* P, int M, int N, int rsize) {
+    const size_t Q = (size_t)(M / 4 + 1);
+    return reinterpret_cast<const uint8_t*>(P) + Q * Q * (size_t)table_class_stride(N, rsize) * (size_t)rsize;
+}
+
 // Bytes of a propagator table with its flags (and 64 bytes of slack).
 __host__ __device__ constexpr size_t table_bytes(int M, int N, int rsize) {
     const size_t Q = (size_t)(M / 4 + 1);
@@ -185,9 +191,11 @@ template <class R>
 hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_t* rmap, const R* vol,
                           C2<R>* spec, int M, int nslices, const LaunchGeom& g, const FftPlan& planH,
                           const C2<R>* tw, hipStream_t st);
+// negf: the negligible-class flags of the propagators the solve applies next
+// (forward pass only; those modes are then not stored), or null.
 template <class R>
 hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
-                          const FftPlan& planM, const C2<R>* tw, hipStream_t st);
+                          const FftPlan& planM, const C2<R>* tw, hipStream_t st, const uint8_t* negf = nullptr);
 template <class R>
 hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftPlan& planM,
                              const C2<R>* tw, double sigma, hipStream_t st);

@@ -75,7 +75,8 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const
 // Column pass: one tile of cols_per_block contiguous columns per workgroup.
 template <class R, bool INV, int EPT, bool TWF, int MS>
 __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M_, int cols_per_block_,
-                          FftPlan planM, const C2<R>* __restrict__ twg) {
+                          FftPlan planM, const C2<R>* __restrict__ twg, const uint8_t* __restrict__ negf,
+                          int FS) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int cols_per_block = MS ? GC.cols : cols_per_block_;
@@ -88,7 +89,7 @@ __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M_, int cols
     // wrote the high slices last, and the memory-side cache still holds them
     const long tile = (long)gridDim.x - 1 - (long)blockIdx.x;
     col_fft_tile<R, INV, EPT, TWF, MS>(spec, ncols, M, cols_per_block, nthr, tile * cols_per_block, planM, tw, buf,
-                                      threadIdx.x);
+                                      threadIdx.x, negf, FS);
 }
 
 template <class R, int EPT, bool TWF>
@@ -413,12 +414,12 @@ hipError_t launch_row_fwd(int src, const R* f, const uint8_t* mask, const uint8_
 
 template <class R>
 hipError_t launch_col_fft(bool inverse, C2<R>* spec, long ncols, int M, const LaunchGeom& g,
-                          const FftPlan& planM, const C2<R>* tw, hipStream_t st) {
+                          const FftPlan& planM, const C2<R>* tw, hipStream_t st, const uint8_t* negf) {
     dim3 grid((unsigned)((ncols + g.cols - 1) / g.cols));
     const size_t lds = tw_bytes<R>(M, g.tw_full_col != 0) + (size_t)lds_padded_size(g.cols * M) * sizeof(C2<R>);
 #define SE2N_COL(I, E, W, MSV)                                                                                 \
     hipLaunchKernelGGL((k_col_fft<R, I, E, W, MSV>), grid, dim3(g.col_threads), lds, st, spec, ncols, M, g.cols, planM, \
-                       tw)
+                       tw, negf, flag_stride(M))
 #define SE2N_COL_E(I)                                                   \
     if (static_size<R>(M, g) == 2048) SE2N_COL(I, 8, false, kStatic<R> ? 2048 : 0);      \
     else if (static_size<R>(M, g) == 1024) SE2N_COL(I, 8, false, kStatic<R> ? 1024 : 0); \
@@ -564,7 +565,7 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
                                           C2<R>*, int, int, const LaunchGeom&, const FftPlan&,         \
                                           const C2<R>*, hipStream_t);                                  \
     template hipError_t launch_col_fft<R>(bool, C2<R>*, long, int, const LaunchGeom&, const FftPlan&,  \
-                                          const C2<R>*, hipStream_t);                                  \
+                                          const C2<R>*, hipStream_t, const uint8_t*);                  \
     template hipError_t launch_col_orient<R>(C2<R>*, int, const LaunchGeom&, const FftPlan&,           \
                                              const C2<R>*, double, hipStream_t);                       \
     template hipError_t launch_row_inv<R>(int, const C2<R>*, R*, typename Enc<R>::U*, uint8_t*, int,   \

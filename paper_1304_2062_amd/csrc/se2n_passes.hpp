@@ -172,10 +172,29 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
 // Column pass: FFT along y of the columns [c0, c0 + ncb) (each M contiguous
 // values), ncb = min(cols_per_tile, ncols - c0).
 // ---------------------------------------------------------------------------
+// With `negf` set (the negligible-class flags of the propagator table that
+// the solve applies next, rows of FS bytes), the modes of negligible classes
+// are not stored: the solve overwrites each of them with zero without reading
+// it, and lines that hold no live mode never reach HBM.  Columns are
+// c = r * (M/2 + 1) + kx; mode (kx, ky) belongs to class (fold kx, fold ky).
+// This applies to full tiles of the compiled sizes whose thread count divides
+// M/4: thread tid then stores, in column q, the rows ky = tid + k nthr, which
+// fall in quadrant k / R4 (R4 = M / (4 nthr)) at offset t = tid + (k mod R4)
+// nthr, with class index t in the even quadrants and M/4 - t in the odd ones.
+// A per-element fold costs more VALU than the skipped stores save.
+template <class R, int MS>
+struct ColSkip {
+    static constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    static constexpr int R4 = MS ? MS / 4 / GC.col_threads : 0;
+    static constexpr int EPT = GC.cols * 4 * R4;  // elements a thread stores
+    static constexpr bool ok = MS != 0 && R4 >= 1 && (MS / 4) % GC.col_threads == 0 && EPT <= 16;
+};
+
 template <class R, bool INV, int EPT, bool TWF, int MS>
 __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncols, int M_, int cols_,
                                              int nthr_, long c0, const FftPlan& planM, const C2<R>* tw,
-                                             C2<R>* buf, int tid) {
+                                             C2<R>* buf, int tid, const uint8_t* __restrict__ negf = nullptr,
+                                             int FS = 0) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int cols_per_tile = MS ? GC.cols : cols_;
@@ -184,6 +203,30 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
     const int ncb = (int)min((long)cols_per_tile, ncols - c0);
     const int nel = ncb * M;
     C2<R>* base = spec + c0 * M;
+    using CS_ = ColSkip<R, MS>;
+    // negligible flag of the element tid + j * nthr: loaded ahead of the
+    // tile, used only by the stores after the transform, so their latency
+    // hides behind it
+    const bool skip = CS_::ok && negf != nullptr && ncb == cols_per_tile;
+    uint8_t fb[CS_::ok ? CS_::EPT : 1];
+    if constexpr (CS_::ok) {
+        if (skip) {
+            const int H = M >> 1;
+#pragma unroll
+            for (int q = 0; q < GC.cols; ++q) {
+                const int kx = ((int)c0 + q) % (H + 1);
+                const uint8_t* row = negf + (size_t)(kx <= M4 ? kx : H - kx) * FS;
+#pragma unroll
+                for (int r = 0; r < CS_::R4; ++r) {
+                    const int t = tid + r * GC.col_threads;
+                    const uint8_t f0 = row[t];
+                    const uint8_t f1 = row[M4 - t];
+#pragma unroll
+                    for (int quad = 0; quad < 4; ++quad) fb[q * 4 * CS_::R4 + quad * CS_::R4 + r] = (quad & 1) ? f1 : f0;
+                }
+            }
+        }
+    }
     for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
     __syncthreads();
     if constexpr (MS != 0) {
@@ -191,6 +234,23 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
         else fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
     } else {
         fft_lds<R, INV, EPT, TWF>(buf, planM, ncb, M, tw, M4, tid, nthr);
+    }
+    if constexpr (CS_::ok) {
+        if (skip) {
+            // a wavefront stores 64 consecutive elements; a line is skipped only
+            // when none of its modes is live (a partly written line still
+            // reaches HBM)
+            constexpr int LPL = 128 / (int)sizeof(C2<R>);  // lanes per 128-byte line
+            constexpr unsigned long long LMASK = (1ull << LPL) - 1;
+            const int lane = tid & 63;
+#pragma unroll
+            for (int j = 0; j < CS_::EPT; ++j) {
+                const int e = tid + j * GC.col_threads;
+                const unsigned long long live = __ballot(!fb[j]);
+                if ((live >> (lane & ~(LPL - 1))) & LMASK) base[e] = buf[lds_pad(e)];
+            }
+            return;
+        }
     }
     for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
 }

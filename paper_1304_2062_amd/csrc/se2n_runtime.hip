@@ -470,13 +470,17 @@ int orient_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, uint
 }
 
 // spec holds the forward half spectrum of all slices; propagate it in place.
-// The inverse column pass runs on column pairs and leaves the pairing step
-// of the real inverse row transform done (the row pass is then `paired`).
+// The forward column pass does not store the modes of negligible classes
+// (the solve writes their zeros).  The inverse column pass runs on column
+// pairs and leaves the pairing step of the real inverse row transform done
+// (the row pass is then `paired`).
 template <class R>
 int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
     const long ncols = (long)p->N * p->K();
-    SE2N_TIMED(p, "col_fft_fwd", st, launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st),
+    SE2N_TIMED(p, "col_fft_fwd", st,
+               launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st,
+                                 table_flags(P, p->M, p->N, (int)sizeof(R))),
                "forward column FFT");
     SE2N_TIMED(p, "solve", st, launch_solve<R>(spec, (const R*)P, p->M, p->N, st), "per-mode solve");
     SE2N_TIMED(p, "col_fft_inv", st, launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st),
@@ -671,7 +675,7 @@ int se2n_propagator_flags(se2n_plan p, double T, double beta, int n_steps, se2n_
     if (rc) return rc;
     const int rs = (int)p->real_size();
     const size_t FS = (size_t)flag_stride(p->M);
-    const uint8_t* dflags = (const uint8_t*)P + (size_t)q * q * table_class_stride(p->N, rs) * rs;
+    const uint8_t* dflags = table_flags(P, p->M, p->N, rs);
     // the precompute ran on `st`; copy the padded rows synchronously, then unpad
     SE2N_HIP(hipStreamSynchronize(st), "hipStreamSynchronize before the flag copy");
     std::vector<uint8_t> rows((size_t)q * FS);

@@ -54,3 +54,17 @@ def test_solve_bytes_limits_and_monotonicity(M, N):
     nk = (1 if i == M // 4 else 2) * (2 if j in (0, M // 4) else 4)
     h = N // 2
     assert b - bench.solve_bytes(M, N, more, 4) == N * nk * 8 + h * (h + 1) * 4
+
+
+@pytest.mark.parametrize("M,N", [(64, 8), (2048, 32)])
+def test_forward_column_bytes_limits(M, N):
+    """No negligible class: the whole spectrum is read and written; all
+    negligible: it is only read; one class more negligible removes exactly
+    its members' writes."""
+    Q = M // 4 + 1
+    V = N * (M // 2 + 1) * M * 8
+    assert bench.col_fwd_bytes(M, N, np.zeros((Q, Q), np.uint8)) == bench.algorithmic_bytes(M, N, 4)["col_fft_fwd"]
+    assert bench.col_fwd_bytes(M, N, np.ones((Q, Q), np.uint8)) == V
+    flags = np.zeros((Q, Q), np.uint8)
+    flags[0, M // 4] = 1  # columns kx in {0, M/2}, rows ky in {M/4, 3M/4}
+    assert bench.col_fwd_bytes(M, N, np.zeros((Q, Q), np.uint8)) - bench.col_fwd_bytes(M, N, flags) == N * 2 * 2 * 8

@@ -204,3 +204,64 @@ def test_poisoned_workspace_leaks_nothing(se2n, dtype):
     want, _ = O.inpaint(fin, mask, N, T, beta, n, rmap=rmap.cpu().numpy())
     assert _rel(got, want) < TOL[dtype]
     plan.close()
+
+
+def test_full_size_band_edges_follow_the_oracle(se2n):
+    """The timed shape (2048^2, N = 32, FP32, T = 4): about half the frequency
+    classes are negligible, in bands a few classes wide, and the forward
+    column pass then leaves out every line that holds no live mode.  Plane
+    waves in live classes at the edges of those bands (their lines are shared
+    with negligible modes) and in negligible classes, through members in all
+    four quadrants, must follow the oracle's per-mode Crank-Nicolson at
+    sampled voxels (the negligible ones decay to zero)."""
+    M, N, T, beta, n = 2048, 32, 4.0, 1.0, 400
+    H = M // 2
+    plan = se2n.Plan(M, N, torch.float32)
+    fl = plan.propagator_flags(T, beta, n)
+    live_inner, live_edges, negl = [], [], []
+    for lx in (2, 9, 37, 120, 263, 411, 500):
+        row = fl[lx]
+        e = [ly for ly in range(1, M // 4) if row[ly] == 0 and (row[ly - 1] == 1 or row[ly + 1] == 1)]
+        g = [ly for ly in range(1, M // 4) if row[ly] == 1]
+        if e:
+            live_edges.append((lx, e[len(e) // 2]))
+        if g:
+            negl.append((lx, g[len(g) // 2]))
+        # the live class farthest from any negligible one in this row
+        dist = [min((abs(ly - j) for j in g), default=M) if row[ly] == 0 else -1 for ly in range(M // 4 + 1)]
+        live_inner.append((lx, int(np.argmax(dist))))
+    assert len(live_edges) >= 3 and len(negl) >= 2
+    members = [lambda lx, ly: (lx, ly), lambda lx, ly: (H - lx, M - ly), lambda lx, ly: (lx, H + ly),
+               lambda lx, ly: (H - lx, H - ly)]
+    rng = np.random.default_rng(2048)
+    waves = []
+    for i, (lx, ly) in enumerate(live_inner[:4] + live_edges[:4] + negl[:2]):
+        k, l = members[i % 4](lx, ly)
+        waves.append((k, l, int(rng.integers(N)), float(rng.uniform(0.3, 1.0)), float(rng.uniform(-np.pi, np.pi))))
+    _say(f"waves (k, l, r): {[w[:3] for w in waves]}")
+    y, x = np.mgrid[0:M, 0:M]
+    psi0 = np.zeros((N, M, M), dtype=np.float32)
+    for (k, l, r, amp, phi) in waves:
+        psi0[r] += (amp * np.cos(2 * np.pi * (k * x + l * y) / M + phi)).astype(np.float32)
+    psi = _dev(psi0)
+    del psi0
+    plan.diffuse(psi, T, beta, n)
+    torch.cuda.synchronize()
+    S = 20000
+    rs = rng.integers(N, size=S)
+    ys = rng.integers(M, size=S)
+    xs = rng.integers(M, size=S)
+    got = psi[torch.from_numpy(rs).cuda(), torch.from_numpy(ys).cuda(), torch.from_numpy(xs).cuda()].cpu().numpy()
+    want = np.zeros(S)
+    for (k, l, r, amp, phi) in waves:
+        e = np.zeros((1, N), dtype=np.complex128)
+        e[0, r] = 1.0
+        v = O.diffuse_modes_cn(e, M, [k], [l], beta, T, n)[0].real
+        want += amp * v[rs] * np.cos(2 * np.pi * (k * xs + l * ys) / M + phi)
+    err = np.abs(got - want).max()
+    _say(f"band edges at full size: max error {err:.3e}, max |want| {np.abs(want).max():.3e}")
+    # the low-frequency waves survive to time T; a live line left out by the
+    # forward column pass would feed the solve row-pass data (errors ~1e-4)
+    assert np.abs(want).max() > 1e-2
+    assert err < 1e-6
+    plan.close()
