@@ -105,8 +105,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         const long ncols = (long)uni(d.N) * (M / 2 + 1);
         __syncthreads();
         ensure_twiddles<false>(tw, uni(d.tw), M, cur, col_nt<MS>());
+        // forward: the modes of the item's negligible classes are not stored
+        // (its solve, the next pass, overwrites them unread)
         col_fft_tile<float, INV, 8, false, MS>(uni(d.spec), ncols, M, uni(d.cols), BT, tl.y, d.planM, tw, buf,
-                                               opaque_tid());
+                                               opaque_tid(), INV ? nullptr : table_flags(uni(d.P), M, uni(d.N), 4),
+                                               uni(d.FS));
     }
 }
 

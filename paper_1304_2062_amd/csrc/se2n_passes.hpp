@@ -177,17 +177,23 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
 // are not stored: the solve overwrites each of them with zero without reading
 // it, and lines that hold no live mode never reach HBM.  Columns are
 // c = r * (M/2 + 1) + kx; mode (kx, ky) belongs to class (fold kx, fold ky).
-// This applies to full tiles of the compiled sizes whose thread count divides
-// M/4: thread tid then stores, in column q, the rows ky = tid + k nthr, which
-// fall in quadrant k / R4 (R4 = M / (4 nthr)) at offset t = tid + (k mod R4)
-// nthr, with class index t in the even quadrants and M/4 - t in the odd ones.
-// A per-element fold costs more VALU than the skipped stores save.
+// This applies to full tiles of the compiled sizes whose thread count nthr
+// divides M and either divides M/2 or is a multiple of it.  Thread tid then
+// stores, in column q, the rows ky = tid + k nthr (k < M / nthr); the class
+// index of a row depends only on u = ky mod M/2 (it is u for u <= M/4, else
+// M/2 - u), and u takes U = max(1, M / (2 nthr)) values per column, so a
+// thread needs U flags per column of its tile.  A per-element fold costs more
+// VALU than the skipped stores save.
 template <class R, int MS>
 struct ColSkip {
     static constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
-    static constexpr int R4 = MS ? MS / 4 / GC.col_threads : 0;
-    static constexpr int EPT = GC.cols * 4 * R4;  // elements a thread stores
-    static constexpr bool ok = MS != 0 && R4 >= 1 && (MS / 4) % GC.col_threads == 0 && EPT <= 16;
+    static constexpr int NT = GC.col_threads;
+    static constexpr int H = MS / 2;
+    static constexpr bool ok = MS != 0 && NT <= MS && MS % NT == 0 && (H % NT == 0 || NT % H == 0);
+    static constexpr int CPT = ok ? MS / NT : 1;           // chunks of nthr rows per column
+    static constexpr int U = ok && NT <= H ? H / NT : 1;   // values of ky mod M/2 per column
+    static constexpr int EPT = GC.cols * CPT;              // elements a thread stores
+    static_assert(!ok || EPT <= 16, "flags per thread");
 };
 
 template <class R, bool INV, int EPT, bool TWF, int MS>
@@ -211,19 +217,19 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
     uint8_t fb[CS_::ok ? CS_::EPT : 1];
     if constexpr (CS_::ok) {
         if (skip) {
-            const int H = M >> 1;
+            constexpr int H = CS_::H;
 #pragma unroll
             for (int q = 0; q < GC.cols; ++q) {
                 const int kx = ((int)c0 + q) % (H + 1);
                 const uint8_t* row = negf + (size_t)(kx <= M4 ? kx : H - kx) * FS;
+                uint8_t fu[CS_::U];
 #pragma unroll
-                for (int r = 0; r < CS_::R4; ++r) {
-                    const int t = tid + r * GC.col_threads;
-                    const uint8_t f0 = row[t];
-                    const uint8_t f1 = row[M4 - t];
-#pragma unroll
-                    for (int quad = 0; quad < 4; ++quad) fb[q * 4 * CS_::R4 + quad * CS_::R4 + r] = (quad & 1) ? f1 : f0;
+                for (int v = 0; v < CS_::U; ++v) {
+                    const int u = (tid + v * CS_::NT) % H;
+                    fu[v] = row[u <= M4 ? u : H - u];
                 }
+#pragma unroll
+                for (int k = 0; k < CS_::CPT; ++k) fb[q * CS_::CPT + k] = fu[k % CS_::U];
             }
         }
     }
