@@ -72,23 +72,39 @@ def live_modes(M: int, flags: np.ndarray) -> int:
     return int((np.outer(nkx, nky) * (flags == 0)).sum())
 
 
-def solve_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
-    """Bytes the solve must move given the negligible-class flags: every mode
-    of the half spectrum is written, only the modes of live classes are read,
-    and only live classes' propagators."""
+# Sides whose column passes leave out negligible modes (FP32): the forward
+# pass does not store them, the solve does not store them, the inverse pass
+# takes them as zero unread.  The single-image path has compiled column
+# kernels for 512, 1024 and 2048; the batch for sides up to 1024.
+SKIP_SIDES_SINGLE = (512, 1024, 2048)
+SKIP_SIDES_BATCH = (512, 1024)
+
+
+def solve_bytes(M: int, N: int, flags: np.ndarray, real: int = 4, skip: bool = False) -> int:
+    """Bytes the solve must move given the negligible-class flags: only the
+    modes and propagators of live classes are read; every mode is written,
+    or with `skip` only the live ones."""
     K = M // 2 + 1
     c = 2 * real
     h = N // 2
-    return N * K * M * c + N * live_modes(M, flags) * c + int((flags == 0).sum()) * h * (h + 1) * real
+    live = N * live_modes(M, flags) * c
+    return (live if skip else N * K * M * c) + live + int((flags == 0).sum()) * h * (h + 1) * real
 
 
 def col_fwd_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
     """Bytes the forward column pass must move when it leaves out the modes
-    of negligible classes (the solve overwrites them unread): the whole half
-    spectrum is read, only the live modes are written."""
+    of negligible classes: the whole half spectrum is read, only the live
+    modes are written."""
     K = M // 2 + 1
     c = 2 * real
     return N * K * M * c + N * live_modes(M, flags) * c
+
+
+def col_inv_bytes(M: int, N: int, flags: np.ndarray, real: int = 4) -> int:
+    """Bytes the inverse column pass must move when it takes the modes of
+    negligible classes as zero: only the live modes are read, the whole half
+    spectrum is written."""
+    return col_fwd_bytes(M, N, flags, real)
 
 
 # Names of the library's timed launches in rocprofv3's short kernel names.
@@ -147,7 +163,11 @@ def batch_algorithmic_bytes(params, flags=None) -> dict:
     for i, p in enumerate(params):
         a = algorithmic_bytes(p["M"], p["N"], 4)
         if flags is not None:
-            a["solve"] = solve_bytes(p["M"], p["N"], flags[i], 4)
+            skip = p["M"] in SKIP_SIDES_BATCH
+            a["solve"] = solve_bytes(p["M"], p["N"], flags[i], 4, skip)
+            if skip:
+                a["col_fft_fwd"] = col_fwd_bytes(p["M"], p["N"], flags[i], 4)
+                a["col_fft_inv"] = col_inv_bytes(p["M"], p["N"], flags[i], 4)
         for k, b in (("b_orient_stencil", a["orient_stencil"]),
                      ("b_orient_row_fwd", a["orient_row_fwd"]), ("b_orient_col", a["orient_col"]),
                      ("b_orient_row_inv", a["orient_row_inv"]), ("b_lift_row_fwd", a["lift_row_fwd"]),
@@ -412,11 +432,15 @@ def main() -> int:
     plan.profile(False)
     alg = algorithmic_bytes(M, N, 4)
     # the solve reads nothing of classes whose propagator is negligible at
-    # this T, and the forward column pass does not write their modes
+    # this T; at this side the column passes and the solve also leave their
+    # modes out (neither stored nor read)
     flags = plan.propagator_flags(T, beta, n)
     negligible = float(flags.mean())
-    alg["solve"] = solve_bytes(M, N, flags, 4)
-    alg["col_fft_fwd"] = col_fwd_bytes(M, N, flags, 4)
+    skip = M in SKIP_SIDES_SINGLE
+    alg["solve"] = solve_bytes(M, N, flags, 4, skip)
+    if skip:
+        alg["col_fft_fwd"] = col_fwd_bytes(M, N, flags, 4)
+        alg["col_fft_inv"] = col_inv_bytes(M, N, flags, 4)
     print(f"[bench] negligible classes {negligible:.3f}; solve moves {alg['solve'] / 1e6:.0f} MB",
           file=sys.stderr, flush=True)
     kernels = {}

@@ -128,7 +128,9 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         C* buf = tw + tw_elems(M, false);
         __syncthreads();
         ensure_twiddles<false>(tw, uni(d.tw), M, cur, pcol_nt<MS>());
-        col_inv_paired_tile<float, 8, MS>(uni(d.spec), M, uni(d.pcols), BT, tl.y, d.planM, tw, buf, opaque_tid());
+        col_inv_paired_tile<float, 8, MS>(uni(d.spec), M, uni(d.pcols), BT, tl.y, d.planM, tw, buf, opaque_tid(), 0,
+                                          uni(d.imask) ? table_flags(uni(d.P), M, uni(d.N), 4) : nullptr,
+                                          uni(d.FS));
     }
 }
 
@@ -219,7 +221,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(WAVES))) vo
         const BItem& d = item_of(items, tl.x);
         __syncthreads();
         solve_tile<float, N, CLS>(uni(d.spec), uni(d.P), uni(d.M), uni(d.Q), uni(d.FS), tl.y, tl.z, Ps,
-                                  opaque_tid());
+                                  opaque_tid(), uni(d.imask) == 0);
     }
 }
 

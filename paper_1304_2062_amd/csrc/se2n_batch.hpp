@@ -24,6 +24,7 @@ struct BItem {
     const float* P;    // propagator table of (M, N, T, beta, n, scheme)
     const C2<float>* tw;  // quarter-wave twiddles of M
     int M, N, K, rows, cols, ocols, pcols, proj, groups, Q, FS;
+    int imask;  // 1: the inverse column pass takes negligible modes as zero, and the solve stores none
     float ocoef, oscale;  // orientation: -2 pi^2 sigma^2 / M^2 and sqrt(M)/M^2
     FftPlan planH, planM;
 };

@@ -680,6 +680,10 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         b.groups = groups_of(x, bp.tune);
         b.Q = M / 4 + 1;
         b.FS = flag_stride(M);
+        {
+            const int side = kBatchSides[batch_class(M)];  // compiled side of the item's column kernels (0: generic)
+            b.imask = side != 0 && col_skip_shape(side, geom_core<float>(side).pcol_threads) ? 1 : 0;
+        }
         b.ocoef = (float)(-2.0 * 9.869604401089358619 * x.sigma * x.sigma / ((double)M * M));
         b.oscale = (float)(std::sqrt((double)M) / ((double)M * M));
         b.planH = make_fft_plan(M / 2, M);

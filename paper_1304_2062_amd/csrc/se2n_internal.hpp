@@ -157,6 +157,14 @@ __host__ __device__ constexpr int table_class_stride(int N, int rsize) {
 // M/4 + 1 bytes padded to 128.
 __host__ __device__ constexpr int flag_stride(int M) { return (M / 4 + 1 + 127) / 128 * 128; }
 
+// Whether a column tile of compiled side MS with NT threads looks up the
+// negligible-class flags cheaply: NT divides MS and divides or is a multiple
+// of MS/2, so the rows a thread handles in one column meet one or two class
+// indices (the class of row ky depends only on ky mod MS/2).
+__host__ __device__ constexpr bool col_skip_shape(int MS, int NT) {
+    return MS != 0 && NT <= MS && MS % NT == 0 && ((MS / 2) % NT == 0 || NT % (MS / 2) == 0);
+}
+
 // The flags of a table at P (the bytes after its propagators).
 __host__ __device__ inline const uint8_t* table_flags(const void* P, int M, int N, int rsize) {
     const size_t Q = (size_t)(M / 4 + 1);
@@ -200,7 +208,7 @@ template <class R>
 hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftPlan& planM,
                              const C2<R>* tw, double sigma, hipStream_t st);
 template <class R>
-hipError_t launch_solve(C2<R>* spec, const R* P, int M, int N, hipStream_t st);
+hipError_t launch_solve(C2<R>* spec, const R* P, int M, int N, hipStream_t st, bool zfill = true);
 // paired: the inverse column pass already applied the pairing step of the
 // real inverse transform (launch_col_inv_paired)
 template <class R>
@@ -210,9 +218,17 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                           bool paired = false);
 // Inverse column FFT of column pairs (kx, M/2-kx) of every slice, followed by
 // the pairing step of the real inverse row transform.
+// negf: the flags of the propagators the solve applied; their modes are then
+// taken as zero and not read (pass it exactly when col_inv_masks holds, and
+// run the solve without zero fill then).
 template <class R>
 hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g, const FftPlan& planM,
-                                 const C2<R>* tw, hipStream_t st);
+                                 const C2<R>* tw, hipStream_t st, const uint8_t* negf = nullptr);
+// Whether the paired inverse column pass for M leaves out negligible modes
+// cheaply (a compiled tile shape whose rows meet one or two class indices
+// per column), so that the solve need not store their zeros.
+template <class R>
+bool col_inv_masks(int M, const LaunchGeom& g);
 template <class R>
 hipError_t launch_fill_enc(typename Enc<R>::U* enc, long n, hipStream_t st);
 template <class R>

@@ -129,7 +129,8 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
 // Paired inverse column pass: one tile of column pairs per workgroup.
 template <class R, int EPT, int MS>
 __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spec, int M_, int pcols_, FftPlan planM,
-                                                         const C2<R>* __restrict__ twg) {
+                                                         const C2<R>* __restrict__ twg,
+                                                         const uint8_t* __restrict__ negf, int FS) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int nthr = MS ? GC.pcol_threads : (int)blockDim.x;
@@ -139,7 +140,8 @@ __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spe
     load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr);
     const int P = (MS ? GC.pcols : pcols_) / 2;
     const int nslices = (int)gridDim.x / ((M / 4 + 1 + P - 1) / P);  // grid: slices x pair blocks
-    col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x, nslices);
+    col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x, nslices,
+                                          negf, FS);
 }
 
 // ---------------------------------------------------------------------------
@@ -455,21 +457,35 @@ hipError_t launch_col_orient(C2<R>* spec, int M, const LaunchGeom& g, const FftP
     return hipGetLastError();
 }
 
+// The compiled size of the paired inverse kernel for M (0: the generic one).
+template <class R>
+static int col_inv_static(int M, const LaunchGeom& g) {
+    const GeomCore c = geom_core<R>(M);
+    const bool fixed = static_size<R>(M, g) != 0 && g.pcols == c.pcols && g.pcol_threads == c.pcol_threads &&
+                       c.pcol_ept == 8;
+    return kStatic<R> && fixed && (M == 2048 || M == 1024 || M == 512) ? M : 0;
+}
+
+template <class R>
+bool col_inv_masks(int M, const LaunchGeom& g) {
+    const int ms = col_inv_static<R>(M, g);
+    return ms != 0 && col_skip_shape(ms, geom_core<R>(ms).pcol_threads);
+}
+
 template <class R>
 hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g, const FftPlan& planM,
-                                 const C2<R>* tw, hipStream_t st) {
+                                 const C2<R>* tw, hipStream_t st, const uint8_t* negf) {
     const int P = g.pcols / 2;
     const int npair = M / 4 + 1;
     const dim3 grid((unsigned)(N * ((npair + P - 1) / P)));
     const size_t lds = tw_bytes<R>(M, false) + (size_t)lds_padded_size(g.pcols * M) * sizeof(C2<R>);
-    const GeomCore c = geom_core<R>(M);
-    const bool fixed = static_size<R>(M, g) != 0 && g.pcols == c.pcols && g.pcol_threads == c.pcol_threads &&
-                       c.pcol_ept == 8;
+    const int ms = col_inv_static<R>(M, g);
 #define SE2N_PCOL(E, MSV) \
-    hipLaunchKernelGGL((k_col_inv_paired<R, E, MSV>), grid, dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw)
-    if (fixed && M == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0);
-    else if (fixed && M == 1024) SE2N_PCOL(8, kStatic<R> ? 1024 : 0);
-    else if (fixed && M == 512) SE2N_PCOL(8, kStatic<R> ? 512 : 0);
+    hipLaunchKernelGGL((k_col_inv_paired<R, E, MSV>), grid, dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw, \
+                       negf, flag_stride(M))
+    if (ms == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0);
+    else if (ms == 1024) SE2N_PCOL(8, kStatic<R> ? 1024 : 0);
+    else if (ms == 512) SE2N_PCOL(8, kStatic<R> ? 512 : 0);
     else if (g.pcol_ept == 8) SE2N_PCOL(8, 0);
     else SE2N_PCOL(16, 0);
 #undef SE2N_PCOL
@@ -572,7 +588,8 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
                                           int, int, R, const LaunchGeom&, int, const FftPlan&,         \
                                           const C2<R>*, hipStream_t, bool);                            \
     template hipError_t launch_col_inv_paired<R>(C2<R>*, int, int, const LaunchGeom&, const FftPlan&,  \
-                                                 const C2<R>*, hipStream_t);                           \
+                                                 const C2<R>*, hipStream_t, const uint8_t*);           \
+    template bool col_inv_masks<R>(int, const LaunchGeom&);                                            \
     template hipError_t launch_fill_enc<R>(typename Enc<R>::U*, long, hipStream_t);                    \
     template hipError_t launch_decode_enc<R>(const typename Enc<R>::U*, R*, long, hipStream_t);        \
     template hipError_t launch_lift<R>(const R*, const uint8_t*, const uint8_t*, R*, int, int,         \

@@ -189,7 +189,7 @@ struct ColSkip {
     static constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     static constexpr int NT = GC.col_threads;
     static constexpr int H = MS / 2;
-    static constexpr bool ok = MS != 0 && NT <= MS && MS % NT == 0 && (H % NT == 0 || NT % H == 0);
+    static constexpr bool ok = col_skip_shape(MS, NT);
     static constexpr int CPT = ok ? MS / NT : 1;           // chunks of nthr rows per column
     static constexpr int U = ok && NT <= H ? H / NT : 1;   // values of ky mod M/2 per column
     static constexpr int EPT = GC.cols * CPT;              // elements a thread stores
@@ -261,6 +261,29 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
     for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
 }
 
+// The paired inverse tile holds the pairs (k, M/2 - k), k = p0 .. p0+P-1:
+// both columns of a pair belong to class row fold(k), and the rows a thread
+// loads meet the same U values of ky mod M/2 as above.
+template <class R, int MS>
+struct ColInvSkip {
+    static constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
+    static constexpr int NT = GC.pcol_threads;
+    static constexpr int H = MS / 2;
+    static constexpr int P = GC.pcols / 2;
+    static constexpr bool ok = col_skip_shape(MS, NT);
+    static constexpr int CPT = ok ? MS / NT : 1;
+    static constexpr int U = ok && NT <= H ? H / NT : 1;
+    static constexpr int EPT = 2 * P * CPT;
+    static_assert(!ok || EPT <= 16, "flags per thread");
+};
+
+// Class index of ky (or kx) for a side M: ky for ky <= M/4, folded back from
+// M/2 and M otherwise.
+__device__ __forceinline__ int fold_class(int k, int M) {
+    const int H = M >> 1, M4 = M >> 2;
+    return k <= M4 ? k : (k <= H ? H - k : (k <= H + M4 ? k - H : M - k));
+}
+
 // ---------------------------------------------------------------------------
 // Inverse column pass on column pairs, then the pairing step of the real
 // inverse row transform.  Tile `tile` of slice r = tile / tiles_per_slice
@@ -271,10 +294,15 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
 // overwrite columns k and H-k (column H is left alone: the row pass reads
 // Z[0 .. H-1] only).  The inverse FFT_H of Z along x is then M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
+//
+// With `negf` set (the flags of the propagators the solve applied), the modes
+// of negligible classes are taken as zero and not read: the solve then need
+// not store them, and lines that hold no live mode are never fetched.
 template <class R, int EPT, int MS, bool HINTS = false>
 __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, int M_, int pcols_, int nthr_,
                                                     int tile, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
-                                                    int tid, int nslices = 0) {
+                                                    int tid, int nslices = 0,
+                                                    const uint8_t* __restrict__ negf = nullptr, int FS = 0) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int pc = MS ? GC.pcols : pcols_;
@@ -320,15 +348,57 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             *p = v;
         }
     };
-    for (int e = tid; e < nel; e += nthr) {
-        if (e < half) {
-            buf[lds_pad(e)] = ld(base + (size_t)p0 * M + e);
-        } else {
-            const int e2 = e - half;
-            const int cm = fdiv(e2, inv_M);           // memory column c2 + cm = H - p0 - q
-            const int y = e2 - cm * M;
-            const int q = np - 1 - cm;
-            buf[lds_pad(half + q * M + y)] = ld(base + (size_t)c2 * M + e2);
+    using CI = ColInvSkip<R, MS>;
+    bool loaded = false;
+    if constexpr (CI::ok) {
+        if (negf != nullptr && np == CI::P) {
+            // U flags per pair of the tile, then element tid + j nthr: column
+            // j / CPT of the first run (pair j / CPT) or of the second (pair
+            // P - 1 - (j - P CPT) / CPT), row ky with ky mod M/2 the
+            // ((j mod CPT) mod U)-th value
+            uint8_t fu[CI::P][CI::U];
+#pragma unroll
+            for (int qq = 0; qq < CI::P; ++qq) {
+                const uint8_t* row = negf + (size_t)fold_class(p0 + qq, M) * FS;
+#pragma unroll
+                for (int v = 0; v < CI::U; ++v) fu[qq][v] = row[fold_class((tid + v * CI::NT) % H, M)];
+            }
+#pragma unroll
+            for (int j = 0; j < CI::EPT; ++j) {
+                constexpr int F = CI::P * CI::CPT;  // elements of the first run per thread
+                const int e = tid + j * CI::NT;
+                C2<R> v = cmk<R>(R(0), R(0));
+                if (j < F) {
+                    if (!fu[j / CI::CPT][(j % CI::CPT) % CI::U]) v = ld(base + (size_t)p0 * M + e);
+                    buf[lds_pad(e)] = v;
+                } else {
+                    const int cm = (j - F) / CI::CPT;  // memory column c2 + cm, pair P - 1 - cm
+                    const int e2 = e - half;
+                    const int y = e2 - cm * M;
+                    if (!fu[CI::P - 1 - cm][(j % CI::CPT) % CI::U]) v = ld(base + (size_t)c2 * M + e2);
+                    buf[lds_pad(half + (CI::P - 1 - cm) * M + y)] = v;
+                }
+            }
+            loaded = true;
+        }
+    }
+    if (!loaded) {
+        for (int e = tid; e < nel; e += nthr) {
+            C2<R> v = cmk<R>(R(0), R(0));
+            if (e < half) {
+                const int q = fdiv(e, inv_M);
+                if (negf == nullptr || !negf[(size_t)fold_class(p0 + q, M) * FS + fold_class(e - q * M, M)])
+                    v = ld(base + (size_t)p0 * M + e);
+                buf[lds_pad(e)] = v;
+            } else {
+                const int e2 = e - half;
+                const int cm = fdiv(e2, inv_M);           // memory column c2 + cm = H - p0 - q
+                const int y = e2 - cm * M;
+                const int q = np - 1 - cm;
+                if (negf == nullptr || !negf[(size_t)fold_class(p0 + q, M) * FS + fold_class(y, M)])
+                    v = ld(base + (size_t)c2 * M + e2);
+                buf[lds_pad(half + q * M + y)] = v;
+            }
         }
     }
     __syncthreads();
@@ -643,9 +713,11 @@ __device__ __forceinline__ double swap_pair(double v) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
+// zfill: store the zeros of negligible classes (off when the inverse column
+// pass takes them as zero without reading them).
 template <class R, int N, int CLS>
 __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q,
-                                           int FS, int lx, int ly0, R* Ps, int tid) {
+                                           int FS, int lx, int ly0, R* Ps, int tid, bool zfill = true) {
     constexpr int h = N / 2;
     constexpr int Eh = h * (h + 1) / 2;
     constexpr int E = 2 * Eh;
@@ -789,7 +861,7 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             const R oy = swap_pair(y[j].y);
             y[j] = odd ? cmk<R>(ox - y[j].x, oy - y[j].y) : cmk<R>(y[j].x + ox, y[j].y + oy);
         }
-        if (live) {  // negligible classes store the zeros they were given
+        if (live && (zfill || read)) {  // negligible classes store the zeros they were given, if asked
 #pragma unroll
             for (int j = 0; j < h; ++j) {
                 const int r0 = j, r1 = j + h;

@@ -470,20 +470,24 @@ int orient_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, uint
 }
 
 // spec holds the forward half spectrum of all slices; propagate it in place.
-// The forward column pass does not store the modes of negligible classes
-// (the solve writes their zeros).  The inverse column pass runs on column
-// pairs and leaves the pairing step of the real inverse row transform done
-// (the row pass is then `paired`).
+// The forward column pass does not store the modes of negligible classes;
+// the solve writes their zeros unless the inverse column pass takes them as
+// zero without reading them.  The inverse column pass runs on column pairs
+// and leaves the pairing step of the real inverse row transform done (the
+// row pass is then `paired`).
 template <class R>
 int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
     const long ncols = (long)p->N * p->K();
-    SE2N_TIMED(p, "col_fft_fwd", st,
-               launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st,
-                                 table_flags(P, p->M, p->N, (int)sizeof(R))),
+    const uint8_t* negf = table_flags(P, p->M, p->N, (int)sizeof(R));
+    // the inverse column pass takes negligible modes as zero where it can do
+    // so cheaply; the solve then does not store their zeros
+    const bool masked = col_inv_masks<R>(p->M, p->geom);
+    SE2N_TIMED(p, "col_fft_fwd", st, launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st, negf),
                "forward column FFT");
-    SE2N_TIMED(p, "solve", st, launch_solve<R>(spec, (const R*)P, p->M, p->N, st), "per-mode solve");
-    SE2N_TIMED(p, "col_fft_inv", st, launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st),
+    SE2N_TIMED(p, "solve", st, launch_solve<R>(spec, (const R*)P, p->M, p->N, st, !masked), "per-mode solve");
+    SE2N_TIMED(p, "col_fft_inv", st,
+               launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st, masked ? negf : nullptr),
                "inverse column FFT");
     return SE2N_OK;
 }

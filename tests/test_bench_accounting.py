@@ -68,3 +68,22 @@ def test_forward_column_bytes_limits(M, N):
     flags = np.zeros((Q, Q), np.uint8)
     flags[0, M // 4] = 1  # columns kx in {0, M/2}, rows ky in {M/4, 3M/4}
     assert bench.col_fwd_bytes(M, N, np.zeros((Q, Q), np.uint8)) - bench.col_fwd_bytes(M, N, flags) == N * 2 * 2 * 8
+
+
+@pytest.mark.parametrize("M,N", [(64, 8), (2048, 32)])
+def test_skipping_solve_and_inverse_bytes(M, N):
+    """With the column passes leaving negligible modes out, the solve writes
+    only live modes (nothing when every class is negligible; the full figure
+    when none is), and the inverse pass reads only live modes."""
+    Q = M // 4 + 1
+    V = N * (M // 2 + 1) * M * 8
+    none, every = np.zeros((Q, Q), np.uint8), np.ones((Q, Q), np.uint8)
+    assert bench.solve_bytes(M, N, none, 4, True) == bench.solve_bytes(M, N, none, 4, False)
+    assert bench.solve_bytes(M, N, every, 4, True) == 0
+    assert bench.col_inv_bytes(M, N, none) == 2 * V
+    assert bench.col_inv_bytes(M, N, every) == V
+    rng = np.random.default_rng(M + N)
+    flags = (rng.random((Q, Q)) < 0.5).astype(np.uint8)
+    # skipping removes exactly the writes of the negligible modes
+    neg_modes = N * (bench.live_modes(M, none) - bench.live_modes(M, flags)) * 8
+    assert bench.solve_bytes(M, N, flags, 4, False) - bench.solve_bytes(M, N, flags, 4, True) == neg_modes

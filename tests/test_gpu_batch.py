@@ -213,9 +213,14 @@ def test_full_heterogeneous_batch_against_single_images(se2n):
 
 def test_poisoned_workspace_leaks_nothing(se2n):
     """Long diffusion times (many negligible classes, whose modes the solve
-    sets to zero without reading them) with the batch workspace filled with
-    NaN bytes: every item still equals the single-image path."""
-    params = [dict(p, T=4.0, n_steps=400) for p in _small_params()]
+    sets to zero without reading them, or, at sides 512 and 1024, neither
+    stores nor the inverse column pass reads) with the batch workspace filled
+    with NaN bytes: every item still equals the single-image path."""
+    large = synth.make_batch(2, seed0=1000, sides=(512, 1024))
+    large = [dict(p, M=m, f=synth.make_image(p["seed"], m, "medium"),
+                  mask=synth.mask_random(p["seed"] + 7919, m, p["rho"]).astype(np.uint8))
+             for p, m in zip(large, (512, 1024))]
+    params = [dict(p, T=4.0, n_steps=400) for p in _small_params() + large]
     items = _items(se2n, params)
     ws = se2n.batch_workspace(items)
     ws.fill_(255)
