@@ -803,6 +803,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         live = live && !(ly == 0 && b >= 2);               // ky in {0, M/2} only
         live = live && !(2 * ly == H && (b & 1));          // ky in {M/4, 3M/4} only
         const bool read = live && !((negm >> c) & 1);      // negligible classes: zeros, nothing read
+        // a wavefront with nothing to read and no zeros to store has no work
+        // (the loop bounds are the same for every lane of a wavefront)
+        if (!zfill && __ballot(read) == 0) continue;
         const int kx = a ? H - lx : lx;
         int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
         if (!live) ky = 0;  // harmless in-range address; nothing is stored
