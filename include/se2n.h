@@ -99,7 +99,10 @@ int se2n_precompute(se2n_plan plan, double T, double beta, int n_steps,
  * scheme): every entry below 2^-30 (FP32 plans) or 2^-60 (FP64 plans).  Their
  * modes are exactly zero at time T to within the rounding of the result
  * (the dropped part of a mode is at most (N/2) 2^-30 of its input), so the
- * diffusion writes zeros there without reading the mode or its propagator.
+ * diffusion takes them as zero: it reads neither the mode nor its propagator,
+ * and for the sides with compiled column kernels (512, 1024, 2048 in FP32)
+ * neither stores nor reloads the mode's spectrum lines when they hold no
+ * live mode.
  * flags [Q][Q] uint8 host buffer, Q = M/4 + 1 (class (lx, ly) at lx*Q + ly):
  * 1 = negligible.  Computes the propagators on `stream` if they are not
  * cached, then waits for the stream.  *Q receives M/4 + 1; flags may be
