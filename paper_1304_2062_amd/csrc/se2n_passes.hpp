@@ -742,6 +742,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         const int l = tid & 63;
         negm = __ballot(l >= ncls || flags[l] != 0);
     }
+    // every class negligible and no zeros to store: nothing to do (negm is
+    // the same in every wavefront, so the whole workgroup returns)
+    if (!zfill && negm == ~0ull) return;
     // Stage the block's propagators, class c at Ps + c * S: 16-byte chunks
     // of the contiguous run, every load of a thread issued before the first
     // is waited on.  Chunks of negligible classes are not read; they and the
