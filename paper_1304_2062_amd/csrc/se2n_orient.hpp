@@ -144,7 +144,9 @@ __device__ __forceinline__ void orient_stencil_tile(const float* __restrict__ f,
 #pragma unroll
     for (int i = 0; i < kOrientCH; ++i) {
         const float t = (atan2f(gy[i], gx[i]) + half_pi) * (float)N / two_pi + 0.5f;
-        int b = (int)floorf(t) % N;
+        // atan2 lies in [-pi, pi], so floor(t) lies in [-N/4, 3N/4]: one
+        // wrap of the negative values is the remainder mod N
+        int b = (int)floorf(t);
         if (b < 0) b += N;
         w[i / 4] |= (uint32_t)b << (8 * (i % 4));
     }

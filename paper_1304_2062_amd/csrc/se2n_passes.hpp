@@ -665,8 +665,9 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
                 const R half_pi = R(1.570796326794896619231);
                 R t0 = (atan2(acc2[i].x, acc[i].x) + half_pi) * (R)N / two_pi + R(0.5);
                 R t1 = (atan2(acc2[i].y, acc[i].y) + half_pi) * (R)N / two_pi + R(0.5);
-                int b0 = (int)floor(t0) % N;
-                int b1 = (int)floor(t1) % N;
+                // floor(t) lies in [-N/4, 3N/4] (atan2 in [-pi, pi]): one wrap
+                int b0 = (int)floor(t0);
+                int b1 = (int)floor(t1);
                 if (b0 < 0) b0 += N;
                 if (b1 < 0) b1 += N;
                 const uint16_t packed = (uint16_t)((unsigned)b0 | ((unsigned)b1 << 8));
