@@ -187,10 +187,13 @@ __host__ __device__ constexpr int solve_lds_stride(int N, int rsize) {
     const int need = solve_q_offset(N) + (N / 2) * (N / 2 + 1) / 2;
     return rsize == 4 ? need + (6 - need % 4) % 4 : (need | 1);
 }
-// Classes per solve workgroup: the largest power of two <= 64 whose staged
-// propagators fit in 72 KB of LDS.
+// Classes per solve workgroup: the largest power of two <= 16 whose staged
+// propagators fit in 72 KB of LDS.  A workgroup stages its propagators, waits
+// at a barrier and then makes few passes over its modes; small workgroups let
+// several of them overlap on a CU (FP32, N = 32, 2048^2: 64 classes 161 us,
+// 32 classes 145 us, 16 classes 141 us, 8 classes 175 us).
 __host__ __device__ constexpr int solve_classes(int N, int rsize) {
-    int c = 64;
+    int c = 16;
     while (c > 1 && (long)solve_lds_stride(N, rsize) * c * rsize > 72 * 1024) c >>= 1;
     return c;
 }
