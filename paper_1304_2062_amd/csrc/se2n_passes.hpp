@@ -701,8 +701,9 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
 // DPP swap gives the even lane p = x_j + x_{j+N/2} and the odd lane
 // q = x_j - x_{j+N/2}; each applies its block (periodic / antiperiodic) and a
 // second swap forms x'_j = y_p + y_q (even) and x'_{j+N/2} = y_p - y_q (odd).
-// A wavefront covers one member for 32 consecutive classes, i.e. 32
-// consecutive (or reversed) ky of one column per orientation plane.
+// A wavefront covers 32 consecutive classes of one member (CLS >= 32), or
+// CLS classes of each of 32/CLS members: runs of consecutive (or reversed)
+// ky of one column per orientation plane.
 __device__ __forceinline__ float swap_pair(float v) {
     // lanes (0,1)(2,3)...: quad_perm [1,0,3,2]
     return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, false));
