@@ -119,6 +119,26 @@ __device__ __forceinline__ void dft(C2<R>* v) {
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> SE2N_LDS_PAD_SHIFT); }
 __host__ __device__ constexpr int lds_padded_size(int n) { return n + (n >> SE2N_LDS_PAD_SHIFT) + 1; }
 
+// A fixed-size stage touches the RADIX positions base + r * STRIDE of each
+// butterfly.  Where the padding of those positions is base's padding plus a
+// constant, one padded base and compile-time offsets replace RADIX separate
+// index computations (each an add, a shift, an add and a byte scaling):
+//  * reads at ib + r NB: exact when NB is a multiple of the padding period P;
+//  * writes at ob + r NS, ob = t BSTRIDE + q NS RADIX + k with k < NS:
+//    exact when NS is a multiple of P, or when NS divides P, NS RADIX
+//    divides or is a multiple of P and BSTRIDE is a multiple of P (the
+//    butterfly's outputs then cross a period boundary only at fixed r).
+// The offset of element r is then r STRIDE + (r STRIDE) / P.
+constexpr int kLdsPadPeriod = 1 << SE2N_LDS_PAD_SHIFT;
+__host__ __device__ constexpr bool pad_linear_read(int NB) { return NB % kLdsPadPeriod == 0; }
+__host__ __device__ constexpr bool pad_linear_write(int NS, int RADIX, int BSTRIDE) {
+    return NS % kLdsPadPeriod == 0 ||
+           (kLdsPadPeriod % NS == 0 &&
+            ((NS * RADIX) % kLdsPadPeriod == 0 || kLdsPadPeriod % (NS * RADIX) == 0) &&
+            BSTRIDE % kLdsPadPeriod == 0);
+}
+__host__ __device__ constexpr int pad_offset(int r, int stride) { return r * stride + (r * stride) / kLdsPadPeriod; }
+
 // Exact quotient n / d for 0 <= n < 2^22 from a float reciprocal (inv = 1/d
 // rounded to float): (n + 1/2) inv lies at least 1/(2d) away from an integer,
 // far more than the float rounding of the product.
@@ -343,8 +363,14 @@ __device__ __forceinline__ void fft_stage_static(C2<R>* buf, const C2<R>* twq, i
             const int q = j / NS;
             const int k = j - q * NS;
             const int ib = t * BSTRIDE + j;
+            if constexpr (pad_linear_read(NB)) {
+                const C2<R>* pa = buf + lds_pad(ib);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * NB)];
+                for (int r = 0; r < RADIX; ++r) v[i][r] = pa[pad_offset(r, NB)];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * NB)];
+            }
             obase[i] = t * BSTRIDE + q * NS * RADIX + k;
             kk[i] = k;
         }
@@ -356,8 +382,14 @@ __device__ __forceinline__ void fft_stage_static(C2<R>* buf, const C2<R>* twq, i
         if (TOTAL % NTHR == 0 || b < TOTAL) {
             if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v[i], twq, kk[i] * TWSTEP, M4);
             dft<R, RADIX, INV>(v[i]);
+            if constexpr (pad_linear_write(NS, RADIX, BSTRIDE)) {
+                C2<R>* pb = buf + lds_pad(obase[i]);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * NS)] = v[i][r];
+                for (int r = 0; r < RADIX; ++r) pb[pad_offset(r, NS)] = v[i][r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) buf[lds_pad(obase[i] + r * NS)] = v[i][r];
+            }
         }
     }
     __syncthreads();
@@ -413,8 +445,14 @@ __device__ __forceinline__ void fft_static_first(C2<R>* buf, int tid, G&& g) {
 #pragma unroll
             for (int r = 0; r < RADIX; ++r) v[r] = g(i * RADIX + r);
             dft<R, RADIX, INV>(v);  // first stage: no twiddles (Ns = 1)
+            if constexpr (pad_linear_write(1, RADIX, BSTRIDE)) {
+                C2<R>* pb = buf + lds_pad(t * BSTRIDE + j * RADIX);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) buf[lds_pad(t * BSTRIDE + j * RADIX + r)] = v[r];
+                for (int r = 0; r < RADIX; ++r) pb[pad_offset(r, 1)] = v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) buf[lds_pad(t * BSTRIDE + j * RADIX + r)] = v[r];
+            }
         }
     }
     __syncthreads();
@@ -473,8 +511,14 @@ __device__ __forceinline__ void fft_stage_static_out(C2<R>* buf, const C2<R>* tw
             const int t = b / NB;
             const int j = b - t * NB;
             const int ib = t * BSTRIDE + j;
+            if constexpr (pad_linear_read(NB)) {
+                const C2<R>* pa = buf + lds_pad(ib);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * NB)];
+                for (int r = 0; r < RADIX; ++r) v[i][r] = pa[pad_offset(r, NB)];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) v[i][r] = buf[lds_pad(ib + r * NB)];
+            }
             tt[i] = t;
             kk[i] = j;  // q = 0 in the last stage: k = j
         }
@@ -515,13 +559,25 @@ __device__ __forceinline__ void fft_stage_pp(const C2<R>* a, C2<R>* b, const C2<
             const int k = j - q * NS;
             const int ib = t * BSTRIDE + j;
             C2<R> v[RADIX];
+            if constexpr (pad_linear_read(NB)) {
+                const C2<R>* pa = a + lds_pad(ib);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
+                for (int r = 0; r < RADIX; ++r) v[r] = pa[pad_offset(r, NB)];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
+            }
             if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, k * TWSTEP, M4);
             dft<R, RADIX, INV>(v);
             const int ob = t * BSTRIDE + q * NS * RADIX + k;
+            if constexpr (pad_linear_write(NS, RADIX, BSTRIDE)) {
+                C2<R>* pb = b + lds_pad(ob);
 #pragma unroll
-            for (int r = 0; r < RADIX; ++r) b[lds_pad(ob + r * NS)] = v[r];
+                for (int r = 0; r < RADIX; ++r) pb[pad_offset(r, NS)] = v[r];
+            } else {
+#pragma unroll
+                for (int r = 0; r < RADIX; ++r) b[lds_pad(ob + r * NS)] = v[r];
+            }
         }
     }
     __syncthreads();
@@ -571,8 +627,14 @@ __device__ __forceinline__ C2<R>* fft_static_out_pp(C2<R>* a, C2<R>* b, const C2
                 const int j = bf - t * NB;  // q = 0 in the last stage: k = j
                 const int ib = t * BSTRIDE + j;
                 C2<R> v[RADIX];
+                if constexpr (pad_linear_read(NB)) {
+                    const C2<R>* pa = a + lds_pad(ib);
 #pragma unroll
-                for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
+                    for (int r = 0; r < RADIX; ++r) v[r] = pa[pad_offset(r, NB)];
+                } else {
+#pragma unroll
+                    for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
+                }
                 if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, j * TWSTEP, M4);
                 dft<R, RADIX, INV>(v);
 #pragma unroll
