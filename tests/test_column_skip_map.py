@@ -72,3 +72,47 @@ def test_inverse_tile_flags(M):
                 # index is the flag the thread loaded for it
                 assert fold(col, M) == fold(p0 + pair, M)
                 assert fold(ky, M) == us[(j % CPT) % U]
+
+
+# LDS padding of the FFT stages: element i lives at i + i // 32.  A stage
+# reads positions ib + r NB and writes ob + r NS (ob = t BSTRIDE + q NS R + k,
+# k < NS); where the predicates below hold, the kernels use the padded base
+# plus r S + (r S) // 32 instead of padding every position.
+P = 32
+
+
+def pad(i):
+    return i + i // P
+
+
+def linear_read(NB):
+    return NB % P == 0
+
+
+def linear_write(NS, R, B):
+    return NS % P == 0 or (P % NS == 0 and ((NS * R) % P == 0 or P % (NS * R) == 0) and B % P == 0)
+
+
+@pytest.mark.parametrize("L", [16, 24, 48, 64, 72, 96, 128, 192, 216, 256, 384, 512, 768, 1024, 2048])
+def test_padded_lds_offsets(L):
+    checked = 0
+    for R in (2, 3, 4, 8):
+        for NS in (1, 2, 3, 4, 6, 8, 9, 12, 16, 24, 27, 32, 48, 64, 72, 96, 128, 256, 512):
+            if L % (NS * R):
+                continue
+            NB = L // R
+            for B in (L, L + 2, 2 * L):
+                for t in (0, 1, 3):
+                    for j in range(0, NB, max(1, NB // 64)):
+                        if linear_read(NB):
+                            ib = t * B + j
+                            for r in range(R):
+                                assert pad(ib + r * NB) == pad(ib) + r * NB + (r * NB) // P
+                                checked += 1
+                        if linear_write(NS, R, B):
+                            q, k = divmod(j, NS)
+                            ob = t * B + q * NS * R + k
+                            for r in range(R):
+                                assert pad(ob + r * NS) == pad(ob) + r * NS + (r * NS) // P
+                                checked += 1
+    assert checked > 0 or L in (24, 72, 216)
