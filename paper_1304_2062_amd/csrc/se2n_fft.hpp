@@ -184,6 +184,21 @@ __device__ __forceinline__ C2<R> tw_get(const C2<R>* tw, int m, int M4) {
     return cmk<R>(-w.y, w.x);
 }
 
+// tw_get for an exponent known to lie below (AMAX + 1) M/4: only the
+// quadrants up to AMAX are tested (AMAX = 0: a plain read).
+template <class R, bool FULL, int AMAX>
+__device__ __forceinline__ C2<R> tw_get_upto(const C2<R>* tw, int m, int M4) {
+    if (FULL || AMAX == 0) return tw[tw_pos(m)];
+    int a = m >= M4;
+    if constexpr (AMAX >= 2) a += m >= 2 * M4;
+    if constexpr (AMAX >= 3) a += m >= 3 * M4;
+    const C2<R> w = tw[tw_pos(m - __mul24(a, M4))];
+    if (a == 0) return w;
+    if (AMAX == 1 || a == 1) return cmk<R>(w.y, -w.x);
+    if (AMAX == 2 || a == 2) return cmk<R>(-w.x, -w.y);
+    return cmk<R>(-w.y, w.x);
+}
+
 // Copy the twiddles into LDS from the quarter table q[r] = w_M^r,
 // r in [0, M/4], in global memory: the full period if `full`, else the
 // quarter table itself (callers synchronise afterwards).
@@ -218,24 +233,29 @@ __host__ __device__ constexpr int tw_elems(int M, bool full) {
 // at an error of a few ulps.
 template <class R, int RADIX, bool INV, bool TWFULL>
 __device__ __forceinline__ void apply_twiddles(C2<R>* v, const C2<R>* twq, int e, int M4) {
-    auto rd = [&](int m) {
-        C2<R> w = tw_get<R, TWFULL>(twq, m, M4);
+    // In a stage of radix RADIX the exponent e = k M / (Ns RADIX), k < Ns,
+    // lies below M / RADIX, which bounds the quadrant of each power read.
+    auto rd = [&](auto amax, int m) {
+        C2<R> w = tw_get_upto<R, TWFULL, decltype(amax)::value>(twq, m, M4);
         if (INV) w.y = -w.y;
         return w;
     };
+    using Q0 = std::integral_constant<int, 0>;
+    using Q1 = std::integral_constant<int, 1>;
+    using Q2 = std::integral_constant<int, 2>;
     if constexpr (RADIX == 2) {
-        v[1] = cmul<R>(v[1], rd(e));
+        v[1] = cmul<R>(v[1], rd(Q1{}, e));  // e < M/2
     } else if constexpr (RADIX == 3) {
-        v[1] = cmul<R>(v[1], rd(e));
-        v[2] = cmul<R>(v[2], rd(2 * e));
+        v[1] = cmul<R>(v[1], rd(Q1{}, e));      // e < M/3
+        v[2] = cmul<R>(v[2], rd(Q2{}, 2 * e));  // 2e < 2M/3
     } else if constexpr (RADIX == 4) {
-        const C2<R> w1 = rd(e), w2 = rd(2 * e);
+        const C2<R> w1 = rd(Q0{}, e), w2 = rd(Q1{}, 2 * e);  // e < M/4, 2e < M/2
         v[1] = cmul<R>(v[1], w1);
         v[2] = cmul<R>(v[2], w2);
         v[3] = cmul<R>(v[3], cmul<R>(w1, w2));
     } else {
         static_assert(RADIX == 8, "radix 2, 3, 4 or 8");
-        const C2<R> w1 = rd(e), w2 = rd(2 * e), w4 = rd(4 * e);
+        const C2<R> w1 = rd(Q0{}, e), w2 = rd(Q0{}, 2 * e), w4 = rd(Q1{}, 4 * e);  // e < M/8
         const C2<R> w3 = cmul<R>(w1, w2);
         v[1] = cmul<R>(v[1], w1);
         v[2] = cmul<R>(v[2], w2);
