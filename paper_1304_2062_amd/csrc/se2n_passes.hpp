@@ -408,6 +408,41 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
     } else {
         fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
     }
+    if constexpr (MS != 0 && GC.pcol_threads <= MS && MS % GC.pcol_threads == 0) {
+        if (np == P) {
+            // full tile of a compiled size: element tid + i nthr lies in pair
+            // i nthr / M, a constant of the unrolled loop, so each thread
+            // reads the two twiddles of each pair once
+            constexpr int NTc = GC.pcol_threads;
+            constexpr int PP = GC.pcols / 2;
+            C2<R> wk[PP], wkk[PP];
+#pragma unroll
+            for (int q = 0; q < PP; ++q) {
+                wk[q] = cconj<R>(tw_get<R, false>(tw, p0 + q, M4));
+                wkk[q] = cconj<R>(tw_get<R, false>(tw, H - p0 - q, M4));
+            }
+#pragma unroll
+            for (int i = 0; i < PP * MS / NTc; ++i) {
+                const int q = i * NTc / MS;
+                const int y = i * NTc - q * MS + tid;
+                const int k = p0 + q;
+                const int kk = H - k;
+                const C2<R> a = buf[lds_pad(q * M + y)];
+                const C2<R> b = buf[lds_pad(half + q * M + y)];
+                const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
+                const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
+                const C2<R> ta = cmul<R>(wk[q], da);
+                st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
+                if (k != 0 && kk != k) {
+                    const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
+                    const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
+                    const C2<R> tb = cmul<R>(wkk[q], db);
+                    st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
+                }
+            }
+            return;
+        }
+    }
     for (int e = tid; e < np * M; e += nthr) {
         const int q = fdiv(e, inv_M);
         const int y = e - q * M;
