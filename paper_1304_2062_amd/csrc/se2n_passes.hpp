@@ -233,7 +233,20 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
             }
         }
     }
-    for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
+    // full tiles of a compiled size: element tid + i nthr sits at
+    // lds_pad(tid) + i (nthr + nthr/32) when nthr is a multiple of the
+    // padding period, so one base and immediate offsets serve every element
+    constexpr bool LINT = MS != 0 && GC.col_threads % kLdsPadPeriod == 0 && (GC.cols * MS) % GC.col_threads == 0;
+    constexpr int LEPT = LINT ? GC.cols * MS / GC.col_threads : 1;
+    constexpr int LSTEP = GC.col_threads + GC.col_threads / kLdsPadPeriod;
+    if (LINT && ncb == cols_per_tile) {
+        C2<R>* lb = buf + lds_pad(tid);
+        const C2<R>* gb = base + tid;
+#pragma unroll
+        for (int i = 0; i < LEPT; ++i) lb[i * LSTEP] = gb[i * GC.col_threads];
+    } else {
+        for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
+    }
     __syncthreads();
     if constexpr (MS != 0) {
         if (ncb == GC.cols) fft_static<R, INV, TWF, MS, GC.cols, MS, GC.col_threads, MS>(buf, tw, tid);
@@ -249,14 +262,23 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
             constexpr int LPL = 128 / (int)sizeof(C2<R>);  // lanes per 128-byte line
             constexpr unsigned long long LMASK = (1ull << LPL) - 1;
             const int lane = tid & 63;
+            static_assert(!CS_::ok || (LINT && CS_::EPT == LEPT), "skip tiles are linear tiles");
+            const C2<R>* lb = buf + lds_pad(tid);
+            C2<R>* gb = base + tid;
 #pragma unroll
             for (int j = 0; j < CS_::EPT; ++j) {
-                const int e = tid + j * GC.col_threads;
                 const unsigned long long live = __ballot(!fb[j]);
-                if ((live >> (lane & ~(LPL - 1))) & LMASK) base[e] = buf[lds_pad(e)];
+                if ((live >> (lane & ~(LPL - 1))) & LMASK) gb[j * GC.col_threads] = lb[j * LSTEP];
             }
             return;
         }
+    }
+    if (LINT && ncb == cols_per_tile) {
+        const C2<R>* lb = buf + lds_pad(tid);
+        C2<R>* gb = base + tid;
+#pragma unroll
+        for (int i = 0; i < LEPT; ++i) gb[i * GC.col_threads] = lb[i * LSTEP];
+        return;
     }
     for (int e = tid; e < nel; e += nthr) base[e] = buf[lds_pad(e)];
 }
@@ -363,20 +385,25 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
 #pragma unroll
                 for (int v = 0; v < CI::U; ++v) fu[qq][v] = row[fold_class((tid + v * CI::NT) % H, M)];
             }
+            // element tid + j nthr: LDS slot lds_pad(tid) plus a compile-time
+            // offset (nthr, M and the run length are multiples of the padding
+            // period), global address run base + tid plus a constant
+            static_assert(CI::NT % kLdsPadPeriod == 0 && MS % kLdsPadPeriod == 0, "linear slots");
+            constexpr int F = CI::P * CI::CPT;  // elements of the first run per thread
+            C2<R>* lb = buf + lds_pad(tid);
+            const C2<R>* g1 = base + (size_t)p0 * M + tid;
+            const C2<R>* g2 = base + (size_t)c2 * M + tid;
 #pragma unroll
             for (int j = 0; j < CI::EPT; ++j) {
-                constexpr int F = CI::P * CI::CPT;  // elements of the first run per thread
-                const int e = tid + j * CI::NT;
                 C2<R> v = cmk<R>(R(0), R(0));
                 if (j < F) {
-                    if (!fu[j / CI::CPT][(j % CI::CPT) % CI::U]) v = ld(base + (size_t)p0 * M + e);
-                    buf[lds_pad(e)] = v;
+                    if (!fu[j / CI::CPT][(j % CI::CPT) % CI::U]) v = ld(g1 + j * CI::NT);
+                    lb[pad_offset(j, CI::NT)] = v;
                 } else {
                     const int cm = (j - F) / CI::CPT;  // memory column c2 + cm, pair P - 1 - cm
-                    const int e2 = e - half;
-                    const int y = e2 - cm * M;
-                    if (!fu[CI::P - 1 - cm][(j % CI::CPT) % CI::U]) v = ld(base + (size_t)c2 * M + e2);
-                    buf[lds_pad(half + (CI::P - 1 - cm) * M + y)] = v;
+                    const int yo = ((j - F) % CI::CPT) * CI::NT;  // row offset within the column
+                    if (!fu[CI::P - 1 - cm][(j % CI::CPT) % CI::U]) v = ld(g2 + (j - F) * CI::NT);
+                    lb[pad_offset(1, CI::P * MS + (CI::P - 1 - cm) * MS + yo)] = v;
                 }
             }
             loaded = true;
@@ -427,8 +454,9 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
                 const int y = i * NTc - q * MS + tid;
                 const int k = p0 + q;
                 const int kk = H - k;
-                const C2<R> a = buf[lds_pad(q * M + y)];
-                const C2<R> b = buf[lds_pad(half + q * M + y)];
+                const C2<R>* lb = buf + lds_pad(tid);  // slot of q M + y is lds_pad(tid) + pad_offset(1, i nthr)
+                const C2<R> a = lb[pad_offset(1, i * NTc)];
+                const C2<R> b = lb[pad_offset(1, PP * MS + i * NTc)];
                 const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
                 const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
                 const C2<R> ta = cmul<R>(wk[q], da);
