@@ -84,12 +84,13 @@ __global__ void k_col_fft(C2<R>* __restrict__ spec, long ncols, int M_, int cols
     extern __shared__ unsigned char smem_raw[];
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
     C2<R>* buf = tw + tw_elems(M, TWF);
-    load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
     // tiles from the last slice to the first: the row pass before this one
     // wrote the high slices last, and the memory-side cache still holds them
     const long tile = (long)gridDim.x - 1 - (long)blockIdx.x;
+    // the tile issues its own loads first and fetches the twiddles meanwhile
     col_fft_tile<R, INV, EPT, TWF, MS>(spec, ncols, M, cols_per_block, nthr, tile * cols_per_block, planM, tw, buf,
-                                      threadIdx.x, negf, FS);
+                                      threadIdx.x, negf, FS,
+                                      [&] { load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr); });
 }
 
 template <class R, int EPT, bool TWF>
@@ -137,11 +138,12 @@ __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spe
     extern __shared__ unsigned char smem_raw[];
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
     C2<R>* buf = tw + tw_elems(M, false);
-    load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr);
     const int P = (MS ? GC.pcols : pcols_) / 2;
     const int nslices = (int)gridDim.x / ((M / 4 + 1 + P - 1) / P);  // grid: slices x pair blocks
+    // the tile fetches the twiddles while its flag loads are in flight
     col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x, nslices,
-                                          negf, FS);
+                                          negf, FS,
+                                          [&] { load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr); });
 }
 
 // ---------------------------------------------------------------------------

@@ -196,11 +196,17 @@ struct ColSkip {
     static_assert(!ok || EPT <= 16, "flags per thread");
 };
 
-template <class R, bool INV, int EPT, bool TWF, int MS>
+// `pre` runs once before the tile's first LDS write, after its own global
+// loads are issued (callers fetch the twiddles there, overlapping the two).
+struct NoPre {
+    __device__ void operator()() const {}
+};
+
+template <class R, bool INV, int EPT, bool TWF, int MS, class Pre = NoPre>
 __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncols, int M_, int cols_,
                                              int nthr_, long c0, const FftPlan& planM, const C2<R>* tw,
                                              C2<R>* buf, int tid, const uint8_t* __restrict__ negf = nullptr,
-                                             int FS = 0) {
+                                             int FS = 0, Pre pre = Pre{}) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int cols_per_tile = MS ? GC.cols : cols_;
@@ -240,11 +246,16 @@ __device__ __forceinline__ void col_fft_tile(C2<R>* __restrict__ spec, long ncol
     constexpr int LEPT = LINT ? GC.cols * MS / GC.col_threads : 1;
     constexpr int LSTEP = GC.col_threads + GC.col_threads / kLdsPadPeriod;
     if (LINT && ncb == cols_per_tile) {
-        C2<R>* lb = buf + lds_pad(tid);
         const C2<R>* gb = base + tid;
+        C2<R> v[LEPT];
 #pragma unroll
-        for (int i = 0; i < LEPT; ++i) lb[i * LSTEP] = gb[i * GC.col_threads];
+        for (int i = 0; i < LEPT; ++i) v[i] = gb[i * GC.col_threads];
+        pre();
+        C2<R>* lb = buf + lds_pad(tid);
+#pragma unroll
+        for (int i = 0; i < LEPT; ++i) lb[i * LSTEP] = v[i];
     } else {
+        pre();
         for (int e = tid; e < nel; e += nthr) buf[lds_pad(e)] = base[e];
     }
     __syncthreads();
@@ -320,11 +331,12 @@ __device__ __forceinline__ int fold_class(int k, int M) {
 // With `negf` set (the flags of the propagators the solve applied), the modes
 // of negligible classes are taken as zero and not read: the solve then need
 // not store them, and lines that hold no live mode are never fetched.
-template <class R, int EPT, int MS, bool HINTS = false>
+template <class R, int EPT, int MS, bool HINTS = false, class Pre = NoPre>
 __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, int M_, int pcols_, int nthr_,
                                                     int tile, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
                                                     int tid, int nslices = 0,
-                                                    const uint8_t* __restrict__ negf = nullptr, int FS = 0) {
+                                                    const uint8_t* __restrict__ negf = nullptr, int FS = 0,
+                                                    Pre pre = Pre{}) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int pc = MS ? GC.pcols : pcols_;
@@ -385,6 +397,7 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
 #pragma unroll
                 for (int v = 0; v < CI::U; ++v) fu[qq][v] = row[fold_class((tid + v * CI::NT) % H, M)];
             }
+            pre();  // overlaps the flag loads, which the data loads below wait for
             // element tid + j nthr: LDS slot lds_pad(tid) plus a compile-time
             // offset (nthr, M and the run length are multiples of the padding
             // period), global address run base + tid plus a constant
@@ -410,6 +423,7 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
         }
     }
     if (!loaded) {
+        pre();
         for (int e = tid; e < nel; e += nthr) {
             C2<R> v = cmk<R>(R(0), R(0));
             if (e < half) {
