@@ -829,7 +829,7 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
     // is waited on.  Chunks of negligible classes are not read; they and the
     // classes past the last one are zeroed (their modes are multiplied by
     // zeros, never by stale LDS).
-    {
+    auto stage = [&]() {
         constexpr int VEC = 16 / (int)sizeof(R);
         typedef R vec_t __attribute__((ext_vector_type(VEC)));
         constexpr int CPC = CS / VEC;  // chunks per class
@@ -863,53 +863,60 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
                 }
             }
         }
-    }
-    __syncthreads();
+    };
     const size_t plane = (size_t)(H + 1) * M;
     const int odd = tid & 1;
     // A wavefront holds 32 pairs; with CLS >= 32 they all belong to one member,
     // so the member, its column kx and its orientation mirroring are uniform
     // across the wavefront and the plane addresses live in scalar registers.
     constexpr bool UNIFORM = CLS >= 32;
-    // every lane of a pair runs the same iterations, so the swaps always meet
-#pragma unroll 1
-    for (int pair = tid >> 1; pair < 8 * CLS; pair += nthr >> 1) {
+    // The mode of lane pair `pair`: its class c, row ky and column, whether it
+    // exists (live), is read, and is mirrored in orientation (perm).
+    struct Mode {
+        int c, ky;
+        bool live, read, perm;
+        C2<R>* colbase;
+    };
+    auto mode_of = [&](int pair) {
+        Mode md;
         int m = pair / CLS;
         if (UNIFORM) m = __builtin_amdgcn_readfirstlane(m);
-        const int c = pair - m * CLS;
-        const int ly = ly0 + c;
+        md.c = pair - m * CLS;
+        const int ly = ly0 + md.c;
         const int a = m >> 2;
         const int b = m & 3;
-        bool live = c < ncls;
+        bool live = md.c < ncls;
         live = live && !(a == 1 && 2 * lx == H);           // kx = M/4 is its own mirror
         live = live && !(ly == 0 && b >= 2);               // ky in {0, M/2} only
         live = live && !(2 * ly == H && (b & 1));          // ky in {M/4, 3M/4} only
-        const bool read = live && !((negm >> c) & 1);      // negligible classes: zeros, nothing read
-        // a wavefront with nothing to read and no zeros to store has no work
-        // (the loop bounds are the same for every lane of a wavefront)
-        if (!zfill && __ballot(read) == 0) continue;
+        md.live = live;
+        md.read = live && !((negm >> md.c) & 1);           // negligible classes: zeros, nothing read
         const int kx = a ? H - lx : lx;
         int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
-        if (!live) ky = 0;  // harmless in-range address; nothing is stored
+        md.ky = live ? ky : 0;  // harmless in-range address; nothing is stored
         // s_ky < 0 exactly for the live members b = 2, 3 (ky in (M/2, M))
-        const bool perm = b >= 2;
-        C2<R>* colbase = spec + (size_t)kx * M;
-        const R* Pc = Ps + c * S + odd * OQ;
-
-        // this lane's half of the orientation vector (lanes of dead or
-        // negligible modes read nothing and hold zeros)
-        C2<R> x[h];
+        md.perm = b >= 2;
+        md.colbase = spec + (size_t)kx * M;
+        return md;
+    };
+    // this lane's half of the orientation vector (lanes of dead or negligible
+    // modes read nothing and hold zeros)
+    auto load_half = [&](const Mode& md, C2<R>* x) {
 #pragma unroll
         for (int j = 0; j < h; ++j) {
             const int r0 = j, r1 = j + h;
-            const int a0 = perm ? (r0 == 0 ? 0 : N - r0) : r0;
-            const int a1 = perm ? N - r1 : r1;
-            const C2<R>* pl0 = colbase + (size_t)a0 * plane;  // wave-uniform
-            const C2<R>* pl1 = colbase + (size_t)a1 * plane;
+            const int a0 = md.perm ? (r0 == 0 ? 0 : N - r0) : r0;
+            const int a1 = md.perm ? N - r1 : r1;
+            const C2<R>* pl0 = md.colbase + (size_t)a0 * plane;  // wave-uniform with UNIFORM
+            const C2<R>* pl1 = md.colbase + (size_t)a1 * plane;
             C2<R> v = cmk<R>(R(0), R(0));
-            if (read) v = odd ? pl1[ky] : pl0[ky];
+            if (md.read) v = odd ? pl1[md.ky] : pl0[md.ky];
             x[j] = v;
         }
+    };
+    // apply the class's blocks to the mode and store it
+    auto apply_store = [&](const Mode& md, C2<R>* x) {
+        const R* Pc = Ps + md.c * S + odd * OQ;
         // even lane: p = x_j + x_{j+h};  odd lane: q = x_j - x_{j+h}
 #pragma unroll
         for (int j = 0; j < h; ++j) {
@@ -946,15 +953,41 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
             const R oy = swap_pair(y[j].y);
             y[j] = odd ? cmk<R>(ox - y[j].x, oy - y[j].y) : cmk<R>(y[j].x + ox, y[j].y + oy);
         }
-        if (live && (zfill || read)) {  // negligible classes store the zeros they were given, if asked
+        if (md.live && (zfill || md.read)) {  // negligible classes store the zeros they were given, if asked
 #pragma unroll
             for (int j = 0; j < h; ++j) {
                 const int r0 = j, r1 = j + h;
-                const int a0 = perm ? (r0 == 0 ? 0 : N - r0) : r0;
-                const int a1 = perm ? N - r1 : r1;
-                C2<R>* pl = colbase + (size_t)(odd ? a1 : a0) * plane;
-                pl[ky] = y[j];
+                const int a0 = md.perm ? (r0 == 0 ? 0 : N - r0) : r0;
+                const int a1 = md.perm ? N - r1 : r1;
+                C2<R>* pl = md.colbase + (size_t)(odd ? a1 : a0) * plane;
+                pl[md.ky] = y[j];
             }
+        }
+    };
+    if constexpr (NT / 2 == 8 * CLS) {
+        // one mode per lane pair: its spectrum loads do not depend on the
+        // table, so they go out before the staging and the two memory round
+        // trips overlap
+        const Mode md = mode_of(tid >> 1);
+        C2<R> x[h];
+        load_half(md, x);
+        stage();
+        __syncthreads();
+        // a wavefront with nothing to read and no zeros to store has no work
+        if (!zfill && __ballot(md.read) == 0) return;
+        apply_store(md, x);
+    } else {
+        stage();
+        __syncthreads();
+        // every lane of a pair runs the same iterations, so the swaps always meet
+#pragma unroll 1
+        for (int pair = tid >> 1; pair < 8 * CLS; pair += nthr >> 1) {
+            const Mode md = mode_of(pair);
+            // (the loop bounds are the same for every lane of a wavefront)
+            if (!zfill && __ballot(md.read) == 0) continue;
+            C2<R> x[h];
+            load_half(md, x);
+            apply_store(md, x);
         }
     }
 }
