@@ -72,10 +72,14 @@ def paired_cols(M):
 
 
 def solve_classes(N):
-    h = N // 2
-    E = h * (h + 1)
-    c = 64
-    while c > 1 and E * c * 4 > 72 * 1024:
+    """Classes per solve tile: the largest power of two <= 16 whose staged
+    propagators fit in 72 KB of LDS, S floats per class (the two packed
+    blocks, the second at an odd offset, S = 2 mod 4)."""
+    eh = (N // 2) * (N // 2 + 1) // 2
+    need = (eh | 1) + eh
+    S = need + (6 - need % 4) % 4
+    c = 16
+    while c > 1 and S * c * 4 > 72 * 1024:
         c //= 2
     return c
 
