@@ -128,7 +128,9 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
 }
 
 // Paired inverse column pass: one tile of column pairs per workgroup.
-template <class R, int EPT, int MS>
+// TWO: each workgroup transforms slices 2s and 2s + 1 of its pair block (grid
+// N/2 x pair blocks), loading the flags and twiddles once for both.
+template <class R, int EPT, int MS, bool TWO = false>
 __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spec, int M_, int pcols_, FftPlan planM,
                                                          const C2<R>* __restrict__ twg,
                                                          const uint8_t* __restrict__ negf, int FS) {
@@ -139,11 +141,18 @@ __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spe
     C2<R>* tw = reinterpret_cast<C2<R>*>(smem_raw);
     C2<R>* buf = tw + tw_elems(M, false);
     const int P = (MS ? GC.pcols : pcols_) / 2;
-    const int nslices = (int)gridDim.x / ((M / 4 + 1 + P - 1) / P);  // grid: slices x pair blocks
+    const int tps = (M / 4 + 1 + P - 1) / P;
+    const int nslices = (TWO ? 2 : 1) * (int)gridDim.x / tps;  // grid: slices (or slice pairs) x pair blocks
+    int tile = blockIdx.x, tile2 = -1;
+    if (TWO) {
+        const int s2 = blockIdx.x / tps;
+        tile = 2 * s2 * tps + (blockIdx.x - s2 * tps);
+        tile2 = tile + tps;
+    }
     // the tile fetches the twiddles while its flag loads are in flight
-    col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, blockIdx.x, planM, tw, buf, threadIdx.x, nslices,
-                                          negf, FS,
-                                          [&] { load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr); });
+    col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, tile, planM, tw, buf, threadIdx.x, nslices, negf,
+                                          FS, [&] { load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr); },
+                                          tile2);
 }
 
 // ---------------------------------------------------------------------------
@@ -479,13 +488,20 @@ hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g,
                                  const C2<R>* tw, hipStream_t st, const uint8_t* negf) {
     const int P = g.pcols / 2;
     const int npair = M / 4 + 1;
-    const dim3 grid((unsigned)(N * ((npair + P - 1) / P)));
     const size_t lds = tw_bytes<R>(M, false) + (size_t)lds_padded_size(g.pcols * M) * sizeof(C2<R>);
     const int ms = col_inv_static<R>(M, g);
+    // two slices per workgroup where every tile takes the flag-reading fast
+    // path (full tiles of a compiled size whose rows meet few class indices)
+    // (compiled for M = 2048, whose tiles are single pairs)
+    const bool two = negf != nullptr && ms == 2048 && col_inv_masks<R>(M, g) && npair % P == 0 && N % 2 == 0;
+    const dim3 grid((unsigned)((two ? N / 2 : N) * ((npair + P - 1) / P)));
 #define SE2N_PCOL(E, MSV) \
     hipLaunchKernelGGL((k_col_inv_paired<R, E, MSV>), grid, dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw, \
                        negf, flag_stride(M))
-    if (ms == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0);
+    if (two && ms == 2048) hipLaunchKernelGGL((k_col_inv_paired<R, 8, kStatic<R> ? 2048 : 0, true>), grid,
+                                             dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw, negf,
+                                             flag_stride(M));
+    else if (ms == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0);
     else if (ms == 1024) SE2N_PCOL(8, kStatic<R> ? 1024 : 0);
     else if (ms == 512) SE2N_PCOL(8, kStatic<R> ? 512 : 0);
     else if (g.pcol_ept == 8) SE2N_PCOL(8, 0);

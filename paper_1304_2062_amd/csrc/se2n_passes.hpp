@@ -331,12 +331,16 @@ __device__ __forceinline__ int fold_class(int k, int M) {
 // With `negf` set (the flags of the propagators the solve applied), the modes
 // of negligible classes are taken as zero and not read: the solve then need
 // not store them, and lines that hold no live mode are never fetched.
+//
+// tile2 >= 0 (full fast-path tiles only, same pair block as `tile`): the
+// workgroup also transforms that tile, reusing the flags and twiddles and
+// holding its input in registers while the first tile is transformed.
 template <class R, int EPT, int MS, bool HINTS = false, class Pre = NoPre>
 __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, int M_, int pcols_, int nthr_,
                                                     int tile, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
                                                     int tid, int nslices = 0,
                                                     const uint8_t* __restrict__ negf = nullptr, int FS = 0,
-                                                    Pre pre = Pre{}) {
+                                                    Pre pre = Pre{}, int tile2 = -1) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int pc = MS ? GC.pcols : pcols_;
@@ -351,6 +355,8 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
     const int p0 = (tile - r * tps) * P;
     const int np = min(P, npair - p0);
     C2<R>* base = spec + (size_t)r * K * M;
+    const int r2 = tile2 >= 0 ? tile2 / tps : r;
+    C2<R>* const base2 = spec + (size_t)r2 * K * M;
     const float inv_M = 1.0f / (float)M;
     const int nel = 2 * np * M;
     // LDS column q < np holds column k = p0 + q, column np + q its partner
@@ -371,7 +377,7 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             return *p;
         }
     };
-    const bool nts = HINTS && 2 * r < nslices;
+    bool nts = HINTS && 2 * r < nslices;
     auto st = [&](C2<R>* p, C2<R> v) {
         if (nts) {
             v2_t w;
@@ -380,6 +386,70 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             __builtin_nontemporal_store(w, reinterpret_cast<v2_t*>(p));
         } else {
             *p = v;
+        }
+    };
+    // transform the tile in LDS and store its pairs (the input is in LDS)
+    auto finish = [&]() {
+        __syncthreads();
+        if constexpr (MS != 0) {
+            if (np == P) fft_static<R, true, false, MS, GC.pcols, MS, GC.pcol_threads, MS>(buf, tw, tid);
+            else fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
+        } else {
+            fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
+        }
+        if constexpr (MS != 0 && GC.pcol_threads <= MS && MS % GC.pcol_threads == 0) {
+            if (np == P) {
+                // full tile of a compiled size: element tid + i nthr lies in pair
+                // i nthr / M, a constant of the unrolled loop, so each thread
+                // reads the two twiddles of each pair once
+                constexpr int NTc = GC.pcol_threads;
+                constexpr int PP = GC.pcols / 2;
+                C2<R> wk[PP], wkk[PP];
+    #pragma unroll
+                for (int q = 0; q < PP; ++q) {
+                    wk[q] = cconj<R>(tw_get<R, false>(tw, p0 + q, M4));
+                    wkk[q] = cconj<R>(tw_get<R, false>(tw, H - p0 - q, M4));
+                }
+    #pragma unroll
+                for (int i = 0; i < PP * MS / NTc; ++i) {
+                    const int q = i * NTc / MS;
+                    const int y = i * NTc - q * MS + tid;
+                    const int k = p0 + q;
+                    const int kk = H - k;
+                    const C2<R>* lb = buf + lds_pad(tid);  // slot of q M + y is lds_pad(tid) + pad_offset(1, i nthr)
+                    const C2<R> a = lb[pad_offset(1, i * NTc)];
+                    const C2<R> b = lb[pad_offset(1, PP * MS + i * NTc)];
+                    const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
+                    const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
+                    const C2<R> ta = cmul<R>(wk[q], da);
+                    st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
+                    if (k != 0 && kk != k) {
+                        const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
+                        const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
+                        const C2<R> tb = cmul<R>(wkk[q], db);
+                        st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
+                    }
+                }
+                return;
+            }
+        }
+        for (int e = tid; e < np * M; e += nthr) {
+            const int q = fdiv(e, inv_M);
+            const int y = e - q * M;
+            const int k = p0 + q;
+            const int kk = H - k;
+            const C2<R> a = buf[lds_pad(q * M + y)];
+            const C2<R> b = buf[lds_pad(half + q * M + y)];
+            const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
+            const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
+            const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, false>(tw, k, M4)), da);
+            st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
+            if (k != 0 && kk != k) {
+                const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
+                const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
+                const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, false>(tw, kk, M4)), db);
+                st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
+            }
         }
     };
     using CI = ColInvSkip<R, MS>;
@@ -404,22 +474,43 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             static_assert(CI::NT % kLdsPadPeriod == 0 && MS % kLdsPadPeriod == 0, "linear slots");
             constexpr int F = CI::P * CI::CPT;  // elements of the first run per thread
             C2<R>* lb = buf + lds_pad(tid);
-            const C2<R>* g1 = base + (size_t)p0 * M + tid;
-            const C2<R>* g2 = base + (size_t)c2 * M + tid;
+            // load the live elements of a tile whose slice starts at bse
+            auto load_tile = [&](const C2<R>* bse, C2<R>* v) {
+                const C2<R>* g1 = bse + (size_t)p0 * M + tid;
+                const C2<R>* g2 = bse + (size_t)c2 * M + tid;
 #pragma unroll
-            for (int j = 0; j < CI::EPT; ++j) {
-                C2<R> v = cmk<R>(R(0), R(0));
-                if (j < F) {
-                    if (!fu[j / CI::CPT][(j % CI::CPT) % CI::U]) v = ld(g1 + j * CI::NT);
-                    lb[pad_offset(j, CI::NT)] = v;
-                } else {
-                    const int cm = (j - F) / CI::CPT;  // memory column c2 + cm, pair P - 1 - cm
-                    const int yo = ((j - F) % CI::CPT) * CI::NT;  // row offset within the column
-                    if (!fu[CI::P - 1 - cm][(j % CI::CPT) % CI::U]) v = ld(g2 + (j - F) * CI::NT);
-                    lb[pad_offset(1, CI::P * MS + (CI::P - 1 - cm) * MS + yo)] = v;
+                for (int j = 0; j < CI::EPT; ++j) {
+                    v[j] = cmk<R>(R(0), R(0));
+                    const int pq = j < F ? j / CI::CPT : CI::P - 1 - (j - F) / CI::CPT;  // pair of element j
+                    if (!fu[pq][(j % CI::CPT) % CI::U]) v[j] = ld(j < F ? g1 + j * CI::NT : g2 + (j - F) * CI::NT);
                 }
-            }
+            };
+            auto to_lds = [&](const C2<R>* v) {
+#pragma unroll
+                for (int j = 0; j < CI::EPT; ++j) {
+                    if (j < F) {
+                        lb[pad_offset(j, CI::NT)] = v[j];
+                    } else {
+                        const int cm = (j - F) / CI::CPT;  // memory column c2 + cm, pair P - 1 - cm
+                        const int yo = ((j - F) % CI::CPT) * CI::NT;  // row offset within the column
+                        lb[pad_offset(1, CI::P * MS + (CI::P - 1 - cm) * MS + yo)] = v[j];
+                    }
+                }
+            };
+            C2<R> v1[CI::EPT], v2[CI::EPT];
+            load_tile(base, v1);
+            if (tile2 >= 0) load_tile(base2, v2);
+            to_lds(v1);
             loaded = true;
+            finish();
+            if (tile2 >= 0) {
+                __syncthreads();  // every thread is done with the first tile's LDS
+                to_lds(v2);
+                base = base2;
+                nts = HINTS && 2 * r2 < nslices;
+                finish();
+            }
+            return;
         }
     }
     if (!loaded) {
@@ -442,67 +533,7 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             }
         }
     }
-    __syncthreads();
-    if constexpr (MS != 0) {
-        if (np == P) fft_static<R, true, false, MS, GC.pcols, MS, GC.pcol_threads, MS>(buf, tw, tid);
-        else fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
-    } else {
-        fft_lds<R, true, EPT, false>(buf, planM, 2 * np, M, tw, M4, tid, nthr);
-    }
-    if constexpr (MS != 0 && GC.pcol_threads <= MS && MS % GC.pcol_threads == 0) {
-        if (np == P) {
-            // full tile of a compiled size: element tid + i nthr lies in pair
-            // i nthr / M, a constant of the unrolled loop, so each thread
-            // reads the two twiddles of each pair once
-            constexpr int NTc = GC.pcol_threads;
-            constexpr int PP = GC.pcols / 2;
-            C2<R> wk[PP], wkk[PP];
-#pragma unroll
-            for (int q = 0; q < PP; ++q) {
-                wk[q] = cconj<R>(tw_get<R, false>(tw, p0 + q, M4));
-                wkk[q] = cconj<R>(tw_get<R, false>(tw, H - p0 - q, M4));
-            }
-#pragma unroll
-            for (int i = 0; i < PP * MS / NTc; ++i) {
-                const int q = i * NTc / MS;
-                const int y = i * NTc - q * MS + tid;
-                const int k = p0 + q;
-                const int kk = H - k;
-                const C2<R>* lb = buf + lds_pad(tid);  // slot of q M + y is lds_pad(tid) + pad_offset(1, i nthr)
-                const C2<R> a = lb[pad_offset(1, i * NTc)];
-                const C2<R> b = lb[pad_offset(1, PP * MS + i * NTc)];
-                const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
-                const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
-                const C2<R> ta = cmul<R>(wk[q], da);
-                st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
-                if (k != 0 && kk != k) {
-                    const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
-                    const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
-                    const C2<R> tb = cmul<R>(wkk[q], db);
-                    st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
-                }
-            }
-            return;
-        }
-    }
-    for (int e = tid; e < np * M; e += nthr) {
-        const int q = fdiv(e, inv_M);
-        const int y = e - q * M;
-        const int k = p0 + q;
-        const int kk = H - k;
-        const C2<R> a = buf[lds_pad(q * M + y)];
-        const C2<R> b = buf[lds_pad(half + q * M + y)];
-        const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
-        const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
-        const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, false>(tw, k, M4)), da);
-        st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
-        if (k != 0 && kk != k) {
-            const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
-            const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
-            const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, false>(tw, kk, M4)), db);
-            st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
-        }
-    }
+    finish();
 }
 
 // ---------------------------------------------------------------------------
