@@ -147,7 +147,7 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
         const int nout = rows * K;
         C2<R>* out = spec + (size_t)s * K * M + y0;
         const int rshift = __ffs(rows) - 1;  // rows is a power of two
-        for (int e = tid; e < nout; e += nthr) {
+        auto unpack = [&](int e) {
             const int kx = e >> rshift;
             const int row = e & (rows - 1);
             const C2<R> z1 = res[lds_pad(row * S + (kx == H ? 0 : kx))];
@@ -157,6 +157,17 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
             const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
             const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
             out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R, TWF>(tw, kx, M4), od));
+        };
+        if constexpr (MS != 0) {
+            // compiled size: a constant count, unrolled so that the LDS reads
+            // of several outputs are in flight together
+            constexpr int NOUT = GC.rows * (MS / 2 + 1);
+            constexpr int FULLIT = NOUT / GC.row_threads;
+#pragma unroll 4
+            for (int it = 0; it < FULLIT; ++it) unpack(tid + it * GC.row_threads);
+            if (tid + FULLIT * GC.row_threads < NOUT) unpack(tid + FULLIT * GC.row_threads);
+        } else {
+            for (int e = tid; e < nout; e += nthr) unpack(e);
         }
         if (pp) {
             // the next first stage fills the buffer nobody reads any more
