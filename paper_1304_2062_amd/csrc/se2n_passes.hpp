@@ -464,7 +464,6 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
         }
     };
     using CI = ColInvSkip<R, MS>;
-    bool loaded = false;
     if constexpr (CI::ok) {
         if (negf != nullptr && np == CI::P) {
             // U flags per pair of the tile, then element tid + j nthr: column
@@ -512,7 +511,6 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             load_tile(base, v1);
             if (tile2 >= 0) load_tile(base2, v2);
             to_lds(v1);
-            loaded = true;
             finish();
             if (tile2 >= 0) {
                 __syncthreads();  // every thread is done with the first tile's LDS
@@ -524,8 +522,8 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             return;
         }
     }
-    if (!loaded) {
-        pre();
+    // generic path: element by element, the flags (if any) looked up per element
+    auto load_generic = [&]() {
         for (int e = tid; e < nel; e += nthr) {
             C2<R> v = cmk<R>(R(0), R(0));
             if (e < half) {
@@ -543,8 +541,17 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
                 buf[lds_pad(half + q * M + y)] = v;
             }
         }
-    }
+    };
+    pre();
+    load_generic();
     finish();
+    if (tile2 >= 0) {  // the same pair block in another slice
+        __syncthreads();
+        base = base2;
+        nts = HINTS && 2 * r2 < nslices;
+        load_generic();
+        finish();
+    }
 }
 
 // ---------------------------------------------------------------------------
