@@ -179,6 +179,31 @@ int se2n_inpaint(se2n_plan plan, const void *f, const uint8_t *mask, double sigm
                  const uint8_t *rmap_in, uint8_t *rmap_out, void *out, void *workspace,
                  void *stream);
 
+/* se2n_inpaint without any allocation, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Same arguments and result as se2n_inpaint, but
+ * instead of a caller workspace the call uses a static device array of
+ * SE2N_NOALLOC_MAX_BYTES bytes inside the library (one per GPU, held until
+ * the process ends).  It calls no hipMalloc, hipFree or other allocating
+ * routine and creates no events (se2n_profile timing does not cover it).
+ * Set-up, done before the first such call for a parameter set:
+ *   - se2n_precompute(plan, T, beta, n_steps, scheme, ...) fills the
+ *     propagator cache (this call never computes propagators);
+ *   - for an FP32 plan without rmap_in, se2n_orient_method(plan, sigma, ...)
+ *     prepares the orientation stencil for sigma (host work).
+ * The plan's device must be current.  Every call on one GPU shares that
+ * GPU's array, and it keeps the last call's contents: calls that overlap in
+ * time on one GPU (other streams, other plans, other threads) race and must
+ * be ordered by the caller.  Nothing in the array needs to start at zero.
+ * Errors: as se2n_inpaint; SE2N_EINVAL if se2n_workspace_bytes(plan) exceeds
+ * SE2N_NOALLOC_MAX_BYTES (e.g. M = 512 fits N <= 60, M = 1024 does not fit
+ * N = 16); SE2N_ESTATE if the propagators or the orientation taps are not
+ * prepared, or another device is current; SE2N_EHIP. */
+#define SE2N_NOALLOC_MAX_BYTES ((size_t)64 << 20)
+int se2n_inpaint_noalloc(se2n_plan plan, const void *f, const uint8_t *mask, double sigma,
+                         double T, double beta, int n_steps, se2n_scheme scheme, se2n_proj mode,
+                         const uint8_t *rmap_in, uint8_t *rmap_out, void *out, void *stream);
+
 /* Kernel timing.  While enabled, every kernel the plan launches is bracketed
  * by two hipEvents recorded on the launch stream; se2n_profile_stats waits
  * for the recorded events and returns, per kernel name, the number of

@@ -232,6 +232,7 @@ struct se2n_plan_s {
     bool alive = true;
     // kernel timing
     bool prof_on = false;
+    bool prof_hold = false;  // set while a call that may not create events runs
     struct ProfRec {
         const char* name;
         hipEvent_t a, b;
@@ -271,7 +272,7 @@ struct ProfScope {
     hipStream_t st;
     hipEvent_t a = nullptr;
     ProfScope(se2n_plan p_, const char* name_, hipStream_t st_) : p(p_), name(name_), st(st_) {
-        if (p->prof_on) {
+        if (p->prof_on && !p->prof_hold) {
             a = prof_event(p);
             if (a) (void)hipEventRecord(a, st);
         }
@@ -411,6 +412,20 @@ int get_propagators(se2n_plan p, double T, double beta, int n_steps, se2n_scheme
     return SE2N_OK;
 }
 
+// The cached propagator table for the given parameters, or NULL (no
+// allocation, no launch).
+const void* find_propagators(se2n_plan p, double T, double beta, int n_steps, se2n_scheme scheme) {
+    CacheKey key{T, beta, scheme == SE2N_CN ? n_steps : 0, (int)scheme};
+    std::lock_guard<std::mutex> lock(p->mu);
+    for (auto it = p->cache.begin(); it != p->cache.end(); ++it) {
+        if (it->key == key) {
+            p->cache.splice(p->cache.begin(), p->cache, it);
+            return p->cache.front().dptr;
+        }
+    }
+    return nullptr;
+}
+
 template <class R>
 struct Ws {
     C2<R>* spec;
@@ -524,9 +539,9 @@ int project_spec(se2n_plan p, const C2<R>* spec, typename Enc<R>::U* enc, se2n_p
 template <class R>
 int inpaint_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, double T, double beta,
                  int n_steps, se2n_scheme scheme, se2n_proj mode, const uint8_t* rmap_in, uint8_t* rmap_out,
-                 R* out, void* workspace, hipStream_t st) {
-    const void* P = nullptr;
-    int rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
+                 R* out, void* workspace, hipStream_t st, const void* P = nullptr) {
+    int rc = SE2N_OK;
+    if (!P) rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
     if (rc) return rc;
     Ws<R> w = split_workspace<R>(p, workspace);
     const uint8_t* rmap = rmap_in;
@@ -577,6 +592,33 @@ int make_twiddles(se2n_plan p) {
     return SE2N_OK;
 }
 
+// Workspace of se2n_inpaint_noalloc: a file-scope device array, so that the
+// call needs no allocation.  Every GPU holds its own copy at its own address
+// until the process ends; in host code `scratch` names only a host-side
+// stand-in, so kernels receive the device address that hipGetSymbolAddress
+// returned for the current device, never the array's name.
+static __device__ __align__(256) unsigned char scratch[SE2N_NOALLOC_MAX_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+hipError_t g_scratch_err[kMaxDevices] = {};
+
+// Look up the scratch array's address on `device` (which must be current).
+// Called once per device at plan creation; later calls return the stored result.
+void scratch_init(int device) {
+    if (device < 0 || device >= kMaxDevices) return;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device] || g_scratch_err[device] != hipSuccess) return;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+        g_scratch_err[device] = e != hipSuccess ? e : hipErrorInvalidSymbol;
+        return;
+    }
+    g_scratch_ptr[device] = ptr;
+}
+
 }  // namespace
 
 extern "C" {
@@ -599,6 +641,7 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     int num_cu = 0;
     if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || num_cu < 1)
         num_cu = 256;
+    scratch_init(p->device);
     p->planH = make_fft_plan(M / 2, M);
     p->planM = make_fft_plan(M, M);
     int rc;
@@ -791,6 +834,54 @@ int se2n_inpaint(se2n_plan p, const void* f, const uint8_t* mask, double sigma, 
                                    rmap_out, (float*)out, workspace, st);
     return inpaint_impl<double>(p, (const double*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in, rmap_out,
                                 (double*)out, workspace, st);
+}
+
+int se2n_inpaint_noalloc(se2n_plan p, const void* f, const uint8_t* mask, double sigma, double T, double beta,
+                         int n_steps, se2n_scheme scheme, se2n_proj mode, const uint8_t* rmap_in, uint8_t* rmap_out,
+                         void* out, void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!f || !mask || !out) return fail(SE2N_EINVAL, "null pointer argument");
+    if (!rmap_in && (!(sigma > 0.0) || !std::isfinite(sigma)))
+        return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
+    if (mode != SE2N_PROJ_MAX && mode != SE2N_PROJ_MEAN) return fail(SE2N_EINVAL, "unknown projection %d", (int)mode);
+    rc = check_diffusion_params(T, beta, n_steps, scheme);
+    if (rc) return rc;
+    if (p->workspace() > (size_t)SE2N_NOALLOC_MAX_BYTES)
+        return fail(SE2N_EINVAL, "M=%d, N=%d needs %zu bytes of workspace, above the %zu-byte static scratch", p->M,
+                    p->N, p->workspace(), (size_t)SE2N_NOALLOC_MAX_BYTES);
+    int dev = -1;
+    SE2N_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev != p->device) return fail(SE2N_ESTATE, "the plan belongs to device %d, device %d is current", p->device, dev);
+    void* ws = nullptr;
+    {
+        std::lock_guard<std::mutex> lock(g_scratch_mu);
+        if (dev < 0 || dev >= kMaxDevices) return fail(SE2N_EUNSUPPORTED, "device index %d out of range", dev);
+        if (g_scratch_err[dev] != hipSuccess) return hip_fail(g_scratch_err[dev], "hipGetSymbolAddress(scratch)");
+        ws = g_scratch_ptr[dev];
+    }
+    if (!ws) return fail(SE2N_ESTATE, "static scratch of device %d not set up", dev);
+    const void* P = find_propagators(p, T, beta, n_steps, scheme);
+    if (!P)
+        return fail(SE2N_ESTATE, "propagators for T=%g, beta=%g, n_steps=%d, scheme=%d are not cached: call "
+                    "se2n_precompute first", T, beta, n_steps, (int)scheme);
+    if (!rmap_in && p->dt == SE2N_F32) {
+        std::lock_guard<std::mutex> lock(p->mu);
+        if (!p->ot_valid || std::memcmp(&p->ot_sigma, &sigma, sizeof sigma) != 0)
+            return fail(SE2N_ESTATE, "orientation taps for sigma=%g are not prepared: call se2n_orient_method first",
+                        sigma);
+    }
+    hipStream_t st = (hipStream_t)stream;
+    p->prof_hold = true;  // timing events would be created on demand
+    if (p->dt == SE2N_F32)
+        rc = inpaint_impl<float>(p, (const float*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in, rmap_out,
+                                 (float*)out, ws, st, P);
+    else
+        rc = inpaint_impl<double>(p, (const double*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in,
+                                  rmap_out, (double*)out, ws, st, P);
+    p->prof_hold = false;
+    return rc;
 }
 
 int se2n_profile(se2n_plan p, int enable) {

@@ -41,6 +41,7 @@ _lib.se2n_lift.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp]
 _lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
 _lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.se2n_inpaint.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]
+_lib.se2n_inpaint_noalloc.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp]
 
 
 class KernelStat(ctypes.Structure):
@@ -54,10 +55,11 @@ _lib.se2n_profile_stats.restype = _i
 _lib.se2n_last_error.restype = ctypes.c_char_p
 _lib.se2n_version.restype = ctypes.c_char_p
 for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_orient_method", "se2n_propagator_flags", "se2n_lift",
-              "se2n_diffuse", "se2n_project", "se2n_inpaint"):
+              "se2n_diffuse", "se2n_project", "se2n_inpaint", "se2n_inpaint_noalloc"):
     getattr(_lib, _name).restype = _i
 
 F32, F64 = 0, 1
+NOALLOC_MAX_BYTES = 64 << 20  # SE2N_NOALLOC_MAX_BYTES
 CN, EXACT = 0, 1
 PROJ_MAX, PROJ_MEAN = 0, 1
 
@@ -195,6 +197,24 @@ class Plan:
                                  _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_in), _ptr(rmap_out), _ptr(out),
                                  _ptr(self.workspace()), _vp(_stream())))
         return out, rmap_out
+
+    def inpaint_noalloc(self, f: torch.Tensor, mask: torch.Tensor, T: float, beta: float, n_steps: int,
+                        out: torch.Tensor, rmap_out: torch.Tensor | None = None, sigma: float = 2.0,
+                        scheme: str = "cn", proj: str = "max", rmap_in: torch.Tensor | None = None):
+        """se2n_inpaint_noalloc: the fused path on the library's static scratch.  The
+        caller passes every output; the propagators (precompute) and, for FP32
+        without rmap_in, the orientation taps (orient_radius) must be prepared."""
+        self._image(f, "f")
+        self._image(mask, "mask", torch.uint8)
+        self._image(out, "out")
+        if rmap_in is not None:
+            self._image(rmap_in, "rmap_in", torch.uint8)
+        if rmap_out is not None:
+            self._image(rmap_out, "rmap_out", torch.uint8)
+        _check(_lib.se2n_inpaint_noalloc(self._h, _ptr(f), _ptr(mask), float(sigma), float(T), float(beta),
+                                         int(n_steps), _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_in),
+                                         _ptr(rmap_out), _ptr(out), _vp(_stream())))
+        return out
 
     def profile(self, enable: bool = True) -> None:
         """Enable/disable per-kernel event timing (clears the statistics)."""

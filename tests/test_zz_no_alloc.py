@@ -1,0 +1,90 @@
+"""se2n_inpaint_noalloc (the fused path on the library's static scratch)
+against se2n_inpaint (the same path on a caller workspace).
+
+Two calls in a row on one GPU, the second with a smaller input, so the second
+call runs on scratch that still holds the first call's larger spectrum.  Both
+entry points launch the same kernels in the same order, so their outputs must
+be identical (exact equality is tighter than the FP32 / FP64 tolerances of the
+parity tests).
+"""
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+
+def _case(M, N, seed, dtype):
+    from paper_1304_2062_amd import synth
+
+    f = synth.make_image(seed, M, "medium")
+    mask = synth.mask_random(seed + 7919, M, 0.7)
+    dev = torch.device("cuda", 0)
+    return (torch.from_numpy(f).to(dev, dtype), torch.from_numpy(mask).to(dev))
+
+
+def _run_pair(M, N, dtype, T, beta, n, proj="max", scheme="cn", use_rmap_in=False, seed=11):
+    from paper_1304_2062_amd import se2n
+
+    f, mask = _case(M, N, seed, dtype)
+    plan = se2n.Plan(M, N, dtype)
+    assert plan.workspace_bytes <= se2n.NOALLOC_MAX_BYTES
+    ref, rmap_ref = plan.inpaint(f, mask, T, beta, n, scheme=scheme, proj=proj)
+    plan.precompute(T, beta, n, scheme)
+    plan.orient_radius(2.0)
+    out = torch.full_like(ref, float("nan"))
+    rmap = torch.full_like(rmap_ref, 255)
+    plan.inpaint_noalloc(f, mask, T, beta, n, out=out, rmap_out=rmap, scheme=scheme, proj=proj,
+                         rmap_in=rmap_ref if use_rmap_in else None)
+    torch.cuda.synchronize()
+    assert torch.equal(rmap, rmap_ref)
+    assert torch.isfinite(out).all()
+    assert torch.equal(out, ref), float((out - ref).abs().max())
+    plan.close()
+    return ref
+
+
+def test_noalloc_matches_workspace_path_twice_second_smaller():
+    print("noalloc: 512^2 N=32 FP32 then 256^2 N=16 FP32", flush=True)
+    a = _run_pair(512, 32, torch.float32, T=2.0, beta=1.0, n=200)
+    b = _run_pair(256, 16, torch.float32, T=1.0, beta=0.5, n=100, proj="mean")
+    assert a.shape == (512, 512) and b.shape == (256, 256)
+
+
+def test_noalloc_fp64_and_given_map():
+    print("noalloc: 192^2 N=24 FP64 exact, then 96^2 N=8 FP64 with rmap_in", flush=True)
+    _run_pair(192, 24, torch.float64, T=0.5, beta=2.0, n=1, scheme="exact")
+    _run_pair(96, 8, torch.float64, T=0.5, beta=1.0, n=50, use_rmap_in=True)
+
+
+def test_noalloc_rejects_unprepared_and_oversized_plans():
+    from paper_1304_2062_amd import se2n
+
+    print("noalloc: error paths", flush=True)
+    f, mask = _case(128, 16, 5, torch.float32)
+    plan = se2n.Plan(128, 16, torch.float32)
+    out = torch.empty((128, 128), dtype=torch.float32, device=f.device)
+    with pytest.raises(se2n.Se2nError) as e:  # propagators not cached
+        plan.inpaint_noalloc(f, mask, 1.0, 1.0, 10, out=out)
+    assert e.value.code == -5
+    plan.precompute(1.0, 1.0, 10)
+    with pytest.raises(se2n.Se2nError) as e:  # orientation taps for sigma not prepared
+        plan.inpaint_noalloc(f, mask, 1.0, 1.0, 10, out=out, sigma=3.0)
+    assert e.value.code == -5
+    plan.orient_radius(3.0)
+    plan.inpaint_noalloc(f, mask, 1.0, 1.0, 10, out=out, sigma=3.0)
+    torch.cuda.synchronize()
+    ref, _ = plan.inpaint(f, mask, 1.0, 1.0, 10, sigma=3.0)
+    torch.cuda.synchronize()
+    assert torch.equal(out, ref)
+    plan.close()
+    big = se2n.Plan(1024, 16, torch.float32)
+    assert big.workspace_bytes > se2n.NOALLOC_MAX_BYTES
+    fb, mb = _case(1024, 16, 6, torch.float32)
+    ob = torch.empty((1024, 1024), dtype=torch.float32, device=fb.device)
+    big.precompute(1.0, 1.0, 10)
+    with pytest.raises(se2n.Se2nError) as e:
+        big.inpaint_noalloc(fb, mb, 1.0, 1.0, 10, out=ob)
+    assert e.value.code == -1
+    big.close()
+    assert np.isfinite(float(ref.sum()))
