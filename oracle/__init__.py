@@ -9,7 +9,8 @@ The oracle is written from the paper (Boscain, Chertovskih, Gauthier, Remizov,
 "Hypoelliptic diffusion and human vision: a semi-discrete new twist") and is
 deliberately plain: full complex FFTs from numpy, an explicit per-mode
 Crank-Nicolson loop in C (``cn_core.c``), and dense eigen-decompositions for the
-exact propagator.
+exact propagator.  ``restore_oracle`` adds the paper's static and dynamic
+restoration heuristics on top of that diffusion.
 """
 from .se2n_oracle import (  # noqa: F401
     orientation_angles,

@@ -30,6 +30,9 @@ __all__ = [
     "BATCH_SIDES",
     "batch_params",
     "make_batch",
+    "TABLE1",
+    "stripe_period",
+    "table1_case",
 ]
 
 
@@ -280,3 +283,54 @@ def make_batch(count: int = 64, seed0: int = 1000, sides=BATCH_SIDES, Ns=(16, 24
         mask = mask_random(p["seed"] + 7919, p["M"], p["rho"]).astype(np.uint8)
         out.append(dict(p, f=img, mask=mask))
     return out
+
+
+# Rows of Appendix A, Table 1 (reconstructions of 256^2 images whose corrupted
+# part is a grid of vertical and horizontal lines of width w): the diffusion
+# weight alpha and time T of the paper's clock, the number n of restoration
+# steps, the mixing weight eps, the line width w in pixels, the corruption in
+# percent, and whether the figure used the dynamic (DR) or the static (SR)
+# procedure (Fig. 2: SR; Fig. 3 and the appendix figures: DR).
+TABLE1 = {
+    "fig2_up": (2.0, 0.8, 200, 0.5, 3, 37, False),
+    "fig2_down": (3.0, 0.2, 200, 0.5, 3, 37, False),
+    "fig3_up": (4.0, 0.2, 200, 0.5, 3, 37, True),
+    "fig3_down": (0.30, 4.0, 160, 0.5, 3, 37, True),
+    "figE1": (0.30, 4.0, 160, 0.5, 3, 67, True),
+    "figE2": (0.30, 4.0, 160, 0.5, 4, 58, True),
+    "figE3": (0.30, 4.0, 160, 0.5, 5, 65, True),
+    "figE4": (0.40, 4.0, 120, 0.5, 5, 69, True),
+    "figE5": (0.35, 5.0, 160, 0.5, 6, 67, True),
+    "figE6": (0.33, 6.0, 180, 0.5, 7, 68, True),
+    "figE7": (0.33, 6.0, 250, 0.5, 8, 43, True),
+    "figE8": (0.33, 6.0, 250, 0.5, 8, 53, True),
+    "figE9": (0.33, 6.0, 250, 0.5, 10, 41, True),
+}
+
+
+def stripe_period(width: int, corruption: float) -> int:
+    """Period p of a w-pixel stripe grid whose corrupted share 1 - (1 - w/p)^2 is
+    closest to ``corruption`` (a fraction)."""
+    return int(round(width / (1.0 - np.sqrt(1.0 - corruption))))
+
+
+def table1_case(name: str, seed: int = 7, M: int = 256, N: int = 30) -> dict:
+    """Input of one Table-1 reconstruction: a seeded image (the medium recipe)
+    mapped to [0.1, 1] -- the restoration heuristics assume f > 0 on the good
+    set -- and the stripe grid of the row's width and corruption (random
+    offset).  The paper's weight alpha and time T_p map to beta = alpha
+    (N / 2 pi)^2 and T = T_p / 2 on the clock of the diffusion here; n is the
+    number of restoration intervals and eps the mixing weight."""
+    alpha, Tp, n, eps, w, pct, dynamic = TABLE1[name]
+    rng = _rng(seed + 31)
+    p = stripe_period(w, pct / 100.0)
+    oy, ox = (int(v) for v in rng.integers(0, p, size=2))
+    idx = np.arange(M)
+    rows = ((idx + oy) % p) < w
+    cols = ((idx + ox) % p) < w
+    mask = (rows[:, None] | cols[None, :]).astype(np.uint8)
+    f = 0.1 + 0.9 * make_image(seed, M, "medium")
+    beta = alpha * (N / (2.0 * np.pi)) ** 2
+    return dict(name=name, seed=seed, M=M, N=N, f=f, mask=mask, alpha=alpha, beta=beta, T=Tp / 2.0,
+                T_paper=Tp, n=n, eps=eps, width=w, period=p, corruption=float(mask.mean()),
+                dynamic=dynamic, sigma=2.0)
