@@ -179,6 +179,40 @@ int se2n_inpaint(se2n_plan plan, const void *f, const uint8_t *mask, double sigm
                  const uint8_t *rmap_in, uint8_t *rmap_out, void *out, void *workspace,
                  void *stream);
 
+/* ------------------------------------------------------------------------
+ * Restoration heuristics (Sec. "Heuristic complements": subsections "Static
+ * restoration (SR)" and "Dynamic restoration (DR)"; Appendix A, Table 1)
+ * ------------------------------------------------------------------------
+ * The pixels split into the good set G (known: mask = 0) and the bad set B.
+ * [0, T] is cut into n_intervals intervals of tau = T / n_intervals with mesh
+ * points t_i = i tau; each interval is integrated by `substeps` Crank-Nicolson
+ * steps of tau / substeps (SE2N_CN) or by e^{tau A} (SE2N_EXACT).  At every
+ * mesh point t_1 .. t_{n-1} the lifted state is mixed with its start on G:
+ *     psi(x, y, theta) *= (eps h_ref + (1 - eps) h) / h,   h = max_theta psi,
+ * at the pixels of G where h > 0 (elsewhere, including where h <= 0, where
+ * the factor is undefined, psi is left unchanged); h_ref = h(x, y, 0) =
+ * max(f, 0).  The state at T is projected without a final mix.
+ * dynamic = 1 (DR): before each mix G grows by the bad pixels that have a
+ * good 8-neighbour and whose h is larger than the mean of h over the bad
+ * pixels of their 3x3 neighbourhood (themselves included; periodic grid;
+ * all decisions of one mesh point taken from the sets before it).  A pixel
+ * that joins at t_i has h_ref = h(x, y, t_i).
+ * The paper's Table 1 gives alpha and T_p in its own clock: use
+ * beta = alpha (N / 2 pi)^2 and T = T_p / 2 here (see the time scale above),
+ * n_intervals = n, eps = epsilon.
+ *   f, mask, sigma, rmap_in, rmap_out, mode, out: as se2n_inpaint.
+ *   join_out optional [M][M] int16: the mesh index at which each pixel
+ *            became good (0: known from the start, -1: never; SR: 0 or -1).
+ *   workspace: se2n_restore_workspace_bytes(plan) bytes.
+ * 0 <= eps <= 1, 1 <= n_intervals <= 32767, substeps >= 1, T >= 0, beta >= 0.
+ * Errors: as se2n_inpaint; SE2N_EINVAL for the ranges above or dynamic not
+ * 0 or 1. */
+size_t se2n_restore_workspace_bytes(se2n_plan plan);
+int se2n_restore(se2n_plan plan, const void *f, const uint8_t *mask, double sigma,
+                 double T, double beta, int n_intervals, int substeps, se2n_scheme scheme,
+                 double eps, int dynamic, se2n_proj mode, const uint8_t *rmap_in,
+                 uint8_t *rmap_out, int16_t *join_out, void *out, void *workspace, void *stream);
+
 /* se2n_inpaint without any allocation, for callers that cannot allocate
  * device memory: code under HIP graph capture, tight serving loops, harnesses
  * that forbid hipMalloc.  Same arguments and result as se2n_inpaint, but

@@ -260,4 +260,14 @@ template <class R>
 hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
                              hipStream_t st);
 
+// Restoration heuristics (se2n_restore.hip): the static mix of a real volume
+// at the known pixels, and the dynamic one (set-up; then per mesh point the
+// orientation maximum, the growth of the good set and the mix).
+template <class R>
+hipError_t launch_sr_mix(R* vol, const R* f, const uint8_t* mask, double eps, int M, int N, hipStream_t st);
+template <class R>
+hipError_t launch_dr_init(int16_t* join, R* href, const R* f, const uint8_t* mask, int M, hipStream_t st);
+template <class R>
+hipError_t launch_dr_step(R* vol, R* h, int16_t* join, R* href, double eps, int step, int M, int N, hipStream_t st);
+
 }  // namespace se2n

@@ -248,6 +248,11 @@ struct se2n_plan_s {
     size_t enc_bytes() const { return align256((size_t)M * M * real_size()); }
     size_t rmap_bytes() const { return align256((size_t)M * M); }
     size_t workspace() const { return spec_bytes() + enc_bytes() + rmap_bytes(); }
+    // restoration: the above, the real volume, h, h_ref and the join map
+    size_t vol_bytes() const { return align256((size_t)N * M * M * real_size()); }
+    size_t restore_workspace() const {
+        return workspace() + vol_bytes() + 2 * enc_bytes() + align256((size_t)M * M * sizeof(int16_t));
+    }
     // class-major propagators + one flag byte per class (padded rows)
     size_t table_bytes() const { return se2n::table_bytes(M, N, (int)real_size()); }
 };
@@ -584,6 +589,71 @@ int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_s
     return SE2N_OK;
 }
 
+// Static / dynamic restoration (Sec. "Heuristic complements"): n intervals
+// of tau = T/n, each integrated by the collapsed propagator of `substeps`
+// Crank-Nicolson steps of tau/substeps (or e^{tau A}).  The state stays in
+// the half spectrum; at mesh points t_1 .. t_{n-1} it is brought to a real
+// volume, mixed on the good set (DR: after growing it), and transformed back.
+template <class R>
+int restore_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, double T, double beta, int n_int,
+                 int substeps, se2n_scheme scheme, double eps, bool dynamic, se2n_proj mode, const uint8_t* rmap_in,
+                 uint8_t* rmap_out, int16_t* join_out, R* out, void* workspace, hipStream_t st) {
+    const double tau = T / n_int;
+    const void* P = nullptr;
+    int rc = get_propagators(p, tau, beta, substeps, scheme, st, &P);
+    if (rc) return rc;
+    Ws<R> w = split_workspace<R>(p, workspace);
+    char* b = (char*)workspace + p->workspace();
+    R* vol = (R*)b;
+    R* h = (R*)(b + p->vol_bytes());
+    R* href = (R*)(b + p->vol_bytes() + p->enc_bytes());
+    int16_t* join = (int16_t*)(b + p->vol_bytes() + 2 * p->enc_bytes());
+    const uint8_t* rmap = rmap_in;
+    if (!rmap_in) {
+        uint8_t* dst = rmap_out ? rmap_out : w.rmap;
+        rc = orient_impl<R>(p, f, mask, sigma, dst, w.spec, st);
+        if (rc) return rc;
+        rmap = dst;
+    } else if (rmap_out && rmap_out != rmap_in) {
+        SE2N_HIP(hipMemcpyAsync(rmap_out, rmap_in, (size_t)p->M * p->M, hipMemcpyDeviceToDevice, st),
+                 "copy of rmap_in to rmap_out");
+    }
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    if (dynamic) SE2N_TIMED(p, "dr_init", st, launch_dr_init<R>(join, href, f, mask, p->M, st), "DR set-up");
+    SE2N_TIMED(p, "lift_row_fwd", st,
+               launch_row_fwd<R>(SRC_LIFT, f, mask, rmap, nullptr, w.spec, p->M, p->N, p->geom, p->planH, tw, st),
+               "lift + row FFT");
+    for (int i = 0; i < n_int; ++i) {
+        if (i > 0) {
+            SE2N_TIMED(p, "row_inv_volume", st,
+                       launch_row_inv<R>(DST_VOLUME, w.spec, vol, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
+                                         p->geom.inv_slices, p->planH, tw, st, true),
+                       "inverse row FFT");
+            if (dynamic)
+                SE2N_TIMED(p, "dr_step", st, launch_dr_step<R>(vol, h, join, href, eps, i, p->M, p->N, st),
+                           "DR growth and mix");
+            else
+                SE2N_TIMED(p, "sr_mix", st, launch_sr_mix<R>(vol, f, mask, eps, p->M, p->N, st), "SR mix");
+            SE2N_TIMED(p, "row_fwd", st,
+                       launch_row_fwd<R>(SRC_VOLUME, nullptr, nullptr, nullptr, vol, w.spec, p->M, p->N, p->geom,
+                                         p->planH, tw, st),
+                       "row FFT");
+        }
+        rc = spectral_middle<R>(p, w.spec, P, st);
+        if (rc) return rc;
+    }
+    rc = project_spec<R>(p, w.spec, w.enc, mode, out, st);
+    if (rc) return rc;
+    if (join_out) {
+        if (dynamic)
+            SE2N_HIP(hipMemcpyAsync(join_out, join, (size_t)p->M * p->M * sizeof(int16_t), hipMemcpyDeviceToDevice, st),
+                     "copy of the join map");
+        else
+            SE2N_TIMED(p, "dr_init", st, launch_dr_init<R>(join_out, href, f, mask, p->M, st), "SR join map");
+    }
+    return SE2N_OK;
+}
+
 template <class R>
 int make_twiddles(se2n_plan p) {
     const std::vector<C2<R>> h = quarter_twiddles<R>(p->M);
@@ -882,6 +952,37 @@ int se2n_inpaint_noalloc(se2n_plan p, const void* f, const uint8_t* mask, double
                                   rmap_out, (double*)out, ws, st, P);
     p->prof_hold = false;
     return rc;
+}
+
+size_t se2n_restore_workspace_bytes(se2n_plan p) {
+    if (!p || !p->alive) return 0;
+    return p->restore_workspace();
+}
+
+int se2n_restore(se2n_plan p, const void* f, const uint8_t* mask, double sigma, double T, double beta,
+                 int n_intervals, int substeps, se2n_scheme scheme, double eps, int dynamic, se2n_proj mode,
+                 const uint8_t* rmap_in, uint8_t* rmap_out, int16_t* join_out, void* out, void* workspace,
+                 void* stream) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!f || !mask || !out || !workspace) return fail(SE2N_EINVAL, "null pointer argument");
+    if (!rmap_in && (!(sigma > 0.0) || !std::isfinite(sigma)))
+        return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
+    if (mode != SE2N_PROJ_MAX && mode != SE2N_PROJ_MEAN) return fail(SE2N_EINVAL, "unknown projection %d", (int)mode);
+    if (n_intervals < 1 || n_intervals > 32767)
+        return fail(SE2N_EINVAL, "n_intervals must lie in [1, 32767] (got %d)", n_intervals);
+    if (substeps < 1) return fail(SE2N_EINVAL, "substeps must be >= 1 (got %d)", substeps);
+    if (!(eps >= 0.0 && eps <= 1.0)) return fail(SE2N_EINVAL, "eps must lie in [0, 1] (got %g)", eps);
+    if (dynamic != 0 && dynamic != 1) return fail(SE2N_EINVAL, "dynamic must be 0 or 1 (got %d)", dynamic);
+    rc = check_diffusion_params(T, beta, substeps, scheme);
+    if (rc) return rc;
+    hipStream_t st = (hipStream_t)stream;
+    if (p->dt == SE2N_F32)
+        return restore_impl<float>(p, (const float*)f, mask, sigma, T, beta, n_intervals, substeps, scheme, eps,
+                                   dynamic != 0, mode, rmap_in, rmap_out, join_out, (float*)out, workspace, st);
+    return restore_impl<double>(p, (const double*)f, mask, sigma, T, beta, n_intervals, substeps, scheme, eps,
+                                dynamic != 0, mode, rmap_in, rmap_out, join_out, (double*)out, workspace, st);
 }
 
 int se2n_profile(se2n_plan p, int enable) {

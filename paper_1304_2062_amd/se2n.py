@@ -42,6 +42,9 @@ _lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
 _lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.se2n_inpaint.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]
 _lib.se2n_inpaint_noalloc.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp]
+_lib.se2n_restore_workspace_bytes.argtypes = [_vp]
+_lib.se2n_restore_workspace_bytes.restype = ctypes.c_size_t
+_lib.se2n_restore.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]
 
 
 class KernelStat(ctypes.Structure):
@@ -55,7 +58,7 @@ _lib.se2n_profile_stats.restype = _i
 _lib.se2n_last_error.restype = ctypes.c_char_p
 _lib.se2n_version.restype = ctypes.c_char_p
 for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_orient_method", "se2n_propagator_flags", "se2n_lift",
-              "se2n_diffuse", "se2n_project", "se2n_inpaint", "se2n_inpaint_noalloc"):
+              "se2n_diffuse", "se2n_project", "se2n_inpaint", "se2n_inpaint_noalloc", "se2n_restore"):
     getattr(_lib, _name).restype = _i
 
 F32, F64 = 0, 1
@@ -215,6 +218,36 @@ class Plan:
                                          int(n_steps), _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_in),
                                          _ptr(rmap_out), _ptr(out), _vp(_stream())))
         return out
+
+    def restore_workspace(self) -> torch.Tensor:
+        n = int(_lib.se2n_restore_workspace_bytes(self._h))
+        if getattr(self, "_rws", None) is None or self._rws.numel() < n:
+            self._rws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        return self._rws
+
+    def restore(self, f: torch.Tensor, mask: torch.Tensor, T: float, beta: float, n_intervals: int, eps: float,
+                dynamic: bool = False, substeps: int = 1, sigma: float = 2.0, scheme: str = "cn",
+                proj: str = "max", rmap_in: torch.Tensor | None = None, out: torch.Tensor | None = None,
+                rmap_out: torch.Tensor | None = None, join_out: torch.Tensor | None = None):
+        """Static (dynamic=False) or dynamic restoration.  Returns (out, rmap, join)."""
+        self._image(f, "f")
+        self._image(mask, "mask", torch.uint8)
+        if rmap_in is not None:
+            self._image(rmap_in, "rmap_in", torch.uint8)
+        if out is None:
+            out = torch.empty((self.M, self.M), dtype=self.dtype, device=self.device)
+        self._image(out, "out")
+        if rmap_out is None:
+            rmap_out = torch.empty((self.M, self.M), dtype=torch.uint8, device=self.device)
+        self._image(rmap_out, "rmap_out", torch.uint8)
+        if join_out is None:
+            join_out = torch.empty((self.M, self.M), dtype=torch.int16, device=self.device)
+        self._image(join_out, "join_out", torch.int16)
+        _check(_lib.se2n_restore(self._h, _ptr(f), _ptr(mask), float(sigma), float(T), float(beta),
+                                 int(n_intervals), int(substeps), _SCHEMES[scheme], float(eps), 1 if dynamic else 0,
+                                 _PROJ[proj], _ptr(rmap_in), _ptr(rmap_out), _ptr(join_out), _ptr(out),
+                                 _ptr(self.restore_workspace()), _vp(_stream())))
+        return out, rmap_out, join_out
 
     def profile(self, enable: bool = True) -> None:
         """Enable/disable per-kernel event timing (clears the statistics)."""
