@@ -135,24 +135,48 @@ def measured_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(case, crop: int) -> dict:
-    """The FP64 oracle on a crop of the same workload, timed on the host cores."""
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(case, crop: int, crop_1t: int = 256) -> dict:
+    """The FP64 oracle on crops of the same workload, timed on the host cores:
+    all OpenMP threads on a crop x crop crop, and one thread on a smaller one.
+    The oracle iterates every Crank-Nicolson step; the GPU applies the
+    collapsed propagator, so n is nominal for the GPU."""
     import oracle as O
     from oracle import se2n_oracle
 
-    f = case["f"][:crop, :crop].astype(np.float32).astype(np.float64)
-    m = case["mask"][:crop, :crop]
-    t0 = time.perf_counter()
-    O.inpaint(f, m, case["N"], case["T"], case["beta"], case["n_steps"], sigma=case["sigma"])
-    dt = time.perf_counter() - t0
-    vs = crop * crop * case["N"] * case["n_steps"]
+    def run(c):
+        f = case["f"][:c, :c].astype(np.float32).astype(np.float64)
+        m = case["mask"][:c, :c]
+        t0 = time.perf_counter()
+        O.inpaint(f, m, case["N"], case["T"], case["beta"], case["n_steps"], sigma=case["sigma"])
+        return time.perf_counter() - t0, c * c * case["N"] * case["n_steps"]
+
+    threads = se2n_oracle.num_threads()
+    dt, vs = run(crop)
+    se2n_oracle.set_num_threads(1)
+    dt1, vs1 = run(crop_1t)
+    se2n_oracle.set_num_threads(threads)
     return {
         "value": vs / dt,
         "unit": "voxel-steps/s",
-        "cores": se2n_oracle.num_threads(),
+        "cores": threads,
         "kind": "oracle",
         "sample": f"FP64 oracle inpaint of the {crop}x{crop} top-left crop of the 2048^2 image, "
                   f"N={case['N']}, T={case['T']}, {case['n_steps']} CN steps ({dt:.1f} s)",
+        "value_1_thread": vs1 / dt1,
+        "sample_1_thread": f"the same on the {crop_1t}x{crop_1t} crop with one thread ({dt1:.1f} s)",
+        "cpu_model": cpu_model(),
+        "nproc": os.cpu_count(),
     }
 
 
@@ -178,6 +202,13 @@ def batch_algorithmic_bytes(params, flags=None) -> dict:
 
 
 def bench_batch(args) -> int:
+    """The heterogeneous batch as its own bench line."""
+    line = run_batch(args)
+    print(json.dumps(line))
+    return 0
+
+
+def run_batch(args, compare_single: bool = True, log: bool = True) -> dict:
     """The heterogeneous batch: 64 images, sides 128..1024, N in {16, 24, 32},
     T ~ U[0.5, 4], tau = 0.01, in one graph launch per batch."""
     import torch
@@ -232,20 +263,22 @@ def bench_batch(args) -> int:
         key = (p["M"], p["N"])
         if key not in plans:
             plans[key] = se2n.Plan(p["M"], p["N"], torch.float32)
-    outs = [torch.empty_like(it.out) for it in items]
-    rms = [torch.empty_like(it.rmap_out) for it in items]
+    ms_single, worst = None, None
+    if compare_single:
+        outs = [torch.empty_like(it.out) for it in items]
+        rms = [torch.empty_like(it.rmap_out) for it in items]
 
-    def one_by_one():
-        for p, it, o, r in zip(params, items, outs, rms):
-            plans[(p["M"], p["N"])].inpaint(it.f, it.mask, p["T"], p["beta"], p["n_steps"], sigma=p["sigma"],
-                                            out=o, rmap_out=r)
+        def one_by_one():
+            for p, it, o, r in zip(params, items, outs, rms):
+                plans[(p["M"], p["N"])].inpaint(it.f, it.mask, p["T"], p["beta"], p["n_steps"], sigma=p["sigma"],
+                                                out=o, rmap_out=r)
 
-    one_by_one()
-    ms_single = timed(one_by_one, max(2, args.steps // 4))
-    torch.cuda.synchronize()
-    worst = max(float(torch.linalg.norm(o - it.out) / torch.linalg.norm(o)) for o, it in zip(outs, items))
-    print(f"[bench] one image at a time {ms_single:.3f} ms per batch; batched/single max rel-L2 {worst:.2e}",
-          file=sys.stderr, flush=True)
+        one_by_one()
+        ms_single = timed(one_by_one, max(2, args.steps // 4))
+        torch.cuda.synchronize()
+        worst = max(float(torch.linalg.norm(o - it.out) / torch.linalg.norm(o)) for o, it in zip(outs, items))
+        print(f"[bench] one image at a time {ms_single:.3f} ms per batch; batched/single max rel-L2 {worst:.2e}",
+              file=sys.stderr, flush=True)
 
     se2n.batch_profile(True)
     for _ in range(args.steps):
@@ -280,10 +313,9 @@ def bench_batch(args) -> int:
         "cold_ms": cold_ms, "tune": tune, "one_by_one_ms": ms_single,
         "batched_vs_single_max_rel_l2": worst, "roofline": roofline, "kernels": kernels, "cpu_baseline": None,
     }
-    print(json.dumps(line))
     for pl in plans.values():
         pl.close()
-    return 0
+    return line
 
 
 def bench_corrector(args) -> int:
@@ -345,6 +377,172 @@ def bench_corrector(args) -> int:
     return 0
 
 
+GOLDEN_C3 = os.path.join(ROOT, "tests", "golden", "c3_oracle_samples.npz")
+
+
+def beta_sweep(plan, f, mask, case, steps: int) -> dict:
+    """For each beta of the 2048^2 configuration: warm ms of the whole path,
+    the share of negligible frequency classes, and the rel-L2 against the FP64
+    oracle's stored outputs at 16384 sampled pixels (tests/golden), with the
+    lift on the oracle's orientation map (the GPU's FP64 map, whose SHA-256
+    must equal the oracle's) -- FP32, and FP64 at beta = 1."""
+    import hashlib
+
+    import torch
+
+    from paper_1304_2062_amd import se2n
+
+    M, N, T, n, sigma = case["M"], case["N"], case["T"], case["n_steps"], case["sigma"]
+    golden = np.load(GOLDEN_C3, allow_pickle=False) if os.path.exists(GOLDEN_C3) else None
+    p64 = se2n.Plan(M, N, torch.float64)
+    rmap64 = p64.orient(f.double(), mask, sigma)
+    sha = hashlib.sha256(rmap64.cpu().numpy().tobytes()).hexdigest()
+    same_map = golden is not None and sha == str(golden["rmap_sha256"])
+    idx = torch.from_numpy(golden["idx"]).cuda() if same_map else None
+    out = torch.empty((M, M), dtype=torch.float32, device="cuda")
+    res = {"oracle_map_identical": same_map}
+
+    def rel_vs_oracle(o, beta):
+        want = torch.from_numpy(golden[f"beta_{beta:g}_samples"]).cuda()
+        got = o.reshape(-1).index_select(0, idx).double()
+        return float(torch.linalg.norm(got - want) / torch.linalg.norm(want))
+
+    for beta in (0.25, 1.0, 4.0):
+        plan.inpaint(f, mask, T, beta, n, sigma=sigma, out=out)  # cold for this beta
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            plan.inpaint(f, mask, T, beta, n, sigma=sigma, out=out)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        e = {"ms": round(ms, 4), "voxel_steps_per_s": M * M * N * n / (ms / 1e3),
+             "negligible_classes": round(float(plan.propagator_flags(T, beta, n).mean()), 4)}
+        if same_map:
+            plan.inpaint(f, mask, T, beta, n, sigma=sigma, rmap_in=rmap64, out=out)
+            e["rel_l2_vs_oracle_fp32"] = rel_vs_oracle(out, beta)
+            if beta == 1.0:
+                o64, _ = p64.inpaint(f.double(), mask, T, beta, n, sigma=sigma, rmap_in=rmap64)
+                e["rel_l2_vs_oracle_fp64"] = rel_vs_oracle(o64, beta)
+        res[f"beta_{beta:g}"] = e
+        print(f"[bench] beta={beta:g}: {ms:.3f} ms, negligible {e['negligible_classes']:.3f}, "
+              f"rel-L2 vs oracle {e.get('rel_l2_vs_oracle_fp32')}", file=sys.stderr, flush=True)
+    p64.close()
+    return res
+
+
+def skip_off(case, f, mask, steps: int, alg_full: dict) -> dict:
+    """The 2048^2 beta = 1 inpaint with no class taken as negligible (every
+    mode read, propagated and stored), per kernel, against the full
+    algorithmic bytes."""
+    import torch
+
+    from paper_1304_2062_amd import se2n
+
+    M, N, T, n, sigma = case["M"], case["N"], case["T"], case["n_steps"], case["sigma"]
+    os.environ["SE2N_KEEP_NEGLIGIBLE"] = "1"
+    try:
+        plan = se2n.Plan(M, N, torch.float32)
+    finally:
+        del os.environ["SE2N_KEEP_NEGLIGIBLE"]
+    out = torch.empty((M, M), dtype=torch.float32, device="cuda")
+    plan.inpaint(f, mask, T, 1.0, n, sigma=sigma, out=out)
+    assert float(plan.propagator_flags(T, 1.0, n).mean()) == 0.0
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.inpaint(f, mask, T, 1.0, n, sigma=sigma, out=out)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / steps * 1e3
+    plan.profile(True)
+    for _ in range(steps):
+        plan.inpaint(f, mask, T, 1.0, n, sigma=sigma, out=out)
+    st = plan.profile_stats()
+    plan.profile(False)
+    plan.close()
+    k = {}
+    for name, (launches, total) in st.items():
+        avg = total / launches
+        e = {"avg_ms": round(avg, 5)}
+        if name in alg_full:
+            gbs = alg_full[name] / (avg / 1e3) / 1e9
+            e.update({"bytes": alg_full[name], "GB_s": round(gbs, 1), "frac_hbm": round(gbs / HBM_PEAK_GBS, 4)})
+        k[name] = e
+    tot = sum(alg_full[name] for name in st if name in alg_full)
+    print(f"[bench] skip off: {ms:.3f} ms, whole path {tot / (ms / 1e3) / 1e9:.0f} GB/s", file=sys.stderr, flush=True)
+    return {"ms": round(ms, 4), "path_bytes": tot, "path_GB_s": round(tot / (ms / 1e3) / 1e9, 1), "kernels": k}
+
+
+def schedules_summary(case, f, mask, steps: int) -> dict:
+    """The two CN schedules on the 2048^2 beta = 1 workload, at the timed 400
+    steps and at 25 steps: the collapsed propagator's cold call (FP64 table
+    built on the stream) and warm calls, against the iterated steps, which
+    need no table."""
+    import torch
+
+    from paper_1304_2062_amd import se2n
+
+    M, N, T, sigma = case["M"], case["N"], case["T"], case["sigma"]
+    out = torch.empty((M, M), dtype=torch.float32, device="cuda")
+    res = {}
+    for n in (400, 25):
+        e = {}
+        for sched in ("propagator", "iterated"):
+            plan = se2n.Plan(M, N, torch.float32)
+            plan.set_schedule(sched)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            plan.inpaint(f, mask, T, 1.0, n, sigma=sigma, out=out)
+            torch.cuda.synchronize()
+            cold = (time.perf_counter() - t0) * 1e3
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                plan.inpaint(f, mask, T, 1.0, n, sigma=sigma, out=out)
+            torch.cuda.synchronize()
+            warm = (time.perf_counter() - t0) / steps * 1e3
+            plan.profile(True)
+            plan.inpaint(f, mask, T, 1.0, n, sigma=sigma, out=out)
+            st = plan.profile_stats()
+            plan.profile(False)
+            plan.close()
+            e[sched] = {"cold_ms": round(cold, 3), "warm_ms": round(warm, 4),
+                        "solve_ms": round(st.get("solve_iter" if sched == "iterated" else "solve", (0, 0.0))[1], 4)}
+        res[f"n_{n}"] = e
+        print(f"[bench] n={n}: propagator cold {e['propagator']['cold_ms']:.2f} / warm "
+              f"{e['propagator']['warm_ms']:.3f} ms; iterated {e['iterated']['warm_ms']:.3f} ms",
+              file=sys.stderr, flush=True)
+    return res
+
+
+def restore_summary(steps: int = 3) -> dict:
+    """Table-1 reconstructions at 256^2, N = 30 on the GPU (FP32): static
+    restoration (Fig. 2, top row) and dynamic restoration (Fig. 3, bottom row)."""
+    import torch
+
+    from paper_1304_2062_amd import se2n, synth
+
+    res = {}
+    for name in ("fig2_up", "fig3_down"):
+        c = synth.table1_case(name)
+        plan = se2n.Plan(c["M"], c["N"], torch.float32)
+        ft = torch.from_numpy(c["f"].astype(np.float32)).cuda()
+        mt = torch.from_numpy(c["mask"]).cuda()
+        run = lambda: plan.restore(ft, mt, c["T"], c["beta"], c["n"], c["eps"], dynamic=c["dynamic"])
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            run()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) / steps * 1e3
+        vs = c["M"] ** 2 * c["N"] * c["n"]
+        res[name] = {"procedure": "DR" if c["dynamic"] else "SR", "M": c["M"], "N": c["N"], "n_intervals": c["n"],
+                     "ms": round(ms, 3), "ms_per_interval": round(ms / c["n"], 4), "voxel_steps_per_s": vs / (ms / 1e3)}
+        print(f"[bench] {name} ({res[name]['procedure']}): {ms:.2f} ms, {ms / c['n'] * 1e3:.1f} us per interval",
+              file=sys.stderr, flush=True)
+        plan.close()
+    return res
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -362,6 +560,8 @@ def main() -> int:
                     help="batch workload: run the autotuner and rewrite the committed schedule table")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="first run one device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="only the headline: no beta sweep, skip-off timing, batch or restoration keys")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path is single-GPU (the multi-GPU split is a design "
@@ -470,6 +670,29 @@ def main() -> int:
         p64.close()
         print(f"[bench] FP32 vs FP64 rel-L2 {rel:.3e}", file=sys.stderr, flush=True)
 
+    # whole path: algorithmic bytes of every timed kernel over the warm time per inpaint
+    path_bytes = sum(alg[k] * kernels[k]["launches"] // args.steps for k in kernels if k in alg)
+    measured = [measured_traffic(k) for k in kernels if k in ROCPROF_NAME]
+    whole_path = {"algorithmic_bytes": path_bytes, "GB_s": round(path_bytes / (ms_per_step / 1e3) / 1e9, 1),
+                  "frac_hbm": round(path_bytes / (ms_per_step / 1e3) / 1e9 / HBM_PEAK_GBS, 4)}
+    if all(m is not None for m in measured) and measured:
+        mb = sum(measured) + alg["orient_stencil"]
+        whole_path.update({"measured_bytes": mb, "measured_GB_s": round(mb / (ms_per_step / 1e3) / 1e9, 1)})
+    print(f"[bench] whole path {whole_path['GB_s']:.0f} GB/s algorithmic", file=sys.stderr, flush=True)
+
+    extras = {}
+    if not args.no_extras:
+        ksteps = max(3, args.steps // 2)
+        extras["beta_sweep"] = beta_sweep(plan, f, mask, case, ksteps)
+        extras["skip_off"] = skip_off(case, f, mask, ksteps, algorithmic_bytes(M, N, 4))
+        extras["cn_schedules"] = schedules_summary(case, f, mask, max(3, args.steps // 4))
+        extras["restore_table1"] = restore_summary()
+        b = run_batch(args, compare_single=False)
+        extras["batch64"] = {"ms": round(b["ms_per_step"], 4), "voxel_steps_per_s": b["value"], "tune": b["tune"],
+                             "cold_ms": round(b["cold_ms"], 2),
+                             "passes": {k: {kk: v[kk] for kk in ("ms_per_batch", "frac_hbm") if kk in v}
+                                        for k, v in b["kernels"].items()}}
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(case, args.cpu_crop)
@@ -495,13 +718,17 @@ def main() -> int:
             "M": M, "N": N, "beta": beta, "T": T, "n_steps": n, "sigma": sigma, "seed": case["seed"],
         },
         "rel_l2_vs_fp64": rel,
+        "note": "n is nominal for the GPU: each mode's Crank-Nicolson steps are collapsed into one FP64-built "
+                "propagator (cached per T, beta, n); cold_ms includes building it.  The oracle iterates all n.",
         "solve_negligible_classes": negligible,
+        "whole_path": whole_path,
         "cold_ms": cold_ms,
         "precompute_ms": cold_stats.get("precompute", (0, None))[1],
         "roofline": roofline,
         "kernels": kernels,
         "cpu_baseline": cpu,
     }
+    line.update(extras)
     plan.close()
     print(json.dumps(line))
     return 0

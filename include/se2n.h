@@ -85,6 +85,28 @@ int se2n_plan_destroy(se2n_plan plan);
  * Returns 0 for a NULL plan. */
 size_t se2n_workspace_bytes(se2n_plan plan);
 
+/* Solver schedule of the Crank-Nicolson diffusion (se2n_diffuse, se2n_inpaint;
+ * SE2N_EXACT always uses the propagator):
+ * SE2N_SCHEDULE_PROPAGATOR  the n steps collapsed into one FP64-built
+ *     propagator per frequency class (cached per (T, beta, n_steps)) and
+ *     applied in one pass over the spectrum: cost independent of n once built.
+ * SE2N_SCHEDULE_ITERATED    the n steps taken one by one on every mode in
+ *     registers (remark 2 after Theorem 2: Crank-Nicolson with a cyclic
+ *     tridiagonal solver, Thomas + Sherman-Morrison; factors in FP64, steps in
+ *     the plan's dtype): no precompute, cost proportional to n.
+ * SE2N_SCHEDULE_AUTO (default)  the cached table if there is one; for a key
+ *     asked for the first time, the iterated steps when they are estimated
+ *     cheaper than building the table; a key asked for again builds it. */
+typedef enum {
+    SE2N_SCHEDULE_AUTO = 0,
+    SE2N_SCHEDULE_PROPAGATOR = 1,
+    SE2N_SCHEDULE_ITERATED = 2
+} se2n_schedule;
+int se2n_set_schedule(se2n_plan plan, se2n_schedule schedule);
+/* The schedule the plan's last diffusion ran (SE2N_SCHEDULE_AUTO before any).
+ * Errors: SE2N_EINVAL (NULL), SE2N_ESTATE. */
+int se2n_last_schedule(se2n_plan plan, se2n_schedule *schedule);
+
 /* Fill the propagator cache for (T, beta, n_steps, scheme) now instead of on
  * the first diffusion (Remark 3 after Theorem 2: the matrices A_{k,l} are
  * universal once M, N and beta are fixed, so their propagators are computed
@@ -222,7 +244,8 @@ int se2n_restore(se2n_plan plan, const void *f, const uint8_t *mask, double sigm
  * routine and creates no events (se2n_profile timing does not cover it).
  * Set-up, done before the first such call for a parameter set:
  *   - se2n_precompute(plan, T, beta, n_steps, scheme, ...) fills the
- *     propagator cache (this call never computes propagators);
+ *     propagator cache (this call never computes propagators), unless the
+ *     plan's schedule is SE2N_SCHEDULE_ITERATED and the scheme SE2N_CN;
  *   - for an FP32 plan without rmap_in, se2n_orient_method(plan, sigma, ...)
  *     prepares the orientation stencil for sigma (host work).
  * The plan's device must be current.  Every call on one GPU shares that
@@ -449,16 +472,36 @@ int se2n_cnn_train_step(se2n_cnn cnn, const float *psi_coarse, const float *psi_
 int se2n_cnn_profile(se2n_cnn cnn, int enable);
 int se2n_cnn_profile_stats(se2n_cnn cnn, se2n_kernel_stat *out, int capacity, int *count);
 
+/* Record the measured accuracy of the network in one regime: applied to the
+ * volume after n_coarse steps (scheme) to time T at side M with weight beta,
+ * its volume rel-L2 against the n_fine-step FP64 solve was rel_l2.  A record
+ * with the same key is replaced.  The records are the network's licence for
+ * se2n_inpaint_corrected (below); se2n_cnn_get_validation returns a record's
+ * rel_l2, or -1 if there is none.  Host only.
+ * Errors: SE2N_EINVAL (sizes, non-finite parameters, rel_l2 < 0, NULL). */
+int se2n_cnn_set_validation(se2n_cnn cnn, int M, double T, double beta, int n_coarse, int n_fine,
+                            se2n_scheme scheme, double rel_l2);
+int se2n_cnn_get_validation(se2n_cnn cnn, int M, double T, double beta, int n_coarse, int n_fine,
+                            se2n_scheme scheme, double *rel_l2);
+
 /* Workspace bytes of se2n_inpaint_corrected (0 if the plan is not FP32, N
  * differs from the network's, or M is not a multiple of 16). */
 size_t se2n_corrected_workspace_bytes(se2n_plan plan, se2n_cnn cnn);
-/* Inpainting with the corrector: orient, lift to a real-space volume
- * (in the workspace), diffuse with n_steps coarse steps, psi += r(psi),
- * project.  rmap_out and out are [M][M] device arrays (uint8, float).
- * Errors: as se2n_inpaint; SE2N_EUNSUPPORTED for FP64 plans. */
+/* Inpainting with the corrector, with the fine-step plain solve as fallback
+ * and judge.  If the network holds a validation record for (M, T, beta,
+ * n_steps, n_fine, scheme) whose rel_l2 is at most max_rel_l2: orient, lift
+ * to a real-space volume (in the workspace), diffuse with n_steps coarse
+ * steps, psi += r(psi), project.  Otherwise the result cannot be shown to
+ * meet the bar and the call runs the plain fused path (se2n_inpaint) with
+ * n_fine steps instead.  *used_fallback (host int, may be NULL) receives 1
+ * when the fallback ran, else 0.  rmap_out and out are [M][M] device arrays
+ * (uint8, float).
+ * Errors: as se2n_inpaint; SE2N_EINVAL if n_fine < n_steps or max_rel_l2 < 0;
+ * SE2N_EUNSUPPORTED for FP64 plans. */
 int se2n_inpaint_corrected(se2n_plan plan, se2n_cnn cnn, const void *f, const uint8_t *mask, double sigma,
-                           double T, double beta, int n_steps, se2n_scheme scheme, se2n_proj mode,
-                           uint8_t *rmap_out, void *out, void *workspace, void *stream);
+                           double T, double beta, int n_steps, int n_fine, se2n_scheme scheme,
+                           se2n_proj mode, double max_rel_l2, uint8_t *rmap_out, void *out,
+                           int *used_fallback, void *workspace, void *stream);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *se2n_last_error(void);

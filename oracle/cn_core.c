@@ -156,3 +156,13 @@ int oracle_num_threads(void)
     return 1;
 #endif
 }
+
+/* Set the number of OpenMP threads of the mode loop (no effect without OpenMP). */
+void oracle_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

@@ -68,6 +68,8 @@ def _core():
         lib.oracle_cyclic_solve.argtypes = [ctypes.c_int, dp, ctypes.c_double, dp, dp]
         lib.oracle_cyclic_solve.restype = ctypes.c_int
         lib.oracle_num_threads.restype = ctypes.c_int
+        lib.oracle_set_num_threads.argtypes = [ctypes.c_int]
+        lib.oracle_set_num_threads.restype = None
         _lib = lib
     return _lib
 
@@ -75,6 +77,11 @@ def _core():
 def num_threads() -> int:
     """Threads the C core uses for its mode loop."""
     return int(_core().oracle_num_threads())
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the C core's mode loop from now on."""
+    _core().oracle_set_num_threads(int(n))
 
 
 def _dptr(a: np.ndarray):

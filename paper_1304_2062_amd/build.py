@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libse2n.so")
 SOURCES = ["se2n_kernels.hip", "se2n_orient.hip", "se2n_solve.hip", "se2n_batch.hip", "se2n_cnn.hip", "se2n_runtime.hip",
-           "se2n_batch_host.hip", "se2n_cnn_host.hip", "se2n_restore.hip"]
+           "se2n_batch_host.hip", "se2n_cnn_host.hip", "se2n_restore.hip", "se2n_solve_iter.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

@@ -30,6 +30,12 @@ struct se2n_cnn_s {
     bf16* wf = nullptr;       // [3][9][32][32]
     bf16* wd = nullptr;
     int t = 0;                // Adam steps taken
+    // measured accuracy of the network per regime (se2n_cnn_set_validation)
+    struct Validation {
+        int M, n_coarse, n_fine, scheme;
+        double T, beta, rel_l2;
+    };
+    std::vector<Validation> validated;
     // kernel timing
     bool prof_on = false;
     struct Rec {
@@ -427,9 +433,43 @@ size_t se2n_corrected_workspace_bytes(se2n_plan plan, se2n_cnn c) {
     return align256(pw) + align256((size_t)N * M * M * sizeof(float)) + se2n_cnn_workspace_bytes(c, M, 1, 0);
 }
 
+int se2n_cnn_set_validation(se2n_cnn c, int M, double T, double beta, int n_coarse, int n_fine, se2n_scheme scheme,
+                            double rel_l2) {
+    clear_error();
+    int rc = check_cnn(c);
+    if (rc) return rc;
+    if (M < 16 || n_coarse < 1 || n_fine < 1 || !(T >= 0.0) || !(beta >= 0.0) || !std::isfinite(T) ||
+        !std::isfinite(beta) || (scheme != SE2N_CN && scheme != SE2N_EXACT) || !(rel_l2 >= 0.0))
+        return fail(SE2N_EINVAL, "bad validation record");
+    for (auto& v : c->validated) {
+        if (v.M == M && v.T == T && v.beta == beta && v.n_coarse == n_coarse && v.n_fine == n_fine &&
+            v.scheme == (int)scheme) {
+            v.rel_l2 = rel_l2;
+            return SE2N_OK;
+        }
+    }
+    c->validated.push_back({M, n_coarse, n_fine, (int)scheme, T, beta, rel_l2});
+    return SE2N_OK;
+}
+
+int se2n_cnn_get_validation(se2n_cnn c, int M, double T, double beta, int n_coarse, int n_fine, se2n_scheme scheme,
+                            double* rel_l2) {
+    clear_error();
+    int rc = check_cnn(c);
+    if (rc) return rc;
+    if (!rel_l2) return fail(SE2N_EINVAL, "rel_l2 is NULL");
+    *rel_l2 = -1.0;
+    for (const auto& v : c->validated)
+        if (v.M == M && v.T == T && v.beta == beta && v.n_coarse == n_coarse && v.n_fine == n_fine &&
+            v.scheme == (int)scheme)
+            *rel_l2 = v.rel_l2;
+    return SE2N_OK;
+}
+
 int se2n_inpaint_corrected(se2n_plan plan, se2n_cnn c, const void* f, const uint8_t* mask, double sigma, double T,
-                           double beta, int n_steps, se2n_scheme scheme, se2n_proj mode, uint8_t* rmap_out, void* out,
-                           void* workspace, void* stream) {
+                           double beta, int n_steps, int n_fine, se2n_scheme scheme, se2n_proj mode,
+                           double max_rel_l2, uint8_t* rmap_out, void* out, int* used_fallback, void* workspace,
+                           void* stream) {
     clear_error();
     int rc = check_cnn(c);
     if (rc) return rc;
@@ -442,7 +482,19 @@ int se2n_inpaint_corrected(se2n_plan plan, se2n_cnn c, const void* f, const uint
     if (M % 16) return fail(SE2N_EUNSUPPORTED, "the corrector needs M divisible by 16 (got %d)", M);
     if (!f || !mask || !rmap_out || !out || !workspace)
         return fail(SE2N_EINVAL, "f, mask, rmap_out, out and workspace must be non-NULL");
+    if (n_fine < 1 || n_fine < n_steps) return fail(SE2N_EINVAL, "n_fine (%d) must be >= n_steps (%d) >= 1", n_fine, n_steps);
+    if (!(max_rel_l2 >= 0.0)) return fail(SE2N_EINVAL, "max_rel_l2 must be >= 0 (got %g)", max_rel_l2);
     char* base = (char*)workspace;
+    // The network is applied only in a regime where its error against the
+    // fine-step solve was measured to be within the bar; everywhere else the
+    // fine-step plain solve runs instead.
+    double measured = -1.0;
+    rc = se2n_cnn_get_validation(c, M, T, beta, n_steps, n_fine, scheme, &measured);
+    if (rc) return rc;
+    const bool trusted = measured >= 0.0 && measured <= max_rel_l2;
+    if (used_fallback) *used_fallback = trusted ? 0 : 1;
+    if (!trusted)
+        return se2n_inpaint(plan, f, mask, sigma, T, beta, n_fine, scheme, mode, nullptr, rmap_out, out, base, stream);
     void* pws = base;
     float* psi = (float*)(base + align256(se2n_workspace_bytes(plan)));
     char* cws = (char*)psi + align256((size_t)N * M * M * sizeof(float));

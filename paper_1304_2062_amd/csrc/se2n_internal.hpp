@@ -256,9 +256,17 @@ struct OrientTaps {
 hipError_t launch_orient_stencil(const float* f, const uint8_t* mask, uint8_t* rmap, int M, int N, int radius,
                                  const OrientTaps& taps, hipStream_t st);
 
+// keep_all: flag no class as negligible (every mode is then read, propagated
+// and stored; used to time the passes without the skip).
 template <class R>
 hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
-                             hipStream_t st);
+                             hipStream_t st, bool keep_all = false);
+
+// Per-mode Crank-Nicolson integrated step by step (se2n_solve_iter.hip):
+// n_steps steps of T / n_steps on every mode of the half spectrum, in place,
+// the inverse transform's 1/M^2 applied at the end.  Even N in [4, 64].
+template <class R>
+hipError_t launch_solve_iter(C2<R>* spec, int M, int N, double beta, double T, int nsteps, hipStream_t st);
 
 // Restoration heuristics (se2n_restore.hip): the static mix of a real volume
 // at the known pixels, and the dynamic one (set-up; then per mesh point the

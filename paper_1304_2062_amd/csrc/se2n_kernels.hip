@@ -220,7 +220,7 @@ __device__ void lds_copy(const double* A, double* B, int n, int tid) {
 template <class R>
 __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q, int FS,
                                                    double beta, double T, int nsteps, int scheme,
-                                                   double scale) {
+                                                   double scale, int keep_all) {
     extern __shared__ double sm[];
     const int h = N / 2;
     const int hh = h * h;
@@ -357,7 +357,7 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     // then writes zeros for the class's modes without reading them
     for (int off = 32; off >= 1; off >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
     uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * Q * CS);
-    if (tid == 0) flags[(size_t)lx * FS + ly] = pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
+    if (tid == 0) flags[(size_t)lx * FS + ly] = !keep_all && pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
     if (ly == Q - 1)  // row padding
         for (int j = ly + 1 + tid; j < FS; j += 64) flags[(size_t)lx * FS + j] = 0;
     // the class's line padding
@@ -583,14 +583,14 @@ hipError_t launch_project(const R* psi, R* out, int M, int N, bool mean, hipStre
 
 template <class R>
 hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
-                             hipStream_t st) {
+                             hipStream_t st, bool keep_all) {
     const int Q = M / 4 + 1;
     const int h = N / 2;
     const size_t lds = (size_t)(6 * h * h + h) * sizeof(double);
     const double scale = 1.0 / (2.0 * (double)M * (double)M);
     hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q,
                        flag_stride(M), beta,
-                       T, nsteps, scheme, scale);
+                       T, nsteps, scheme, scale, keep_all ? 1 : 0);
     return hipGetLastError();
 }
 
@@ -613,7 +613,7 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
     template hipError_t launch_lift<R>(const R*, const uint8_t*, const uint8_t*, R*, int, int,         \
                                        hipStream_t);                                                   \
     template hipError_t launch_project<R>(const R*, R*, int, int, bool, hipStream_t);                  \
-    template hipError_t launch_precompute<R>(R*, int, int, double, double, int, int, hipStream_t);
+    template hipError_t launch_precompute<R>(R*, int, int, double, double, int, int, hipStream_t, bool);
 
 SE2N_INSTANTIATE(float)
 SE2N_INSTANTIATE(double)

@@ -12,6 +12,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <tuple>
 #include <type_traits>
 #include <vector>
 
@@ -233,6 +234,14 @@ struct se2n_plan_s {
     // kernel timing
     bool prof_on = false;
     bool prof_hold = false;  // set while a call that may not create events runs
+    // SE2N_KEEP_NEGLIGIBLE set at plan creation: no class is taken as
+    // negligible (measurement of the passes without the skip)
+    bool keep_negligible = false;
+    // solver schedule of the CN diffusion: collapsed propagator or iterated
+    // steps (se2n_set_schedule); requests per uncached key for the automatic choice
+    se2n_schedule schedule = SE2N_SCHEDULE_AUTO;
+    se2n_schedule last_schedule = SE2N_SCHEDULE_AUTO;
+    std::map<std::tuple<uint64_t, uint64_t, int>, int> misses;
     struct ProfRec {
         const char* name;
         hipEvent_t a, b;
@@ -403,9 +412,10 @@ int get_propagators(se2n_plan p, double T, double beta, int n_steps, se2n_scheme
     {
         ProfScope ps(p, "precompute", st);
         if (p->dt == SE2N_F32)
-            e = launch_precompute<float>((float*)d, p->M, p->N, beta, T, n_steps, (int)scheme, st);
+            e = launch_precompute<float>((float*)d, p->M, p->N, beta, T, n_steps, (int)scheme, st, p->keep_negligible);
         else
-            e = launch_precompute<double>((double*)d, p->M, p->N, beta, T, n_steps, (int)scheme, st);
+            e = launch_precompute<double>((double*)d, p->M, p->N, beta, T, n_steps, (int)scheme, st,
+                                          p->keep_negligible);
     }
     if (e != hipSuccess) {
         (void)hipFree(d);
@@ -429,6 +439,50 @@ const void* find_propagators(se2n_plan p, double T, double beta, int n_steps, se
         }
     }
     return nullptr;
+}
+
+// Estimated milliseconds of the two CN schedules on MI355X, from measured
+// per-unit costs: the iterated kernel per mode and step, the FP64 propagator
+// build per class (it grows with (N/2)^3 and with the binary powering's
+// log2 n products).  Used only to choose a schedule for an uncached key.
+// (FP32, 2048^2, N = 32: 6.66 ms for 400 iterated steps; 10.5 ms to build
+// the 400-step table.)
+double est_iterated_ms(int M, int N, int n) {
+    return 8.0e-9 * (double)(M / 2 + 1) * M * n * (N / 32.0);
+}
+double est_precompute_ms(int M, int N, int n) {
+    const double h = N / 2.0;
+    return 4.0e-5 * (double)(M / 4 + 1) * (M / 4 + 1) * (h * h * h / 4096.0) * (std::log2((double)n) + 3.0) / 11.6;
+}
+
+// Whether this CN diffusion runs the iterated schedule.  AUTO: a cached
+// propagator table is always used; for an uncached key the iterated steps
+// run while they are estimated cheaper than building the table, until the
+// key has been asked for a second time (a table then pays for itself).
+bool use_iterated(se2n_plan p, double T, double beta, int n_steps, se2n_scheme scheme) {
+    if (scheme != SE2N_CN) return false;
+    if (p->schedule == SE2N_SCHEDULE_ITERATED) return true;
+    if (p->schedule == SE2N_SCHEDULE_PROPAGATOR) return false;
+    if (find_propagators(p, T, beta, n_steps, scheme)) return false;
+    uint64_t tb, bb;
+    std::memcpy(&tb, &T, sizeof tb);
+    std::memcpy(&bb, &beta, sizeof bb);
+    std::lock_guard<std::mutex> lock(p->mu);
+    const int seen = p->misses[std::make_tuple(tb, bb, n_steps)]++;
+    return seen == 0 && est_iterated_ms(p->M, p->N, n_steps) < est_precompute_ms(p->M, p->N, n_steps);
+}
+
+template <class R>
+int spectral_middle_iter(se2n_plan p, C2<R>* spec, double T, double beta, int n_steps, hipStream_t st) {
+    const C2<R>* tw = (const C2<R>*)p->tw;
+    const long ncols = (long)p->N * p->K();
+    SE2N_TIMED(p, "col_fft_fwd", st, launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st, nullptr),
+               "forward column FFT");
+    SE2N_TIMED(p, "solve_iter", st, launch_solve_iter<R>(spec, p->M, p->N, beta, T, n_steps, st),
+               "iterated per-mode Crank-Nicolson");
+    SE2N_TIMED(p, "col_fft_inv", st, launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st, nullptr),
+               "inverse column FFT");
+    return SE2N_OK;
 }
 
 template <class R>
@@ -546,8 +600,10 @@ int inpaint_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, dou
                  int n_steps, se2n_scheme scheme, se2n_proj mode, const uint8_t* rmap_in, uint8_t* rmap_out,
                  R* out, void* workspace, hipStream_t st, const void* P = nullptr) {
     int rc = SE2N_OK;
-    if (!P) rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
+    const bool iter = !P && use_iterated(p, T, beta, n_steps, scheme);
+    if (!P && !iter) rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
     if (rc) return rc;
+    p->last_schedule = iter ? SE2N_SCHEDULE_ITERATED : SE2N_SCHEDULE_PROPAGATOR;
     Ws<R> w = split_workspace<R>(p, workspace);
     const uint8_t* rmap = rmap_in;
     if (!rmap_in) {
@@ -563,7 +619,7 @@ int inpaint_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, dou
     SE2N_TIMED(p, "lift_row_fwd", st,
                launch_row_fwd<R>(SRC_LIFT, f, mask, rmap, nullptr, w.spec, p->M, p->N, p->geom, p->planH, tw, st),
                "lift + row FFT");
-    rc = spectral_middle<R>(p, w.spec, P, st);
+    rc = iter ? spectral_middle_iter<R>(p, w.spec, T, beta, n_steps, st) : spectral_middle<R>(p, w.spec, P, st);
     if (rc) return rc;
     return project_spec<R>(p, w.spec, w.enc, mode, out, st);
 }
@@ -572,15 +628,17 @@ template <class R>
 int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_scheme scheme, void* workspace,
                  hipStream_t st) {
     const void* P = nullptr;
-    int rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
+    const bool iter = use_iterated(p, T, beta, n_steps, scheme);
+    int rc = iter ? SE2N_OK : get_propagators(p, T, beta, n_steps, scheme, st, &P);
     if (rc) return rc;
+    p->last_schedule = iter ? SE2N_SCHEDULE_ITERATED : SE2N_SCHEDULE_PROPAGATOR;
     Ws<R> w = split_workspace<R>(p, workspace);
     const C2<R>* tw = (const C2<R>*)p->tw;
     SE2N_TIMED(p, "row_fwd", st,
                launch_row_fwd<R>(SRC_VOLUME, nullptr, nullptr, nullptr, psi, w.spec, p->M, p->N, p->geom,
                                  p->planH, tw, st),
                "row FFT");
-    rc = spectral_middle<R>(p, w.spec, P, st);
+    rc = iter ? spectral_middle_iter<R>(p, w.spec, T, beta, n_steps, st) : spectral_middle<R>(p, w.spec, P, st);
     if (rc) return rc;
     SE2N_TIMED(p, "row_inv_volume", st,
                launch_row_inv<R>(DST_VOLUME, w.spec, psi, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
@@ -712,6 +770,7 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     if (hipDeviceGetAttribute(&num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess || num_cu < 1)
         num_cu = 256;
     scratch_init(p->device);
+    p->keep_negligible = std::getenv("SE2N_KEEP_NEGLIGIBLE") != nullptr;
     p->planH = make_fft_plan(M / 2, M);
     p->planM = make_fft_plan(M, M);
     int rc;
@@ -932,10 +991,11 @@ int se2n_inpaint_noalloc(se2n_plan p, const void* f, const uint8_t* mask, double
         ws = g_scratch_ptr[dev];
     }
     if (!ws) return fail(SE2N_ESTATE, "static scratch of device %d not set up", dev);
-    const void* P = find_propagators(p, T, beta, n_steps, scheme);
-    if (!P)
+    const bool iter = scheme == SE2N_CN && p->schedule == SE2N_SCHEDULE_ITERATED;
+    const void* P = iter ? nullptr : find_propagators(p, T, beta, n_steps, scheme);
+    if (!P && !iter)
         return fail(SE2N_ESTATE, "propagators for T=%g, beta=%g, n_steps=%d, scheme=%d are not cached: call "
-                    "se2n_precompute first", T, beta, n_steps, (int)scheme);
+                    "se2n_precompute first (or set the iterated schedule)", T, beta, n_steps, (int)scheme);
     if (!rmap_in && p->dt == SE2N_F32) {
         std::lock_guard<std::mutex> lock(p->mu);
         if (!p->ot_valid || std::memcmp(&p->ot_sigma, &sigma, sizeof sigma) != 0)
@@ -983,6 +1043,25 @@ int se2n_restore(se2n_plan p, const void* f, const uint8_t* mask, double sigma, 
                                    dynamic != 0, mode, rmap_in, rmap_out, join_out, (float*)out, workspace, st);
     return restore_impl<double>(p, (const double*)f, mask, sigma, T, beta, n_intervals, substeps, scheme, eps,
                                 dynamic != 0, mode, rmap_in, rmap_out, join_out, (double*)out, workspace, st);
+}
+
+int se2n_set_schedule(se2n_plan p, se2n_schedule schedule) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (schedule != SE2N_SCHEDULE_AUTO && schedule != SE2N_SCHEDULE_PROPAGATOR && schedule != SE2N_SCHEDULE_ITERATED)
+        return fail(SE2N_EINVAL, "unknown schedule %d", (int)schedule);
+    p->schedule = schedule;
+    return SE2N_OK;
+}
+
+int se2n_last_schedule(se2n_plan p, se2n_schedule* schedule) {
+    g_last_error.clear();
+    int rc = check_plan(p);
+    if (rc) return rc;
+    if (!schedule) return fail(SE2N_EINVAL, "schedule is NULL");
+    *schedule = p->last_schedule;
+    return SE2N_OK;
 }
 
 int se2n_profile(se2n_plan p, int enable) {

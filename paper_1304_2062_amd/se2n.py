@@ -42,6 +42,8 @@ _lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
 _lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.se2n_inpaint.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]
 _lib.se2n_inpaint_noalloc.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp]
+_lib.se2n_set_schedule.argtypes = [_vp, _i]
+_lib.se2n_last_schedule.argtypes = [_vp, ctypes.POINTER(_i)]
 _lib.se2n_restore_workspace_bytes.argtypes = [_vp]
 _lib.se2n_restore_workspace_bytes.restype = ctypes.c_size_t
 _lib.se2n_restore.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _d, _i, _i, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -58,7 +60,8 @@ _lib.se2n_profile_stats.restype = _i
 _lib.se2n_last_error.restype = ctypes.c_char_p
 _lib.se2n_version.restype = ctypes.c_char_p
 for _name in ("se2n_plan_create", "se2n_plan_destroy", "se2n_precompute", "se2n_orient", "se2n_orient_method", "se2n_propagator_flags", "se2n_lift",
-              "se2n_diffuse", "se2n_project", "se2n_inpaint", "se2n_inpaint_noalloc", "se2n_restore"):
+              "se2n_diffuse", "se2n_project", "se2n_inpaint", "se2n_inpaint_noalloc", "se2n_restore",
+              "se2n_set_schedule", "se2n_last_schedule"):
     getattr(_lib, _name).restype = _i
 
 F32, F64 = 0, 1
@@ -67,6 +70,7 @@ CN, EXACT = 0, 1
 PROJ_MAX, PROJ_MEAN = 0, 1
 
 _SCHEMES = {"cn": CN, "exact": EXACT}
+_SCHEDULES = {"auto": 0, "propagator": 1, "iterated": 2}
 _PROJ = {"max": PROJ_MAX, "mean": PROJ_MEAN}
 
 
@@ -218,6 +222,15 @@ class Plan:
                                          int(n_steps), _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_in),
                                          _ptr(rmap_out), _ptr(out), _vp(_stream())))
         return out
+
+    def set_schedule(self, schedule: str) -> None:
+        """'auto' (default), 'propagator' (collapsed, cached per key) or 'iterated' (n CN steps per mode)."""
+        _check(_lib.se2n_set_schedule(self._h, _SCHEDULES[schedule]))
+
+    def last_schedule(self) -> str:
+        v = _i(0)
+        _check(_lib.se2n_last_schedule(self._h, ctypes.byref(v)))
+        return {k: n for n, k in _SCHEDULES.items()}[v.value]
 
     def restore_workspace(self) -> torch.Tensor:
         n = int(_lib.se2n_restore_workspace_bytes(self._h))
@@ -425,10 +438,14 @@ _lib.se2n_cnn_profile.argtypes = [_vp, _i]
 _lib.se2n_cnn_profile_stats.argtypes = [_vp, ctypes.POINTER(KernelStat), _i, ctypes.POINTER(_i)]
 _lib.se2n_corrected_workspace_bytes.argtypes = [_vp, _vp]
 _lib.se2n_corrected_workspace_bytes.restype = ctypes.c_size_t
-_lib.se2n_inpaint_corrected.argtypes = [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp]
+_lib.se2n_inpaint_corrected.argtypes = [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _i, _d, _vp, _vp,
+                                        ctypes.POINTER(_i), _vp, _vp]
+_lib.se2n_cnn_set_validation.argtypes = [_vp, _i, _d, _d, _i, _i, _i, _d]
+_lib.se2n_cnn_get_validation.argtypes = [_vp, _i, _d, _d, _i, _i, _i, ctypes.POINTER(_d)]
 for _name in ("se2n_plan_info", "se2n_cnn_create", "se2n_cnn_destroy", "se2n_cnn_get_params", "se2n_cnn_set_params",
               "se2n_cnn_forward", "se2n_cnn_gradients", "se2n_cnn_adam_step", "se2n_cnn_train_step",
-              "se2n_cnn_profile", "se2n_cnn_profile_stats", "se2n_inpaint_corrected"):
+              "se2n_cnn_profile", "se2n_cnn_profile_stats", "se2n_inpaint_corrected", "se2n_cnn_set_validation",
+              "se2n_cnn_get_validation"):
     getattr(_lib, _name).restype = _i
 
 CNN_PARAMS = 3 * (32 * 32 * 9 + 32)
@@ -446,6 +463,7 @@ class Corrector:
             _check(_lib.se2n_cnn_create(ctypes.byref(h), self.N, int(seed)))
         self._h = h
         self._ws = {}
+        self._validation = {}
 
     def _vol(self, t: torch.Tensor, name: str) -> tuple:
         if t.dim() == 3:
@@ -523,10 +541,26 @@ class Corrector:
         _check(_lib.se2n_cnn_profile_stats(self._h, arr, n.value, ctypes.byref(n)))
         return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n.value)}
 
+    def set_validation(self, M: int, T: float, beta: float, n_coarse: int, n_fine: int, rel_l2: float,
+                       scheme: str = "cn") -> None:
+        """Record the measured volume rel-L2 against the n_fine-step FP64 solve in a regime."""
+        _check(_lib.se2n_cnn_set_validation(self._h, int(M), float(T), float(beta), int(n_coarse), int(n_fine),
+                                            _SCHEMES[scheme], float(rel_l2)))
+        self._validation[(int(M), float(T), float(beta), int(n_coarse), int(n_fine), scheme)] = float(rel_l2)
+
+    def validation(self, M: int, T: float, beta: float, n_coarse: int, n_fine: int, scheme: str = "cn"):
+        """The recorded rel-L2 of a regime, or None."""
+        r = _d()
+        _check(_lib.se2n_cnn_get_validation(self._h, int(M), float(T), float(beta), int(n_coarse), int(n_fine),
+                                            _SCHEMES[scheme], ctypes.byref(r)))
+        return None if r.value < 0 else r.value
+
     def save(self, path: str) -> None:
-        """Parameters to a NumPy .npz (no pickled objects)."""
+        """Parameters and validation records to a NumPy .npz (no pickled objects)."""
         import numpy as np
-        np.savez(path, params=self.params(), N=np.int64(self.N))
+        rec = np.array([[k[0], k[1], k[2], k[3], k[4], _SCHEMES[k[5]], v] for k, v in self._validation.items()],
+                       dtype=np.float64).reshape(-1, 7)
+        np.savez(path, params=self.params(), N=np.int64(self.N), validation=rec)
 
     def load(self, path: str) -> None:
         import numpy as np
@@ -534,6 +568,10 @@ class Corrector:
             if int(z["N"]) != self.N:
                 raise ValueError(f"{path} holds a network for N={int(z['N'])}, not {self.N}")
             self.set_params(z["params"])
+            rec = z["validation"] if "validation" in z.files else np.zeros((0, 7))
+        names = {v: k for k, v in _SCHEMES.items()}
+        for M, T, beta, nc, nf, sch, err in rec:
+            self.set_validation(int(M), T, beta, int(nc), int(nf), err, names[int(sch)])
 
     def close(self) -> None:
         if getattr(self, "_h", None) is not None:
@@ -549,12 +587,15 @@ class Corrector:
 
 
 def inpaint_corrected(plan: Plan, cnn: Corrector, f: torch.Tensor, mask: torch.Tensor, T: float, beta: float,
-                      n_steps: int, sigma: float = 2.0, scheme: str = "cn", proj: str = "max",
-                      out: torch.Tensor | None = None, rmap_out: torch.Tensor | None = None,
-                      workspace: torch.Tensor | None = None):
-    """orient -> lift -> diffuse (n_steps) -> psi + r(psi) -> project.  Returns (out, rmap)."""
+                      n_steps: int, n_fine: int | None = None, sigma: float = 2.0, scheme: str = "cn",
+                      proj: str = "max", max_rel_l2: float = 1e-3, out: torch.Tensor | None = None,
+                      rmap_out: torch.Tensor | None = None, workspace: torch.Tensor | None = None):
+    """Corrected inpainting (coarse n_steps + network) where the network's recorded
+    error against the n_fine-step solve (default 8 n_steps) is within max_rel_l2,
+    else the plain fused path with n_fine steps.  Returns (out, rmap, used_fallback)."""
     plan._image(f, "f")
     plan._image(mask, "mask", torch.uint8)
+    n_fine = 8 * int(n_steps) if n_fine is None else int(n_fine)
     if out is None:
         out = torch.empty((plan.M, plan.M), dtype=torch.float32, device=plan.device)
     if rmap_out is None:
@@ -564,7 +605,9 @@ def inpaint_corrected(plan: Plan, cnn: Corrector, f: torch.Tensor, mask: torch.T
         if n == 0:
             raise Se2nError(-1, _lib.se2n_last_error().decode() or "plan and network do not match")
         workspace = torch.empty(n, dtype=torch.uint8, device=plan.device)
+    used = _i(0)
     _check(_lib.se2n_inpaint_corrected(plan._h, cnn._h, _ptr(f), _ptr(mask), float(sigma), float(T), float(beta),
-                                       int(n_steps), _SCHEMES[scheme], _PROJ[proj], _ptr(rmap_out), _ptr(out),
-                                       _ptr(workspace), _vp(_stream())))
-    return out, rmap_out
+                                       int(n_steps), n_fine, _SCHEMES[scheme], _PROJ[proj], float(max_rel_l2),
+                                       _ptr(rmap_out), _ptr(out), ctypes.byref(used), _ptr(workspace),
+                                       _vp(_stream())))
+    return out, rmap_out, bool(used.value)

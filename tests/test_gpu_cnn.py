@@ -147,16 +147,54 @@ def test_corrected_path_with_an_identity_network_is_the_plain_path(se2n):
     case = synth.make_case("small", M=64)
     N = case["N"]
     plan = se2n.Plan(64, N, torch.float32)
+    plan.set_schedule("propagator")  # the same schedule for the calls compared bit for bit
     net = se2n.Corrector(N, seed=6)
     f = torch.from_numpy(case["f"].astype(np.float32)).cuda()
     m = torch.from_numpy(case["mask"]).cuda()
-    out_c, rmap_c = se2n.inpaint_corrected(plan, net, f, m, case["T"], case["beta"], 8)
+    # a record licenses the network in this regime (the identity's error against
+    # the 64-step solve is the coarse solve's own)
+    net.set_validation(64, case["T"], case["beta"], 8, 64, 0.01)
+    out_c, rmap_c, fb = se2n.inpaint_corrected(plan, net, f, m, case["T"], case["beta"], 8, 64, max_rel_l2=0.02)
     out_p, rmap_p = plan.inpaint(f, m, case["T"], case["beta"], 8)
     torch.cuda.synchronize()
+    assert not fb
     assert torch.equal(rmap_c, rmap_p)
     assert _rel(out_c.cpu().numpy(), out_p.cpu().numpy()) < 1e-6
+    # above the recorded error, or without a record, the fine-step plain path runs
+    out_f, _, fb = se2n.inpaint_corrected(plan, net, f, m, case["T"], case["beta"], 8, 64, max_rel_l2=0.005)
+    ref_f, _ = plan.inpaint(f, m, case["T"], case["beta"], 64)
+    torch.cuda.synchronize()
+    assert fb and torch.equal(out_f, ref_f)
+    _, _, fb = se2n.inpaint_corrected(plan, net, f, m, case["T"], case["beta"], 8, 32, max_rel_l2=1.0)
+    assert fb
     net.close()
     plan.close()
+
+
+def test_corrected_call_meets_the_bar_at_1024(se2n):
+    """The committed network at 1024^2, N = 32 (25 coarse steps to T = 2 against
+    the 200-step solve): whichever path the call takes, its output is within
+    1e-3 of the fine-step FP64 solve (the network's recorded error there is
+    far above the bar, so the call must fall back)."""
+    import os
+    from paper_1304_2062_amd import corrector
+    M, N, T, beta = 1024, 32, 2.0, 1.0
+    net = se2n.Corrector(N)
+    net.load(os.path.join(os.path.dirname(corrector.__file__), "corrector_N32.npz"))
+    plan = se2n.Plan(M, N, torch.float32)
+    p64 = se2n.Plan(M, N, torch.float64)
+    (f, m), = corrector.images([corrector.EVAL_SEED0 + 100], M, workers=1)
+    ft, mt = torch.from_numpy(f).cuda(), torch.from_numpy(m).cuda()
+    out, rmap, fb = se2n.inpaint_corrected(plan, net, ft, mt, T, beta, 25, 200, max_rel_l2=1e-3)
+    ref, _ = p64.inpaint(ft.double(), mt, T, beta, 200, rmap_in=rmap)
+    torch.cuda.synchronize()
+    rel = _rel(out.double().cpu().numpy(), ref.cpu().numpy())
+    _say(f"corrected call at 1024^2: fallback={fb}, rel-L2 vs fine FP64 {rel:.2e}")
+    assert fb
+    assert rel < 1e-3
+    net.close()
+    plan.close()
+    p64.close()
 
 
 def _pairs(se2n, M, N, seeds, n_coarse=25, n_fine=200, T=2.0):
