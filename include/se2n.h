@@ -87,16 +87,18 @@ size_t se2n_workspace_bytes(se2n_plan plan);
 
 /* Solver schedule of the Crank-Nicolson diffusion (se2n_diffuse, se2n_inpaint;
  * SE2N_EXACT always uses the propagator):
- * SE2N_SCHEDULE_PROPAGATOR  the n steps collapsed into one FP64-built
- *     propagator per frequency class (cached per (T, beta, n_steps)) and
- *     applied in one pass over the spectrum: cost independent of n once built.
+ * SE2N_SCHEDULE_PROPAGATOR (default)  the n steps collapsed into one
+ *     FP64-built propagator per frequency class (cached per (T, beta,
+ *     n_steps)) and applied in one pass over the spectrum: cost independent
+ *     of n once built; repeated calls give identical bits.
  * SE2N_SCHEDULE_ITERATED    the n steps taken one by one on every mode in
  *     registers (remark 2 after Theorem 2: Crank-Nicolson with a cyclic
  *     tridiagonal solver, Thomas + Sherman-Morrison; factors in FP64, steps in
  *     the plan's dtype): no precompute, cost proportional to n.
- * SE2N_SCHEDULE_AUTO (default)  the cached table if there is one; for a key
- *     asked for the first time, the iterated steps when they are estimated
- *     cheaper than building the table; a key asked for again builds it. */
+ * SE2N_SCHEDULE_AUTO  the cached table if there is one; for a key asked for
+ *     the first time, the iterated steps when they are estimated cheaper
+ *     than building the table; a key asked for again builds it (so the first
+ *     and later results of a key differ by rounding). */
 typedef enum {
     SE2N_SCHEDULE_AUTO = 0,
     SE2N_SCHEDULE_PROPAGATOR = 1,

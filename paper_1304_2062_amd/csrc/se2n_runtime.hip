@@ -239,7 +239,7 @@ struct se2n_plan_s {
     bool keep_negligible = false;
     // solver schedule of the CN diffusion: collapsed propagator or iterated
     // steps (se2n_set_schedule); requests per uncached key for the automatic choice
-    se2n_schedule schedule = SE2N_SCHEDULE_AUTO;
+    se2n_schedule schedule = SE2N_SCHEDULE_PROPAGATOR;
     se2n_schedule last_schedule = SE2N_SCHEDULE_AUTO;
     std::map<std::tuple<uint64_t, uint64_t, int>, int> misses;
     struct ProfRec {

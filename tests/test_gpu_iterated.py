@@ -96,6 +96,8 @@ def test_auto_schedule_choice():
     second request builds the table; EXACT always uses the table."""
     case = synth.make_case("small")
     plan = se2n.Plan(64, 16, torch.float32)
+    assert plan.last_schedule() == "auto"  # nothing run yet
+    plan.set_schedule("auto")
     f = torch.from_numpy(case["f"]).to(DEV, torch.float32)
     m = torch.from_numpy(case["mask"]).to(DEV)
     a, _ = plan.inpaint(f, m, 0.5, 1.0, 10)
