@@ -66,8 +66,9 @@ typedef enum { SE2N_PROJ_MAX = 0, SE2N_PROJ_MEAN = 1 } se2n_proj;
 typedef struct se2n_plan_s *se2n_plan;
 
 /* Create a plan for M x M images and N orientations.
- * M: 16 <= M <= 4096, M = 2^a 3^b with a >= 3 (the FFTs are mixed radix 2/3
- *    and rows are processed in groups of 8).
+ * M: 16 <= M <= 4096, M = 2^a 3^b with a >= 2 (the FFTs are mixed radix 2/3;
+ *    4 | M gives the frequency classes their (k, M/2 - k) pairing; sides
+ *    with 8 !| M, e.g. 36, 108, 324, move 4 image rows at a time).
  * N: even, 4 <= N <= 64 (even N lets each per-mode system split into two
  *    N/2 blocks, because the potential cos/sin^2 is pi-periodic, Sec. "The
  *    weighting of the metric", remark about projectivization).
@@ -504,6 +505,13 @@ int se2n_inpaint_corrected(se2n_plan plan, se2n_cnn cnn, const void *f, const ui
                            double T, double beta, int n_steps, int n_fine, se2n_scheme scheme,
                            se2n_proj mode, double max_rel_l2, uint8_t *rmap_out, void *out,
                            int *used_fallback, void *workspace, void *stream);
+
+/* Test hook for the error paths: after `after` more successful device (or
+ * pinned host) allocations by the library, every later one fails as if the
+ * memory were exhausted, until the hook is reset with after = -1 (the
+ * default).  Calls that then need memory return SE2N_ENOMEM and free what
+ * they had allocated.  Process-wide.  Errors: SE2N_EINVAL (after < -1). */
+int se2n_debug_fail_allocations(long after);
 
 /* Message describing the last failure on the calling thread ("" if none). */
 const char *se2n_last_error(void);

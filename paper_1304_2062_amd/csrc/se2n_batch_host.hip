@@ -602,7 +602,10 @@ int build_schedule(BatchPlan& bp) {
         bp.launches.push_back(L);
         flat.insert(flat.end(), p.tiles.begin(), p.tiles.end());
     }
-    SE2N_HIP(hipMalloc(&bp.d_tiles, std::max<size_t>(flat.size(), 1) * sizeof(int4)), "hipMalloc batch tiles");
+    if (dev_malloc((void**)&bp.d_tiles, std::max<size_t>(flat.size(), 1) * sizeof(int4)) != hipSuccess) {
+        bp.d_tiles = nullptr;
+        return fail(SE2N_ENOMEM, "hipMalloc of the batch tiles failed");
+    }
     SE2N_HIP(hipMemcpy(bp.d_tiles, flat.data(), flat.size() * sizeof(int4), hipMemcpyHostToDevice),
              "upload of batch tiles");
 
@@ -637,11 +640,16 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
     bp.layout = layout_of(bp.shapes);
     SE2N_HIP(hipStreamCreateWithFlags(&bp.cap, hipStreamNonBlocking), "capture stream");
     for (int k = 0; k < 2; ++k) {
-        SE2N_HIP(hipHostMalloc((void**)&bp.pinned[k], (size_t)count * sizeof(BItem), hipHostMallocDefault),
-                 "pinned item staging");
+        if (pinned_malloc((void**)&bp.pinned[k], (size_t)count * sizeof(BItem)) != hipSuccess) {
+            bp.pinned[k] = nullptr;
+            return fail(SE2N_ENOMEM, "pinned allocation of the item staging failed");
+        }
         SE2N_HIP(hipEventCreateWithFlags(&bp.pinned_ev[k], hipEventDisableTiming), "staging event");
     }
-    SE2N_HIP(hipMalloc(&bp.d_items, (size_t)count * sizeof(BItem)), "hipMalloc batch items");
+    if (dev_malloc((void**)&bp.d_items, (size_t)count * sizeof(BItem)) != hipSuccess) {
+        bp.d_items = nullptr;
+        return fail(SE2N_ENOMEM, "hipMalloc of the batch items failed");
+    }
 
     bp.items.assign(count, BItem{});
     for (int i = 0; i < count; ++i) {
@@ -651,7 +659,8 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         if (!bp.twiddles.count(M)) {
             const std::vector<C2<float>> h = quarter_twiddles<float>(M);
             void* d = nullptr;
-            SE2N_HIP(hipMalloc(&d, h.size() * sizeof(C2<float>)), "hipMalloc twiddles");
+            if (dev_malloc(&d, h.size() * sizeof(C2<float>)) != hipSuccess)
+                return fail(SE2N_ENOMEM, "hipMalloc of a twiddle table failed");
             bp.twiddles[M] = d;
             SE2N_HIP(hipMemcpy(d, h.data(), h.size() * sizeof(C2<float>), hipMemcpyHostToDevice), "twiddle upload");
         }
@@ -659,7 +668,7 @@ int build_plan(BatchPlan& bp, const se2n_item* items, int count, hipStream_t st)
         const TableKey tk{M, x.N, x.n, x.scheme, x.T, x.beta};
         if (!bp.tables.count(tk)) {
             void* d = nullptr;
-            const hipError_t e = hipMalloc(&d, table_bytes(M, x.N, 4));  // class-major propagators + class flags
+            const hipError_t e = dev_malloc(&d, table_bytes(M, x.N, 4));  // class-major propagators + class flags
             if (e != hipSuccess) return fail(SE2N_ENOMEM, "hipMalloc of a propagator table: %s", hipGetErrorString(e));
             bp.tables[tk] = d;
             SE2N_HIP(launch_precompute<float>((float*)d, M, x.N, x.beta, x.T, x.n, x.scheme, st),

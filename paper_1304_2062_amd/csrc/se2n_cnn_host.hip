@@ -270,10 +270,10 @@ int se2n_cnn_create(se2n_cnn* out, int N, uint64_t seed) {
     (void)hipGetDevice(&c->device);
     hipError_t e = hipSuccess;
     for (float** p : {&c->params, &c->m, &c->v, &c->grads})
-        if (e == hipSuccess) e = hipMalloc((void**)p, kCnnP * sizeof(float));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->loss, 256);
-    if (e == hipSuccess) e = hipMalloc((void**)&c->wf, 3 * kCnnW * sizeof(bf16));
-    if (e == hipSuccess) e = hipMalloc((void**)&c->wd, 3 * kCnnW * sizeof(bf16));
+        if (e == hipSuccess) e = dev_malloc((void**)p, kCnnP * sizeof(float));
+    if (e == hipSuccess) e = dev_malloc((void**)&c->loss, 256);
+    if (e == hipSuccess) e = dev_malloc((void**)&c->wf, 3 * kCnnW * sizeof(bf16));
+    if (e == hipSuccess) e = dev_malloc((void**)&c->wd, 3 * kCnnW * sizeof(bf16));
     if (e != hipSuccess) {
         free_cnn(c);
         delete c;

@@ -25,6 +25,11 @@ std::vector<C2<R>> quarter_twiddles(int M);
 
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Every device (and pinned host) allocation of the library goes through
+// these, so that se2n_debug_fail_allocations can make the k-th one fail.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t pinned_malloc(void** p, size_t bytes);
+
 struct OrientTaps;
 // Taps of the orientation stencil for side M and Gaussian width sigma: the
 // radius it needs (kernel tails below 2^-26 of each kernel's absolute sum,

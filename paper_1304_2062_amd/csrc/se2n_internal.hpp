@@ -93,6 +93,7 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
 #define SE2N_ROW_SEG_BYTES 64
 #endif
     int rows = SE2N_ROW_SEG_BYTES / cs;                // contiguous bytes per (slice, kx) segment
+    while (M % rows) rows >>= 1;                       // sides with 4 | M, 8 !| M: 4-row blocks
     while (rows * 2 * H <= target && M % (rows * 2) == 0 && rows * 2 <= M) rows *= 2;
     g.rows = rows;
     fft_threads_of(rows * H, g.row_threads, g.row_ept);

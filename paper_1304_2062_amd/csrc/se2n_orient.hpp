@@ -151,7 +151,7 @@ __device__ __forceinline__ void orient_stencil_tile(const float* __restrict__ f,
         w[i / 4] |= (uint32_t)b << (8 * (i % 4));
     }
     uint8_t* dst = rmap + (size_t)py * M + px;
-    if (px + kOrientCH <= M) {
+    if (px + kOrientCH <= M && (M & 7) == 0) {
         // M is a multiple of 8, so each half of the run is 8-byte aligned
         reinterpret_cast<uint2*>(dst)[0] = make_uint2(w[0], w[1]);
         reinterpret_cast<uint2*>(dst)[1] = make_uint2(w[2], w[3]);

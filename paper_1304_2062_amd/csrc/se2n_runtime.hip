@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -41,6 +42,29 @@ int hip_fail(hipError_t e, const char* what) {
 }
 
 void clear_error() { g_last_error.clear(); }
+
+// Allocation-failure injection: -1 disables it; k >= 0 lets k allocations
+// succeed and fails every later one until reset.
+std::atomic<long> g_alloc_budget{-1};
+
+static bool alloc_allowed() {
+    long k = g_alloc_budget.load();
+    while (k >= 0) {
+        if (k == 0) return false;
+        if (g_alloc_budget.compare_exchange_weak(k, k - 1)) return true;
+    }
+    return true;
+}
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+    if (!alloc_allowed()) return hipErrorOutOfMemory;
+    return hipMalloc(p, bytes);
+}
+
+hipError_t pinned_malloc(void** p, size_t bytes) {
+    if (!alloc_allowed()) return hipErrorOutOfMemory;
+    return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
 
 bool is_2a3b(int M, int* twos, int* threes) {
     int a = 0, b = 0, m = M;
@@ -406,7 +430,7 @@ int get_propagators(se2n_plan p, double T, double beta, int n_steps, se2n_scheme
         p->cache.pop_back();
     }
     void* d = nullptr;
-    hipError_t e = hipMalloc(&d, bytes);
+    hipError_t e = dev_malloc(&d, bytes);
     if (e != hipSuccess) return fail(SE2N_ENOMEM, "hipMalloc of %zu bytes for propagators: %s", bytes,
                                      hipGetErrorString(e));
     {
@@ -715,7 +739,11 @@ int restore_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, dou
 template <class R>
 int make_twiddles(se2n_plan p) {
     const std::vector<C2<R>> h = quarter_twiddles<R>(p->M);
-    SE2N_HIP(hipMalloc(&p->tw, h.size() * sizeof(C2<R>)), "hipMalloc twiddles");
+    const hipError_t e = dev_malloc(&p->tw, h.size() * sizeof(C2<R>));
+    if (e != hipSuccess) {
+        p->tw = nullptr;
+        return fail(SE2N_ENOMEM, "hipMalloc of the twiddle table: %s", hipGetErrorString(e));
+    }
     SE2N_HIP(hipMemcpy(p->tw, h.data(), h.size() * sizeof(C2<R>), hipMemcpyHostToDevice), "twiddle upload");
     return SE2N_OK;
 }
@@ -755,8 +783,8 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     g_last_error.clear();
     if (!out) return fail(SE2N_EINVAL, "out is NULL");
     int twos = 0;
-    if (M < 16 || M > 4096 || !is_2a3b(M, &twos, nullptr) || twos < 3)
-        return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 3 and 16 <= M <= 4096 (got %d)", M);
+    if (M < 16 || M > 4096 || !is_2a3b(M, &twos, nullptr) || twos < 2)
+        return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 2 and 16 <= M <= 4096 (got %d)", M);
     if (N < 4 || N > 64) return fail(SE2N_EINVAL, "N must lie in [4, 64] (got %d)", N);
     if (N % 2) return fail(SE2N_EUNSUPPORTED, "odd N (%d) is not supported: N must be even", N);
     if (dtype != SE2N_F32 && dtype != SE2N_F64) return fail(SE2N_EINVAL, "unknown dtype %d", (int)dtype);
@@ -887,8 +915,8 @@ int se2n_orient_method(se2n_plan p, double sigma, int* radius) {
 int se2n_orient_stencil_taps(int M, double sigma, float* g, float* d, int* radius) {
     g_last_error.clear();
     if (!g || !d || !radius) return fail(SE2N_EINVAL, "null pointer argument");
-    if (M < 16 || M > 4096 || !is_2a3b(M, nullptr, nullptr) || M % 8 != 0)
-        return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 3 in [16, 4096] (got %d)", M);
+    if (M < 16 || M > 4096 || !is_2a3b(M, nullptr, nullptr) || M % 4 != 0)
+        return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 2 in [16, 4096] (got %d)", M);
     if (!(sigma > 0.0) || !std::isfinite(sigma)) return fail(SE2N_EINVAL, "sigma must be > 0 (got %g)", sigma);
     OrientTaps t;
     const int rad = orient_stencil_taps(M, sigma, &t);
@@ -1105,6 +1133,13 @@ int se2n_profile_stats(se2n_plan p, se2n_kernel_stat* out, int capacity, int* co
         ++i;
     }
     *count = i;
+    return SE2N_OK;
+}
+
+int se2n_debug_fail_allocations(long after) {
+    g_last_error.clear();
+    if (after < -1) return fail(SE2N_EINVAL, "after must be >= -1 (got %ld)", after);
+    g_alloc_budget.store(after);
     return SE2N_OK;
 }
 

@@ -42,6 +42,8 @@ _lib.se2n_diffuse.argtypes = [_vp, _vp, _d, _d, _i, _i, _vp, _vp]
 _lib.se2n_project.argtypes = [_vp, _vp, _i, _vp, _vp]
 _lib.se2n_inpaint.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp, _vp]
 _lib.se2n_inpaint_noalloc.argtypes = [_vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _vp, _vp, _vp, _vp]
+_lib.se2n_debug_fail_allocations.argtypes = [ctypes.c_long]
+_lib.se2n_debug_fail_allocations.restype = _i
 _lib.se2n_set_schedule.argtypes = [_vp, _i]
 _lib.se2n_last_schedule.argtypes = [_vp, ctypes.POINTER(_i)]
 _lib.se2n_restore_workspace_bytes.argtypes = [_vp]
@@ -85,6 +87,11 @@ class Se2nError(RuntimeError):
 def _check(rc: int) -> None:
     if rc != 0:
         raise Se2nError(rc, _lib.se2n_last_error().decode())
+
+
+def debug_fail_allocations(after: int) -> None:
+    """Make the library's allocations fail after `after` more successes (-1 resets)."""
+    _check(_lib.se2n_debug_fail_allocations(int(after)))
 
 
 def version() -> str:

@@ -1,0 +1,97 @@
+"""The GPU diffusion against the paper's theoretical statements (cross-checks
+of the semi-discrete model; FP64 plans, se2n_diffuse on plane-wave volumes).
+
+* Theorem 1 / equation (redap): a trigonometric polynomial evolves by an
+  N-dimensional ODE per frequency.  On the grid the frequency lambda becomes
+  the central-difference symbol sqrt(M) sin(lambda / sqrt(M)); at a fixed
+  physical frequency the grid result converges to the reduction's as M grows,
+  with error O(1/M) (the symbol's relative error is lambda^2 / (6 M)).
+* The rotation theorem of Sec. "A view through almost periodic functions":
+  the solution for a rotated frequency is the orientation-shifted solution.
+  On the square grid the 90-degree rotation maps frequencies to frequencies
+  (4 | N, shift N/4), and there it holds to rounding.
+* Sec. "The weighting of the metric": with beta_N = alpha (N / 2 pi)^2 the
+  semi-discrete system tends to the continuous-angle equation
+  (contdif-weight) as N grows, at second order in 1/N.
+The references come from oracle/theory_oracle.py (pinned by closed forms).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+from oracle import theory_oracle as TH
+from paper_1304_2062_amd import se2n
+
+pytestmark = pytest.mark.gpu
+DEV = torch.device("cuda", 0)
+
+
+def _wave_coefficients(M, N, k, l, a0, T, beta, scheme="exact", n=1):
+    """Diffuse psi_r = a0_r cos(2 pi (k x + l y) / M) on the GPU and return the
+    cosine and sine coefficient vectors of the result at (k, l)."""
+    y, x = np.mgrid[0:M, 0:M]
+    ph = 2 * np.pi * (k * x + l * y) / M
+    c, s = np.cos(ph), np.sin(ph)
+    psi = np.asarray(a0)[:, None, None] * c[None]
+    plan = se2n.Plan(M, N, torch.float64)
+    t = torch.from_numpy(psi).to(DEV)
+    plan.diffuse(t, T, beta, n, scheme)
+    torch.cuda.synchronize()
+    out = t.cpu().numpy()
+    plan.close()
+    cc = 2.0 / (M * M) * np.tensordot(out, c, axes=([1, 2], [0, 1]))
+    ss = 2.0 / (M * M) * np.tensordot(out, s, axes=([1, 2], [0, 1]))
+    return cc, ss
+
+
+def test_grid_converges_to_the_almost_periodic_reduction():
+    N, beta, T = 16, 2.0, 0.3
+    e = 2 * np.pi * np.arange(N) / N
+    a0 = np.exp(np.cos(e - 0.3))
+    lam, mu = 2 * np.pi / 8, 3 * 2 * np.pi / 8
+    ref = TH.ap_solve(lam, mu, a0, N, beta, T).real
+    errs = []
+    for M in (64, 256, 1024):
+        k, l = int(np.sqrt(M)) // 8, 3 * int(np.sqrt(M)) // 8
+        print(f"theory: plane wave ({k}, {l}) at M={M}", flush=True)
+        cc, ss = _wave_coefficients(M, N, k, l, a0, T, beta)
+        assert np.abs(ss).max() < 1e-12 * np.abs(cc).max()
+        # the grid system itself is the reduction at the grid symbol (Theorem 2)
+        sym = np.sqrt(M) * np.sin(2 * np.pi * np.array([k, l]) / M)
+        np.testing.assert_allclose(cc, TH.ap_solve(sym[0], sym[1], a0, N, beta, T).real, atol=1e-12)
+        errs.append(np.abs(cc - ref).max() / np.abs(ref).max())
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    print(f"  errors {errs}, ratios {ratios}", flush=True)
+    assert all(3.8 < r < 4.2 for r in ratios)
+    assert errs[-1] < 1e-3
+
+
+@pytest.mark.parametrize("scheme,n", [("exact", 1), ("cn", 20)])
+def test_rotation_theorem_on_the_grid(scheme, n):
+    """omega' = (-l, k) is omega = (k, l) rotated by 90 degrees = N/4 orientation
+    steps: started from S^{N/4} a0 it evolves into S^{N/4} A(T)."""
+    M, N, beta, T = 64, 16, 1.5, 0.4
+    rng = np.random.default_rng(7)
+    a0 = rng.normal(size=N)
+    c1, s1 = _wave_coefficients(M, N, 3, 5, a0, T, beta, scheme, n)
+    c2, s2 = _wave_coefficients(M, N, -5 % M, 3, np.roll(a0, N // 4), T, beta, scheme, n)
+    np.testing.assert_allclose(c2, np.roll(c1, N // 4), atol=1e-13)
+    assert np.abs(s1).max() < 1e-13 and np.abs(s2).max() < 1e-13
+
+
+def test_semi_discrete_tends_to_the_continuous_angle_limit():
+    M, T, alpha = 64, 0.3, 0.4
+    k, l = 1, 2
+    sym = np.sqrt(M) * np.sin(2 * np.pi * np.array([k, l]) / M)
+    g = lambda t: np.exp(0.8 * np.cos(t - 0.3))
+    errs = []
+    for N in (16, 32, 64):
+        e = 2 * np.pi * np.arange(N) / N
+        print(f"theory: N={N} against the continuous-angle limit", flush=True)
+        cc, _ = _wave_coefficients(M, N, k, l, g(e), T, O.beta_from_alpha(alpha, N))
+        errs.append(np.abs(cc - TH.theta_continuum(sym[0], sym[1], alpha, g, T, e)).max())
+    ratios = [errs[0] / errs[1], errs[1] / errs[2]]
+    print(f"  errors {errs}, ratios {ratios}", flush=True)
+    assert all(3.5 < r < 4.5 for r in ratios)
+    assert errs[-1] < 2e-3

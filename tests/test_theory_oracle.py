@@ -1,0 +1,97 @@
+"""Pins of the theory references (oracle/theory_oracle.py): closed forms of
+the almost-periodic reduction (equation (redap), Theorem 1) and of the
+continuous-angle limit (equation (contdif-weight)), the rotation theorem of
+Sec. "A view through almost periodic functions", and the correspondence
+between the reduction and the grid's per-mode systems (Theorem 2)."""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import oracle as O  # noqa: E402
+from oracle import theory_oracle as TH  # noqa: E402
+
+
+def test_ap_zero_frequency_orientation_modes_decay_in_closed_form():
+    """lambda = mu = 0: A = beta L, so the orientation DFT mode m decays by
+    exp(-4 beta sin^2(pi m / N) T)."""
+    N, beta, T = 12, 1.7, 0.8
+    r = np.arange(N)
+    for m in range(N):
+        a0 = np.exp(2j * np.pi * m * r / N)
+        got = TH.ap_solve(0.0, 0.0, a0, N, beta, T)
+        np.testing.assert_allclose(got, np.exp(-4 * beta * np.sin(np.pi * m / N) ** 2 * T) * a0, atol=1e-13)
+
+
+def test_ap_without_coupling_decays_by_the_potential():
+    N, lam, mu, T = 10, 1.3, -0.7, 0.9
+    a0 = np.linspace(1.0, 2.0, N)
+    e = 2 * np.pi * np.arange(N) / N
+    got = TH.ap_solve(lam, mu, a0, N, 0.0, T)
+    np.testing.assert_allclose(got, np.exp(-((lam * np.cos(e) + mu * np.sin(e)) ** 2) * T) * a0, rtol=1e-13)
+
+
+@pytest.mark.parametrize("j", [1, 3, 5])
+def test_rotation_theorem(j):
+    """If omega' = R_j omega then the solution for omega' started from
+    S^j A(0) is S^j A(t): one resolvent per rotation orbit suffices."""
+    N, beta, T = 16, 2.0, 0.6
+    lam, mu = 1.1, 0.4
+    e = 2 * np.pi * j / N
+    lam2, mu2 = lam * np.cos(e) - mu * np.sin(e), lam * np.sin(e) + mu * np.cos(e)
+    rng = np.random.default_rng(j)
+    a0 = rng.normal(size=N) + 1j * rng.normal(size=N)
+    A = TH.ap_solve(lam, mu, a0, N, beta, T)
+    A2 = TH.ap_solve(lam2, mu2, np.roll(a0, j), N, beta, T)
+    np.testing.assert_allclose(A2, np.roll(A, j), atol=1e-12)
+
+
+def test_grid_mode_is_the_reduction_at_the_central_difference_symbol():
+    """Theorem 2's per-mode system at grid frequency (k, l) is the almost-periodic
+    system with lambda = sqrt(M) sin(2 pi k / M), mu = sqrt(M) sin(2 pi l / M)."""
+    M, N, beta, T = 64, 8, 1.5, 0.4
+    rng = np.random.default_rng(3)
+    for k, l in ((1, 3), (5, 0), (17, 40)):
+        a0 = rng.normal(size=N) + 1j * rng.normal(size=N)
+        grid = O.diffuse_modes_exact(a0[None, :], M, [k], [l], beta, T)[0]
+        s = np.sqrt(M) * np.sin(2 * np.pi * np.array([k, l]) / M)
+        np.testing.assert_allclose(grid, TH.ap_solve(s[0], s[1], a0, N, beta, T), atol=1e-13)
+
+
+def test_continuum_pure_angular_diffusion():
+    alpha, T = 0.3, 0.7
+    th = np.linspace(0, 2 * np.pi, 13, endpoint=False)
+    got = TH.theta_continuum(0.0, 0.0, alpha, lambda t: np.cos(3 * t) + 0.5 * np.sin(t), T, th)
+    want = np.exp(-9 * alpha * T) * np.cos(3 * th) + 0.5 * np.exp(-alpha * T) * np.sin(th)
+    np.testing.assert_allclose(got, want, atol=1e-13)
+
+
+def test_continuum_without_angular_diffusion_is_pointwise():
+    """alpha = 0: a(theta, T) = exp(-(lam cos theta + mu sin theta)^2 T) a(theta, 0)."""
+    lam, mu, T = 1.2, -0.8, 0.5
+    g = lambda t: np.exp(np.cos(t - 0.4))
+    th = np.linspace(0, 2 * np.pi, 17, endpoint=False)
+    got = TH.theta_continuum(lam, mu, 0.0, g, T, th)
+    want = np.exp(-((lam * np.cos(th) + mu * np.sin(th)) ** 2) * T) * g(th)
+    np.testing.assert_allclose(got, want, rtol=1e-11)
+
+
+def test_semi_discrete_tends_to_the_continuum_at_second_order():
+    """beta_N = alpha (N / 2 pi)^2: the N-orientation system converges to the
+    continuous-angle equation as N grows, the error falling like 1/N^2
+    (the cyclic second difference is a second-order approximation)."""
+    lam, mu, alpha, T = 1.0, 0.5, 0.4, 0.6
+    g = lambda t: np.exp(0.8 * np.cos(t - 0.3))
+    errs = []
+    for N in (16, 32, 64, 128):
+        e = 2 * np.pi * np.arange(N) / N
+        beta = O.beta_from_alpha(alpha, N)
+        semi = TH.ap_solve(lam, mu, g(e), N, beta, T).real
+        errs.append(np.abs(semi - TH.theta_continuum(lam, mu, alpha, g, T, e)).max())
+    ratios = [errs[i] / errs[i + 1] for i in range(3)]
+    assert all(3.6 < r < 4.4 for r in ratios), (errs, ratios)
