@@ -69,9 +69,11 @@ typedef struct se2n_plan_s *se2n_plan;
  * M: 16 <= M <= 4096, M = 2^a 3^b with a >= 2 (the FFTs are mixed radix 2/3;
  *    4 | M gives the frequency classes their (k, M/2 - k) pairing; sides
  *    with 8 !| M, e.g. 36, 108, 324, move 4 image rows at a time).
- * N: even, 4 <= N <= 64 (even N lets each per-mode system split into two
- *    N/2 blocks, because the potential cos/sin^2 is pi-periodic, Sec. "The
- *    weighting of the metric", remark about projectivization).
+ * N: 4 <= N <= 64.  Even N lets each per-mode system split into two N/2
+ *    blocks (the potential is pi-periodic, Sec. "The weighting of the
+ *    metric", remark about projectivization): the fast path.  Odd N keeps
+ *    one N x N propagator per frequency class (a plain solve kernel; the
+ *    iterated schedule needs even N).
  * The plan owns twiddle tables (allocated here) and a cache of per-frequency
  * propagators (allocated on first use).  *out is set on success only.
  * Errors: SE2N_EINVAL (null out, bad M or N, bad dtype), SE2N_ENOMEM, SE2N_EHIP. */
@@ -105,6 +107,7 @@ typedef enum {
     SE2N_SCHEDULE_PROPAGATOR = 1,
     SE2N_SCHEDULE_ITERATED = 2
 } se2n_schedule;
+/* Errors: SE2N_EINVAL (unknown schedule), SE2N_EUNSUPPORTED (iterated with odd N). */
 int se2n_set_schedule(se2n_plan plan, se2n_schedule schedule);
 /* The schedule the plan's last diffusion ran (SE2N_SCHEDULE_AUTO before any).
  * Errors: SE2N_EINVAL (NULL), SE2N_ESTATE. */

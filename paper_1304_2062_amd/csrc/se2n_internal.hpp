@@ -148,9 +148,14 @@ __host__ __device__ constexpr int xcd_contiguous(int i, int n) {
 // (N/2)(N/2 + 1) reals, padded to whole 128-byte lines: the classes a solve
 // workgroup stages form one contiguous run, and a negligible class that is
 // skipped shares no line with a live one.
+// Reals per class: both N/2 x N/2 blocks (even N), or the whole N x N
+// propagator (odd N, where the potential's period N/2 is no symmetry).
+__host__ __device__ constexpr int table_class_entries(int N) {
+    return (N & 1) ? N * (N + 1) / 2 : (N / 2) * (N / 2 + 1);
+}
 __host__ __device__ constexpr int table_class_stride(int N, int rsize) {
     const int line = 128 / rsize;
-    const int E = (N / 2) * (N / 2 + 1);
+    const int E = table_class_entries(N);
     return (E + line - 1) / line * line;
 }
 

@@ -197,6 +197,7 @@ __global__ void k_project(const R* __restrict__ psi, R* __restrict__ out, long M
 // ---------------------------------------------------------------------------
 // For class (lx, ly) and each block (periodic +, antiperiodic -) of size
 // h = N/2:  A = beta L_h^{+-} - diag(pot_j), pot_j = M (cos e_j s_x + sin e_j s_y)^2.
+// Odd N: one periodic block of size h = N, the whole propagator.
 //   CN:    C = (I - tau A/2)^{-1} (I + tau A/2) by Gauss-Jordan (the left
 //          matrix is symmetric, diagonally dominant: no pivoting), P = C^n by
 //          binary powering.
@@ -222,14 +223,20 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
                                                    double beta, double T, int nsteps, int scheme,
                                                    double scale, int keep_all) {
     extern __shared__ double sm[];
-    const int h = N / 2;
+    const bool odd = (N & 1) != 0;
+    const int h = odd ? N : N / 2;
+    const int nblk = odd ? 1 : 2;
     const int hh = h * h;
-    double* A = sm;          // generator block
-    double* Bs = A + hh;     // base / result of the solve
-    double* Rs = Bs + hh;    // running product
+    // LDS: W (2hh) | Rs (hh) | Ts (hh) | pot (h).  CN builds the generator A
+    // in Ts, fills the augmented matrix W from it, eliminates (Ts then holds
+    // the pivot column), and compacts the right half of W (the one-step
+    // propagator) into W's first hh entries, Bs.  EXACT keeps A in W.
+    double* W = sm;          // h x 2h augmented matrix
+    double* Bs = W;          // base of the powering (CN)
+    double* Rs = W + 2 * hh; // running product
     double* Ts = Rs + hh;    // temporary
-    double* W = Ts + hh;     // h x 2h augmented matrix
-    double* pot = W + 2 * hh;
+    double* pot = Ts + hh;
+    double* A = scheme == 0 ? Ts : W;  // generator block
     const int tid = threadIdx.x;
     const int lx = blockIdx.x / Q;
     const int ly = blockIdx.x - lx * Q;
@@ -243,10 +250,10 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     }
     __syncthreads();
     const int Eh = h * (h + 1) / 2;
-    const int E = 2 * Eh;
+    const int E = nblk * Eh;
     const int CS = table_class_stride(N, (int)sizeof(R));
     double pmax = 0.0;  // largest entry of the unscaled propagator, this thread's share
-    for (int blk = 0; blk < 2; ++blk) {
+    for (int blk = 0; blk < nblk; ++blk) {
         const double wrap = blk == 0 ? 1.0 : -1.0;
         for (int idx = tid; idx < hh; idx += 64) {
             const int i = idx / h;
@@ -281,10 +288,19 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
                 }
                 __syncthreads();
             }
+            // compact the right half of W into its first hh entries, row by
+            // row: row i's destination [i h, i h + h) holds only entries of
+            // rows already copied (and left halves, no longer needed)
+            for (int i = 0; i < h; ++i) {
+                double v = 0.0;
+                if (tid < h) v = W[i * 2 * h + h + tid];
+                __syncthreads();
+                if (tid < h) Bs[i * h + tid] = v;
+                __syncthreads();
+            }
             for (int idx = tid; idx < hh; idx += 64) {
                 const int i = idx / h;
                 const int j = idx - i * h;
-                Bs[idx] = W[i * 2 * h + h + j];
                 Rs[idx] = (i == j) ? 1.0 : 0.0;
             }
             __syncthreads();
@@ -585,9 +601,10 @@ template <class R>
 hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
                              hipStream_t st, bool keep_all) {
     const int Q = M / 4 + 1;
-    const int h = N / 2;
-    const size_t lds = (size_t)(6 * h * h + h) * sizeof(double);
-    const double scale = 1.0 / (2.0 * (double)M * (double)M);
+    const int h = (N & 1) ? N : N / 2;
+    const size_t lds = (size_t)(4 * h * h + h) * sizeof(double);
+    // the inverse FFT's 1/M^2, and for even N the 1/2 of the p/q recombination
+    const double scale = ((N & 1) ? 1.0 : 0.5) / ((double)M * (double)M);
     hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q,
                        flag_stride(M), beta,
                        T, nsteps, scheme, scale, keep_all ? 1 : 0);

@@ -484,7 +484,7 @@ double est_precompute_ms(int M, int N, int n) {
 // run while they are estimated cheaper than building the table, until the
 // key has been asked for a second time (a table then pays for itself).
 bool use_iterated(se2n_plan p, double T, double beta, int n_steps, se2n_scheme scheme) {
-    if (scheme != SE2N_CN) return false;
+    if (scheme != SE2N_CN || (p->N & 1)) return false;  // the iterated kernel splits even N into p/q blocks
     if (p->schedule == SE2N_SCHEDULE_ITERATED) return true;
     if (p->schedule == SE2N_SCHEDULE_PROPAGATOR) return false;
     if (find_propagators(p, T, beta, n_steps, scheme)) return false;
@@ -786,7 +786,6 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
     if (M < 16 || M > 4096 || !is_2a3b(M, &twos, nullptr) || twos < 2)
         return fail(SE2N_EINVAL, "M must be 2^a 3^b with a >= 2 and 16 <= M <= 4096 (got %d)", M);
     if (N < 4 || N > 64) return fail(SE2N_EINVAL, "N must lie in [4, 64] (got %d)", N);
-    if (N % 2) return fail(SE2N_EUNSUPPORTED, "odd N (%d) is not supported: N must be even", N);
     if (dtype != SE2N_F32 && dtype != SE2N_F64) return fail(SE2N_EINVAL, "unknown dtype %d", (int)dtype);
     se2n_plan p = new (std::nothrow) se2n_plan_s;
     if (!p) return fail(SE2N_ENOMEM, "host allocation of the plan failed");
@@ -1079,6 +1078,8 @@ int se2n_set_schedule(se2n_plan p, se2n_schedule schedule) {
     if (rc) return rc;
     if (schedule != SE2N_SCHEDULE_AUTO && schedule != SE2N_SCHEDULE_PROPAGATOR && schedule != SE2N_SCHEDULE_ITERATED)
         return fail(SE2N_EINVAL, "unknown schedule %d", (int)schedule);
+    if (schedule == SE2N_SCHEDULE_ITERATED && (p->N & 1))
+        return fail(SE2N_EUNSUPPORTED, "the iterated schedule needs even N (got %d)", p->N);
     p->schedule = schedule;
     return SE2N_OK;
 }

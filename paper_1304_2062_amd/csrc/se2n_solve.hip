@@ -45,8 +45,69 @@ static hipError_t launch_solve_n(C2<R>* spec, const R* P, int M, hipStream_t st,
     return hipGetLastError();
 }
 
+// Odd N: the propagator of class (lx, ly) is one symmetric N x N matrix,
+// stored as its packed upper triangle (scaled by the inverse FFT's 1/M^2).
+// One workgroup per class; thread (member m, orientation r) of its up to 8
+// members (kx in {lx, M/2 - lx}, ky in {ly, M/2 - ly, M/2 + ly, M - ly})
+// stages x_r of its member in LDS and forms y_r = sum_c P[r][c] x_c.  The
+// members with ky > M/2 (s_ky < 0) see the class potential with r -> -r:
+// for them y_r = sum_c P[-r][-c] x_c.  Negligible classes: zeros (zfill) or
+// nothing.  Odd N is a correctness path (no p/q split exists), not a tuned one.
+template <class R>
+__global__ __launch_bounds__(512) void k_solve_odd(C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int N,
+                                                   int Q, int FS, int zfill) {
+    extern __shared__ unsigned char smem_raw[];
+    C2<R>* xs = reinterpret_cast<C2<R>*>(smem_raw);  // [8][N]
+    const int lx = blockIdx.x / Q;
+    const int ly = blockIdx.x - lx * Q;
+    const int H = M / 2;
+    const int t = threadIdx.x;
+    const int m = t / N;
+    const int r = t - m * N;
+    const int a = m >> 2, b = m & 3;
+    bool live = m < 8;
+    live = live && !(a == 1 && 2 * lx == H);
+    live = live && !(ly == 0 && b >= 2);
+    live = live && !(2 * ly == H && (b & 1));
+    const int kx = a ? H - lx : lx;
+    const int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
+    const size_t plane = (size_t)(H + 1) * M;
+    C2<R>* col = spec + (size_t)kx * M + (live ? ky : 0);
+    const uint8_t* flags = reinterpret_cast<const uint8_t*>(P + (size_t)Q * Q * table_class_stride(N, sizeof(R)));
+    if (flags[(size_t)lx * FS + ly]) {
+        if (live && zfill) col[(size_t)r * plane] = cmk<R>(R(0), R(0));
+        return;
+    }
+    if (live) xs[m * N + r] = col[(size_t)r * plane];
+    __syncthreads();
+    if (!live) return;
+    const R* Pc = P + ((size_t)lx * Q + ly) * table_class_stride(N, sizeof(R));
+    const bool perm = b >= 2;
+    const int rr = perm ? (N - r) % N : r;
+    C2<R> acc = cmk<R>(R(0), R(0));
+    for (int c = 0; c < N; ++c) {
+        const int cc = perm ? (N - c) % N : c;
+        const int i = rr < cc ? rr : cc, j = rr < cc ? cc : rr;
+        const R p = Pc[i * N - i * (i - 1) / 2 + (j - i)];
+        const C2<R> x = xs[m * N + c];
+        acc.x += p * x.x;
+        acc.y += p * x.y;
+    }
+    col[(size_t)r * plane] = acc;
+}
+
+template <class R>
+static hipError_t launch_solve_odd(C2<R>* spec, const R* P, int M, int N, hipStream_t st, bool zfill) {
+    const int Q = M / 4 + 1;
+    const int threads = (8 * N + 63) / 64 * 64;
+    hipLaunchKernelGGL((k_solve_odd<R>), dim3((unsigned)(Q * Q)), dim3(threads), 8 * N * sizeof(C2<R>), st, spec, P,
+                       M, N, Q, flag_stride(M), zfill ? 1 : 0);
+    return hipGetLastError();
+}
+
 template <class R>
 hipError_t launch_solve(C2<R>* spec, const R* P, int M, int N, hipStream_t st, bool zfill) {
+    if (N & 1) return launch_solve_odd<R>(spec, P, M, N, st, zfill);
     switch (N) {
 #define SE2N_CASE(n) \
     case n: return launch_solve_n<R, n>(spec, P, M, st, zfill);

@@ -15,6 +15,7 @@ Usage:
     python -m paper_1304_2062_amd.profile_summary stats <dir> --cmd "<command>" > profiles/x.md
     python -m paper_1304_2062_amd.profile_summary traffic <fetch_dir> <write_dir> --copy-bytes B \\
         --cmd "<commands>" [--json out.json] > profiles/y.md
+    python -m paper_1304_2062_amd.profile_summary sq <dir> [<dir> ...] --cmd "<commands>" > profiles/z.md
 """
 from __future__ import annotations
 
@@ -80,6 +81,15 @@ def counters(dirname: str) -> dict[str, list[float]]:
     return agg
 
 
+def named_counters(dirname: str) -> dict[str, dict[str, list[float]]]:
+    """{kernel: {counter: [value per dispatch]}} of a --pmc run with several counters."""
+    rows = list(csv.DictReader(open(_find(dirname, "counter_collection.csv"))))
+    agg: dict[str, dict[str, list[float]]] = defaultdict(lambda: defaultdict(list))
+    for r in rows:
+        agg[short_name(r["Kernel_Name"])][r["Counter_Name"]].append(float(r["Counter_Value"]))
+    return agg
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     sub = ap.add_subparsers(dest="mode", required=True)
@@ -92,7 +102,32 @@ def main(argv=None) -> int:
     b.add_argument("--copy-bytes", type=int, required=True)
     b.add_argument("--cmd", required=True)
     b.add_argument("--json")
+    c = sub.add_parser("sq", help="per-kernel averages of SQ counters from one or more --pmc runs")
+    c.add_argument("dirs", nargs="+")
+    c.add_argument("--cmd", required=True)
+    c.add_argument("--kernels", default="", help="comma-separated kernel name prefixes to keep")
     args = ap.parse_args(argv)
+
+    if args.mode == "sq":
+        keep = [k for k in args.kernels.split(",") if k]
+        table: dict[str, dict[str, float]] = defaultdict(dict)
+        names: list[str] = []
+        for d in args.dirs:
+            for k, cs in named_counters(d).items():
+                if keep and not any(k.startswith(p) for p in keep):
+                    continue
+                for cn, vals in cs.items():
+                    table[k][cn] = sum(vals) / len(vals)
+                    if cn not in names:
+                        names.append(cn)
+        print("# SQ counters per dispatch (rocprofv3 --pmc)\n")
+        print(f"Commands:\n\n    {args.cmd}\n")
+        print(f"Source hash of the single-image kernels: {kernel_source_hash()}\n")
+        print("| kernel | " + " | ".join(names) + " |")
+        print("|---|" + "---|" * len(names))
+        for k in sorted(table):
+            print(f"| `{k}` | " + " | ".join(f"{table[k].get(n, float('nan')):.4g}" for n in names) + " |")
+        return 0
 
     if args.mode == "stats":
         st = stats(args.dir)
