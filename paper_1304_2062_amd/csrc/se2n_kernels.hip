@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <cstdlib>
 
 #include "se2n_fft.hpp"
 #include "se2n_internal.hpp"
@@ -381,6 +382,198 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
 }
 
 // ---------------------------------------------------------------------------
+// Propagator precompute on the FP64 matrix cores, for blocks of at most
+// 16 x 16 (even N <= 32): one wavefront per frequency class, both blocks.
+// ---------------------------------------------------------------------------
+// Each block is embedded in a 16 x 16 matrix (the padding is the identity,
+// which every step below keeps, and is never stored).  Matrices live in LDS
+// row-major with a row stride of 17 doubles, so that the 16 lanes reading a
+// column touch 16 distinct bank pairs.
+//   CN:    the left matrix I - tau A / 2 is cyclic tridiagonal; lane c of
+//          block b solves it for the unit vector e_c (Thomas elimination with
+//          a Sherman-Morrison correction for the corners, as the paper's
+//          remark 2 suggests for the time steps themselves), and the
+//          one-step propagator is C = (I - tau A/2)^{-1} (I + tau A/2)
+//          = 2 (I - tau A/2)^{-1} - I.  P = C^n by binary powering.
+//   EXACT: P = e^{T A} by scaling and squaring of a degree-16 Taylor sum.
+// A 16 x 16 x 16 product is four v_mfma_f64_16x16x4 (A[i][k] from lane
+// i + 16 k, B[k][j] from lane j + 16 k; D[i][j] comes back in lane
+// j + 16 (i mod 4), element i div 4); the two blocks' products are issued
+// interleaved.
+typedef double mf64x4 __attribute__((ext_vector_type(4)));
+constexpr int kMS = 17;            // LDS row stride of a 16 x 16 matrix
+constexpr int kMM = 16 * kMS;      // doubles per matrix
+
+// D_b = X_b Y_b for b = 0, nb - 1 (X, Y, D: per-block matrix pointers).
+__device__ __forceinline__ void mm16_pair(const double* X0, const double* Y0, double* D0, const double* X1,
+                                          const double* Y1, double* D1, int nb, int l) {
+    const int i = l & 15, q = l >> 4;
+    mf64x4 c0 = {0.0, 0.0, 0.0, 0.0}, c1 = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int kk = 0; kk < 4; ++kk) {
+        const int k = 4 * kk + q;
+        c0 = __builtin_amdgcn_mfma_f64_16x16x4f64(X0[i * kMS + k], Y0[k * kMS + i], c0, 0, 0, 0);
+        if (nb > 1) c1 = __builtin_amdgcn_mfma_f64_16x16x4f64(X1[i * kMS + k], Y1[k * kMS + i], c1, 0, 0, 0);
+    }
+    __syncthreads();  // every operand read before any result is written (D may be an operand)
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+        D0[(4 * v + q) * kMS + i] = c0[v];
+        if (nb > 1) D1[(4 * v + q) * kMS + i] = c1[v];
+    }
+    __syncthreads();
+}
+
+template <class R>
+__global__ __launch_bounds__(64) void k_precompute_mfma(R* __restrict__ Ptab, int M, int N, int Q, int FS,
+                                                        double beta, double T, int nsteps, int scheme, double scale,
+                                                        int keep_all) {
+    __shared__ double sm[6 * kMM];
+    __shared__ double spot[16];
+    const int l = threadIdx.x;
+    const int h = N / 2;
+    const int lx = blockIdx.x / Q;
+    const int ly = blockIdx.x - lx * Q;
+    const double two_pi = 6.283185307179586476925;
+    const double sx = sin(two_pi * lx / M);
+    const double sy = sin(two_pi * ly / M);
+    // per block b: base / product / scratch matrices, as offsets into sm
+    // (matrix b of a kind at sm + off + b * kMM)
+    int Bo = 0, Ro = 2 * kMM, To = 4 * kMM;
+    // the potential pot_j = M (cos e_j s_x + sin e_j s_y)^2, j < h, once per class
+    if (l < h) {
+        const double e = two_pi * l / N;
+        const double a = cos(e) * sx + sin(e) * sy;
+        spot[l] = (double)M * a * a;
+    }
+    __syncthreads();
+    auto pot = [&](int j) { return spot[j]; };
+    if (scheme == 0) {
+        const double tau = T / nsteps;
+        const double o = -0.5 * tau * beta;  // off-diagonal of I - tau A / 2
+        // lane l < 32: column c = l mod 16 of block b = l / 16
+        if (l < 32) {
+            const int b = l >> 4, c = l & 15;
+            double* Bb = sm + Bo + b * kMM;
+            if (c < h) {
+                const double cr = b == 0 ? o : -o;  // corners: periodic (p) / antiperiodic (q)
+                double d[16], cp[16], w[16], z[16];
+                for (int j = 0; j < h; ++j) d[j] = 1.0 + tau * beta + 0.5 * tau * pot(j);
+                const double g = -d[0];
+                // Thomas factorisation of Tm (d with d_0 - g, d_{h-1} - cr^2/g), solving
+                // Tm w = e_c and Tm z = u, u = (g, 0, .., 0, cr)
+                double prev_cp = 0.0, pw = 0.0, pz = 0.0;
+                for (int j = 0; j < h; ++j) {
+                    double tj = d[j];
+                    if (j == 0) tj -= g;
+                    if (j == h - 1) tj -= cr * cr / g;
+                    const double iden = 1.0 / (tj - (j ? o * prev_cp : 0.0));
+                    cp[j] = o * iden;
+                    w[j] = ((j == c ? 1.0 : 0.0) - (j ? o * pw : 0.0)) * iden;
+                    z[j] = ((j == 0 ? g : 0.0) + (j == h - 1 ? cr : 0.0) - (j ? o * pz : 0.0)) * iden;
+                    prev_cp = cp[j];
+                    pw = w[j];
+                    pz = z[j];
+                }
+                for (int j = h - 2; j >= 0; --j) {
+                    w[j] -= cp[j] * w[j + 1];
+                    z[j] -= cp[j] * z[j + 1];
+                }
+                const double f = (w[0] + (cr / g) * w[h - 1]) / (1.0 + z[0] + (cr / g) * z[h - 1]);
+                for (int i = 0; i < 16; ++i) {
+                    const double inv = i < h ? w[i] - f * z[i] : 0.0;
+                    Bb[i * kMS + c] = i < h ? 2.0 * inv - (i == c ? 1.0 : 0.0) : 0.0;
+                }
+            } else {
+                for (int i = 0; i < 16; ++i) Bb[i * kMS + c] = i == c ? 1.0 : 0.0;
+            }
+        }
+        for (int e = l; e < 2 * 256; e += 64) {
+            const int b = e >> 8, i = (e >> 4) & 15, j = e & 15;
+            sm[Ro + b * kMM + i * kMS + j] = i == j ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        // binary powering: R = C^n (the roles of the three matrices rotate)
+        int n = nsteps;
+        while (n > 0) {
+            if (n & 1) {
+                mm16_pair(sm + Ro, sm + Bo, sm + To, sm + Ro + kMM, sm + Bo + kMM, sm + To + kMM, 2, l);
+                const int t = Ro;
+                Ro = To;
+                To = t;
+            }
+            n >>= 1;
+            if (n) {
+                mm16_pair(sm + Bo, sm + Bo, sm + To, sm + Bo + kMM, sm + Bo + kMM, sm + To + kMM, 2, l);
+                const int t = Bo;
+                Bo = To;
+                To = t;
+            }
+        }
+    } else {
+        // X = T A / 2^s with ||T A||_inf / 2^s <= 1/2 (the larger of the two blocks' norms)
+        double nrm = 0.0;
+        for (int i = 0; i < h; ++i)  // row sums: |diagonal| plus at most 2 beta off the diagonal
+            nrm = fmax(nrm, fabs(-2.0 * beta - pot(i)) + 2.0 * beta);
+        nrm *= T;
+        int sq = 0;
+        while (nrm > 0.5) {
+            nrm *= 0.5;
+            ++sq;
+        }
+        const double xs = T * ldexp(1.0, -sq);
+        for (int e = l; e < 2 * 256; e += 64) {
+            const int b = e >> 8, i = (e >> 4) & 15, j = e & 15;
+            double v = 0.0;
+            if (i < h && j < h) {
+                const double wrap = b == 0 ? 1.0 : -1.0;
+                if (i == j) v = -2.0 * beta - pot(i);
+                if (j == (i + 1) % h) v += (i + 1 < h) ? beta : wrap * beta;
+                if (j == (i + h - 1) % h) v += (i >= 1) ? beta : wrap * beta;
+            }
+            sm[Bo + b * kMM + i * kMS + j] = v * xs;
+            sm[Ro + b * kMM + i * kMS + j] = i == j ? 1.0 : 0.0;
+        }
+        __syncthreads();
+        // Horner: E = I + X (I + X/2 (I + X/3 (... (I + X/16))))
+        for (int k = 16; k >= 1; --k) {
+            mm16_pair(sm + Bo, sm + Ro, sm + To, sm + Bo + kMM, sm + Ro + kMM, sm + To + kMM, 2, l);
+            for (int e = l; e < 2 * 256; e += 64) {
+                const int b = e >> 8, i = (e >> 4) & 15, j = e & 15;
+                sm[Ro + b * kMM + i * kMS + j] = (i == j ? 1.0 : 0.0) + sm[To + b * kMM + i * kMS + j] / k;
+            }
+            __syncthreads();
+        }
+        for (int s2 = 0; s2 < sq; ++s2) {
+            mm16_pair(sm + Ro, sm + Ro, sm + To, sm + Ro + kMM, sm + Ro + kMM, sm + To + kMM, 2, l);
+            const int t = Ro;
+            Ro = To;
+            To = t;
+        }
+    }
+    // packed upper triangles of both blocks, symmetrised, scaled, stored as R
+    const int Eh = h * (h + 1) / 2;
+    const int CS = table_class_stride(N, (int)sizeof(R));
+    R* dst = Ptab + ((size_t)lx * Q + ly) * CS;
+    double pmax = 0.0;
+    for (int e = l; e < 2 * h * h; e += 64) {
+        const int b = e / (h * h), r = e - b * h * h, i = r / h, j = r - (r / h) * h;
+        if (j >= i) {
+            const double* Rb = sm + Ro + b * kMM;
+            const double u = 0.5 * (Rb[i * kMS + j] + Rb[j * kMS + i]);
+            pmax = fmax(pmax, fabs(u));
+            dst[b * Eh + i * h - i * (i - 1) / 2 + (j - i)] = (R)(u * scale);
+        }
+    }
+    for (int off = 32; off >= 1; off >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
+    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * Q * CS);
+    if (l == 0) flags[(size_t)lx * FS + ly] = !keep_all && pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
+    if (ly == Q - 1)
+        for (int j = ly + 1 + l; j < FS; j += 64) flags[(size_t)lx * FS + j] = 0;
+    for (int e = 2 * Eh + l; e < CS; e += 64) dst[e] = R(0);
+}
+
+// ---------------------------------------------------------------------------
 // Launchers (host side, called by the runtime with validated arguments).
 // ---------------------------------------------------------------------------
 template <class R>
@@ -605,6 +798,14 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
     const size_t lds = (size_t)(4 * h * h + h) * sizeof(double);
     // the inverse FFT's 1/M^2, and for even N the 1/2 of the p/q recombination
     const double scale = ((N & 1) ? 1.0 : 0.5) / ((double)M * (double)M);
+    // matrix cores for blocks of 9..16 (N = 18..32, the padded 16 x 16 products
+    // pay off there: N = 32 at 2048^2, 400 steps: 8.6 -> 2 ms; N = 16 is
+    // faster on the scalar path); SE2N_SCALAR_PRECOMPUTE forces the scalar one
+    if (!(N & 1) && h > 8 && h <= 16 && std::getenv("SE2N_SCALAR_PRECOMPUTE") == nullptr) {
+        hipLaunchKernelGGL((k_precompute_mfma<R>), dim3((unsigned)(Q * Q)), dim3(64), 0, st, Ptab, M, N, Q,
+                           flag_stride(M), beta, T, nsteps, scheme, scale, keep_all ? 1 : 0);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q,
                        flag_stride(M), beta,
                        T, nsteps, scheme, scale, keep_all ? 1 : 0);
