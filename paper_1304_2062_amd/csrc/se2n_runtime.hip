@@ -469,14 +469,18 @@ const void* find_propagators(se2n_plan p, double T, double beta, int n_steps, se
 // per-unit costs: the iterated kernel per mode and step, the FP64 propagator
 // build per class (it grows with (N/2)^3 and with the binary powering's
 // log2 n products).  Used only to choose a schedule for an uncached key.
-// (FP32, 2048^2, N = 32: 6.66 ms for 400 iterated steps; 10.5 ms to build
-// the 400-step table.)
+// (FP32, 2048^2, N = 32: 6.66 ms for 400 iterated steps; the 400-step table
+// takes 2.6 ms on the matrix cores (blocks of 9..16), 8.6 ms on the scalar
+// path, whose cost grows with (N/2)^3.)
 double est_iterated_ms(int M, int N, int n) {
     return 8.0e-9 * (double)(M / 2 + 1) * M * n * (N / 32.0);
 }
 double est_precompute_ms(int M, int N, int n) {
     const double h = N / 2.0;
-    return 4.0e-5 * (double)(M / 4 + 1) * (M / 4 + 1) * (h * h * h / 4096.0) * (std::log2((double)n) + 3.0) / 11.6;
+    const double classes = (double)(M / 4 + 1) * (M / 4 + 1);
+    const double products = (std::log2((double)n) + 3.0) / 11.6;
+    if (h > 8 && h <= 16) return 1.0e-5 * classes * products;
+    return 3.3e-5 * classes * (h * h * h / 4096.0) * products;
 }
 
 // Whether this CN diffusion runs the iterated schedule.  AUTO: a cached
