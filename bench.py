@@ -359,6 +359,36 @@ def bench_corrector(args) -> int:
                   (f"  {v['TFLOP_s']:.0f} TFLOP/s" if "TFLOP_s" in v else ""), file=sys.stderr, flush=True)
     ev = corrector.evaluate(net, M=1024, count=args.eval_images, log=lambda m: None)
     print(f"[bench] 1024^2 held-out rel-L2 vs fine FP64: {ev['volume_rel_l2']}", file=sys.stderr, flush=True)
+    ev256 = corrector.evaluate(net, M=256, count=args.eval_images, log=lambda m: None)
+    print(f"[bench] 256^2 held-out rel-L2 vs fine FP64: {ev256['volume_rel_l2']}", file=sys.stderr, flush=True)
+    if args.record_weights:
+        net.save(args.record_weights)  # the weights with both validation records
+    # the corrector against the iterated schedule, whose cost grows with the
+    # step count: 25 coarse steps + network vs 200 plain steps, 1024^2
+    from paper_1304_2062_amd import synth as _synth
+    f1 = torch.from_numpy(_synth.make_image(20000, 1024, "medium").astype(np.float32)).cuda()
+    m1 = torch.from_numpy(_synth.mask_random(27919, 1024, 0.6)).cuda()
+    pit = se2n.Plan(1024, N, torch.float32)
+    pit.set_schedule("iterated")
+    cws = torch.empty(int(se2n._lib.se2n_corrected_workspace_bytes(pit._h, net._h)), dtype=torch.uint8, device="cuda")
+
+    def _ms(fn, k=10):
+        fn()
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for _ in range(k):
+            fn()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t) / k * 1e3
+
+    iterated = {
+        "plain_200_steps_ms": _ms(lambda: pit.inpaint(f1, m1, 2.0, 1.0, 200)),
+        "plain_25_steps_ms": _ms(lambda: pit.inpaint(f1, m1, 2.0, 1.0, 25)),
+        "corrected_25_steps_ms": _ms(lambda: se2n.inpaint_corrected(pit, net, f1, m1, 2.0, 1.0, 25, 200,
+                                                                    max_rel_l2=float("inf"), workspace=cws)),
+    }
+    pit.close()
+    print(f"[bench] iterated schedule at 1024^2: {iterated}", file=sys.stderr, flush=True)
     dom = res["inference"]["kernels"]["cnn_conv2"]
     MFMA_BF16 = 2500.0
     line = {
@@ -370,7 +400,8 @@ def bench_corrector(args) -> int:
         "roofline": {"kernel": "cnn_conv2 (inference)", "bound": "mfma", "achieved": dom["TFLOP_s"],
                      "peak": MFMA_BF16, "unit": "TFLOP/s", "frac": round(dom["TFLOP_s"] / MFMA_BF16, 4),
                      "traffic": None},
-        "corrector": res, "evaluation_1024": ev, "cpu_baseline": None,
+        "corrector": res, "evaluation_1024": ev, "evaluation_256": ev256, "iterated_schedule_1024": iterated,
+        "cpu_baseline": None,
     }
     print(json.dumps(line))
     net.close()
@@ -556,6 +587,7 @@ def main() -> int:
                     help="single: the 2048^2 N=32 inpaint; batch: the 64-image heterogeneous batch; "
                          "corrector: the learned corrector's kernels and accuracy")
     ap.add_argument("--eval-images", type=int, default=4, help="corrector workload: held-out 1024^2 images")
+    ap.add_argument("--record-weights", help="corrector workload: save the weights with the validation records here")
     ap.add_argument("--autotune", action="store_true",
                     help="batch workload: run the autotuner and rewrite the committed schedule table")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
