@@ -31,22 +31,43 @@ __device__ __forceinline__ R lift_max(R f) {
     return f > R(0) ? f : R(0);
 }
 
+// A pixel's N orientations, loaded into registers with every load issued
+// before the first is used (N <= 64; the slices are MM apart, and
+// consecutive threads read consecutive pixels of each slice).
 template <class R>
-__device__ __forceinline__ void scale_pixel(R* __restrict__ vol, long i, long MM, int N, R s) {
-    for (int r = 0; r < N; ++r) vol[(size_t)r * MM + i] *= s;
-}
+struct PixelVec {
+    R v[64];
+    __device__ __forceinline__ void load(const R* __restrict__ vol, long i, long MM, int N) {
+#pragma unroll
+        for (int r = 0; r < 64; ++r)
+            if (r < N) v[r] = vol[(size_t)r * MM + i];
+    }
+    __device__ __forceinline__ R max(int N) const {
+        R h = v[0];
+#pragma unroll
+        for (int r = 1; r < 64; ++r)
+            if (r < N) h = fmax(h, v[r]);
+        return h;
+    }
+    __device__ __forceinline__ void store_scaled(R* __restrict__ vol, long i, long MM, int N, R s) const {
+#pragma unroll
+        for (int r = 0; r < 64; ++r)
+            if (r < N) vol[(size_t)r * MM + i] = v[r] * s;
+    }
+};
 
 // SR: G is the set of known pixels, h_ref = max(f, 0) there.
 template <class R>
-__global__ void k_sr_mix(R* __restrict__ vol, const R* __restrict__ f, const uint8_t* __restrict__ mask, R eps,
-                         long MM, int N) {
+__global__ __launch_bounds__(256) void k_sr_mix(R* __restrict__ vol, const R* __restrict__ f,
+                                                const uint8_t* __restrict__ mask, R eps, long MM, int N) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= MM || mask[i]) return;
-    R h = vol[i];
-    for (int r = 1; r < N; ++r) h = fmax(h, vol[(size_t)r * MM + i]);
+    PixelVec<R> p;
+    p.load(vol, i, MM, N);
+    const R h = p.max(N);
     if (!(h > R(0))) return;
     const R s = (eps * lift_max(f[i]) + (R(1) - eps) * h) / h;
-    scale_pixel(vol, i, MM, N, s);
+    p.store_scaled(vol, i, MM, N, s);
 }
 
 // DR, set-up: join = 0 on known pixels (good from the start), -1 on missing
@@ -64,12 +85,12 @@ __global__ void k_dr_init(int16_t* __restrict__ join, R* __restrict__ href, cons
 // DR: h = max over orientations at every pixel (the growth rule needs the
 // neighbours' values before any pixel is mixed).
 template <class R>
-__global__ void k_dr_max(const R* __restrict__ vol, R* __restrict__ h, long MM, int N) {
+__global__ __launch_bounds__(256) void k_dr_max(const R* __restrict__ vol, R* __restrict__ h, long MM, int N) {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= MM) return;
-    R m = vol[i];
-    for (int r = 1; r < N; ++r) m = fmax(m, vol[(size_t)r * MM + i]);
-    h[i] = m;
+    PixelVec<R> p;
+    p.load(vol, i, MM, N);
+    h[i] = p.max(N);
 }
 
 // DR at mesh point `step`: grow G, then mix.  A pixel q was good before this
@@ -78,7 +99,7 @@ __global__ void k_dr_max(const R* __restrict__ vol, R* __restrict__ h, long MM, 
 // (simultaneous update from G_{i-1}) requires.  The mean is summed in the
 // order (dy, dx) = (-1, -1), (-1, 0), ..., (1, 1).
 template <class R>
-__global__ void k_dr_grow_mix(R* __restrict__ vol, const R* __restrict__ h, int16_t* __restrict__ join,
+__global__ __launch_bounds__(256) void k_dr_grow_mix(R* __restrict__ vol, const R* __restrict__ h, int16_t* __restrict__ join,
                               R* __restrict__ href, R eps, int step, int M, int N) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
@@ -115,7 +136,9 @@ __global__ void k_dr_grow_mix(R* __restrict__ vol, const R* __restrict__ h, int1
     }
     if (!good || !(hp > R(0))) return;
     const R sg = (eps * href[i] + (R(1) - eps) * hp) / hp;
-    scale_pixel(vol, i, MM, N, sg);
+    PixelVec<R> p;
+    p.load(vol, i, MM, N);
+    p.store_scaled(vol, i, MM, N, sg);
 }
 
 }  // namespace
