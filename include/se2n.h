@@ -452,6 +452,14 @@ int se2n_cnn_get_params(se2n_cnn cnn, float *host, int capacity, int *count);
 /* Replace the parameters from host memory (padded entries forced to zero)
  * and reset the Adam state.  Errors: SE2N_EINVAL (count, non-finite). */
 int se2n_cnn_set_params(se2n_cnn cnn, const float *host, int count);
+/* The Adam optimiser's state (first and second moments, 27744 floats each,
+ * and the step counter), for checkpointing and resuming training:
+ * se2n_cnn_get_adam copies it to host memory (m and v may both be NULL to
+ * query *step only; synchronises the device); se2n_cnn_set_adam replaces it
+ * (call after se2n_cnn_set_params, which resets it).  Errors: SE2N_EINVAL
+ * (NULL, count or capacity, non-finite values, v < 0, step < 0), SE2N_EHIP. */
+int se2n_cnn_get_adam(se2n_cnn cnn, float *m, float *v, int capacity, int *step);
+int se2n_cnn_set_adam(se2n_cnn cnn, const float *m, const float *v, int count, int step);
 /* Workspace bytes of se2n_cnn_forward (training = 0) or of the gradient and
  * training calls (training = 1) for `batch` volumes of side M; 0 if invalid. */
 size_t se2n_cnn_workspace_bytes(se2n_cnn cnn, int M, int batch, int training);

@@ -327,6 +327,38 @@ int se2n_cnn_set_params(se2n_cnn c, const float* host, int count) {
     return upload_params(c, p);
 }
 
+int se2n_cnn_get_adam(se2n_cnn c, float* m, float* v, int capacity, int* step) {
+    clear_error();
+    int rc = check_cnn(c);
+    if (rc) return rc;
+    if (!step) return fail(SE2N_EINVAL, "step is NULL");
+    *step = c->t;
+    if (!m && !v) return SE2N_OK;
+    if (!m || !v) return fail(SE2N_EINVAL, "m and v must both be given");
+    if (capacity < kCnnP) return fail(SE2N_EINVAL, "capacity %d < %d parameters", capacity, kCnnP);
+    SE2N_HIP(hipDeviceSynchronize(), "synchronise before reading the Adam state");
+    SE2N_HIP(hipMemcpy(m, c->m, kCnnP * sizeof(float), hipMemcpyDeviceToHost), "Adam first moment download");
+    SE2N_HIP(hipMemcpy(v, c->v, kCnnP * sizeof(float), hipMemcpyDeviceToHost), "Adam second moment download");
+    return SE2N_OK;
+}
+
+int se2n_cnn_set_adam(se2n_cnn c, const float* m, const float* v, int count, int step) {
+    clear_error();
+    int rc = check_cnn(c);
+    if (rc) return rc;
+    if (!m || !v) return fail(SE2N_EINVAL, "m and v must be non-NULL");
+    if (count != kCnnP) return fail(SE2N_EINVAL, "expected %d values (got %d)", kCnnP, count);
+    if (step < 0) return fail(SE2N_EINVAL, "step must be >= 0 (got %d)", step);
+    for (int i = 0; i < kCnnP; ++i)
+        if (!std::isfinite(m[i]) || !std::isfinite(v[i]) || v[i] < 0.f)
+            return fail(SE2N_EINVAL, "Adam moments must be finite, v >= 0");
+    SE2N_HIP(hipDeviceSynchronize(), "synchronise before writing the Adam state");
+    SE2N_HIP(hipMemcpy(c->m, m, kCnnP * sizeof(float), hipMemcpyHostToDevice), "Adam first moment upload");
+    SE2N_HIP(hipMemcpy(c->v, v, kCnnP * sizeof(float), hipMemcpyHostToDevice), "Adam second moment upload");
+    c->t = step;
+    return SE2N_OK;
+}
+
 size_t se2n_cnn_workspace_bytes(se2n_cnn c, int M, int batch, int training) {
     clear_error();
     if (check_cnn(c) || check_shape(c, M, batch)) return 0;

@@ -448,11 +448,13 @@ _lib.se2n_corrected_workspace_bytes.restype = ctypes.c_size_t
 _lib.se2n_inpaint_corrected.argtypes = [_vp, _vp, _vp, _vp, _d, _d, _d, _i, _i, _i, _i, _d, _vp, _vp,
                                         ctypes.POINTER(_i), _vp, _vp]
 _lib.se2n_cnn_set_validation.argtypes = [_vp, _i, _d, _d, _i, _i, _i, _d]
+_lib.se2n_cnn_get_adam.argtypes = [_vp, _FP, _FP, _i, ctypes.POINTER(_i)]
+_lib.se2n_cnn_set_adam.argtypes = [_vp, _FP, _FP, _i, _i]
 _lib.se2n_cnn_get_validation.argtypes = [_vp, _i, _d, _d, _i, _i, _i, ctypes.POINTER(_d)]
 for _name in ("se2n_plan_info", "se2n_cnn_create", "se2n_cnn_destroy", "se2n_cnn_get_params", "se2n_cnn_set_params",
               "se2n_cnn_forward", "se2n_cnn_gradients", "se2n_cnn_adam_step", "se2n_cnn_train_step",
               "se2n_cnn_profile", "se2n_cnn_profile_stats", "se2n_inpaint_corrected", "se2n_cnn_set_validation",
-              "se2n_cnn_get_validation"):
+              "se2n_cnn_get_validation", "se2n_cnn_get_adam", "se2n_cnn_set_adam"):
     getattr(_lib, _name).restype = _i
 
 CNN_PARAMS = 3 * (32 * 32 * 9 + 32)
@@ -562,12 +564,33 @@ class Corrector:
                                             _SCHEMES[scheme], ctypes.byref(r)))
         return None if r.value < 0 else r.value
 
-    def save(self, path: str) -> None:
-        """Parameters and validation records to a NumPy .npz (no pickled objects)."""
+    def adam_state(self):
+        """(m, v, step) of the Adam optimiser, host copies."""
+        import numpy as np
+        t = _i(0)
+        m = np.empty(CNN_PARAMS, dtype=np.float32)
+        v = np.empty(CNN_PARAMS, dtype=np.float32)
+        _check(_lib.se2n_cnn_get_adam(self._h, m.ctypes.data_as(_FP), v.ctypes.data_as(_FP), CNN_PARAMS,
+                                      ctypes.byref(t)))
+        return m, v, t.value
+
+    def set_adam_state(self, m, v, step: int) -> None:
+        import numpy as np
+        m = np.ascontiguousarray(m, dtype=np.float32)
+        v = np.ascontiguousarray(v, dtype=np.float32)
+        _check(_lib.se2n_cnn_set_adam(self._h, m.ctypes.data_as(_FP), v.ctypes.data_as(_FP), int(m.size), int(step)))
+
+    def save(self, path: str, with_optimizer: bool = False) -> None:
+        """Parameters and validation records (and, for a training checkpoint,
+        the Adam state) to a NumPy .npz (no pickled objects)."""
         import numpy as np
         rec = np.array([[k[0], k[1], k[2], k[3], k[4], _SCHEMES[k[5]], v] for k, v in self._validation.items()],
                        dtype=np.float64).reshape(-1, 7)
-        np.savez(path, params=self.params(), N=np.int64(self.N), validation=rec)
+        extra = {}
+        if with_optimizer:
+            m, v, t = self.adam_state()
+            extra = dict(adam_m=m, adam_v=v, adam_step=np.int64(t))
+        np.savez(path, params=self.params(), N=np.int64(self.N), validation=rec, **extra)
 
     def load(self, path: str) -> None:
         import numpy as np
@@ -575,6 +598,8 @@ class Corrector:
             if int(z["N"]) != self.N:
                 raise ValueError(f"{path} holds a network for N={int(z['N'])}, not {self.N}")
             self.set_params(z["params"])
+            if "adam_m" in z.files:
+                self.set_adam_state(z["adam_m"], z["adam_v"], int(z["adam_step"]))
             rec = z["validation"] if "validation" in z.files else np.zeros((0, 7))
         names = {v: k for k, v in _SCHEMES.items()}
         for M, T, beta, nc, nf, sch, err in rec:

@@ -248,3 +248,32 @@ def test_committed_network_gains_on_held_out_images(se2n):
     _say(f"committed network at 256^2: rel-L2 {rel:.3e} vs coarse {base:.3e} ({rel / base:.3f})")
     assert rel < 0.3 * base
     net.close()
+
+
+def test_training_resumes_bit_for_bit_from_a_checkpoint(se2n, tmp_path):
+    """Training checkpoint = parameters + Adam moments + step counter: 3 steps,
+    save, 3 more steps; a fresh network loaded from the checkpoint and taking
+    the same 3 steps ends with identical parameters (training is deterministic)."""
+    torch.manual_seed(0)
+    M, N = 64, 8
+    c = torch.randn((4, N, M, M), device="cuda")
+    f = c + 0.05 * torch.randn_like(c)
+    a = se2n.Corrector(N, seed=3)
+    for _ in range(3):
+        a.train_step(c, f, 1e-3)
+    path = str(tmp_path / "ckpt.npz")
+    a.save(path, with_optimizer=True)
+    for _ in range(3):
+        a.train_step(c, f, 1e-3)
+    b = se2n.Corrector(N, seed=99)
+    b.load(path)
+    assert b.adam_state()[2] == 3
+    for _ in range(3):
+        b.train_step(c, f, 1e-3)
+    torch.cuda.synchronize()
+    assert np.array_equal(a.params(), b.params())
+    ma, va, ta = a.adam_state()
+    mb, vb, tb = b.adam_state()
+    assert ta == tb == 6 and np.array_equal(ma, mb) and np.array_equal(va, vb)
+    a.close()
+    b.close()
