@@ -84,8 +84,11 @@ int se2n_plan_create(se2n_plan *out, int M, int N, se2n_dtype dtype);
 int se2n_plan_destroy(se2n_plan plan);
 
 /* Bytes of device workspace that se2n_diffuse and se2n_inpaint need: the
- * half-spectrum volume [N][M/2+1][M] of complex values plus small scratch.
- * Returns 0 for a NULL plan. */
+ * half-spectrum volume [N][M/2+1][M] of complex values plus small scratch;
+ * for FP32 plans of the sides with compiled passes (512, 1024, 2048) a
+ * second volume of that size, into which the inverse column pass writes its
+ * result in the row-blocked layout that the inverse row pass reads
+ * contiguously.  Returns 0 for a NULL plan. */
 size_t se2n_workspace_bytes(se2n_plan plan);
 
 /* Solver schedule of the Crank-Nicolson diffusion (se2n_diffuse, se2n_inpaint;
@@ -258,10 +261,13 @@ int se2n_restore(se2n_plan plan, const void *f, const uint8_t *mask, double sigm
  * GPU's array, and it keeps the last call's contents: calls that overlap in
  * time on one GPU (other streams, other plans, other threads) race and must
  * be ordered by the caller.  Nothing in the array needs to start at zero.
- * Errors: as se2n_inpaint; SE2N_EINVAL if se2n_workspace_bytes(plan) exceeds
- * SE2N_NOALLOC_MAX_BYTES (e.g. M = 512 fits N <= 60, M = 1024 does not fit
- * N = 16); SE2N_ESTATE if the propagators or the orientation taps are not
- * prepared, or another device is current; SE2N_EHIP. */
+ * When the array is too small for the second (row-blocked) volume of
+ * se2n_workspace_bytes, the inverse passes work in place on the first one
+ * (same result, a slower inverse row pass).
+ * Errors: as se2n_inpaint; SE2N_EINVAL if the workspace without that second
+ * volume exceeds SE2N_NOALLOC_MAX_BYTES (e.g. M = 512 fits N <= 60, M = 1024
+ * does not fit N = 16); SE2N_ESTATE if the propagators or the orientation
+ * taps are not prepared, or another device is current; SE2N_EHIP. */
 #define SE2N_NOALLOC_MAX_BYTES ((size_t)64 << 20)
 int se2n_inpaint_noalloc(se2n_plan plan, const void *f, const uint8_t *mask, double sigma,
                          double T, double beta, int n_steps, se2n_scheme scheme, se2n_proj mode,

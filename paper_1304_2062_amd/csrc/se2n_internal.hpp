@@ -74,6 +74,18 @@ struct GeomCore {
     int tw_full, tw_full_col;
 };
 
+// Row-blocked layout of one slice of the paired half spectrum (the inverse
+// column pass's output for the inverse row pass): rows ky come in blocks of
+// kRowBlk, and within a block the columns kx < M/2 follow one another, each
+// holding its kRowBlk rows contiguously:
+//     element (kx, ky) at (ky / kRowBlk) (M/2) kRowBlk + kx kRowBlk + ky mod kRowBlk.
+// A row-pass tile (8 rows of every column) then reads 64-byte pieces of
+// consecutive 128-byte runs instead of one 64-byte piece per 16-KB column.
+constexpr int kRowBlk = 16;
+__host__ __device__ constexpr long row_blk_index(int kx, int ky, int H) {
+    return (long)(ky / kRowBlk) * H * kRowBlk + (long)kx * kRowBlk + ky % kRowBlk;
+}
+
 __host__ __device__ constexpr void fft_threads_of(int elems, int& threads, int& ept) {
     ept = 8;
     threads = (elems + 7) / 8;
@@ -220,19 +232,28 @@ template <class R>
 hipError_t launch_solve(C2<R>* spec, const R* P, int M, int N, hipStream_t st, bool zfill = true);
 // paired: the inverse column pass already applied the pairing step of the
 // real inverse transform (launch_col_inv_paired)
+// blocked: spec holds the row-blocked layout that launch_col_inv_paired writes
+// into its `blk` buffer (only where row_blocked holds; paired then)
 template <class R>
 hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U* enc, uint8_t* rmap,
                           int M, int nslices, int N, R out_scale, const LaunchGeom& g,
                           int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st,
-                          bool paired = false);
+                          bool paired = false, bool blocked = false);
 // Inverse column FFT of column pairs (kx, M/2-kx) of every slice, followed by
 // the pairing step of the real inverse row transform.
 // negf: the flags of the propagators the solve applied; their modes are then
 // taken as zero and not read (pass it exactly when col_inv_masks holds, and
 // run the solve without zero fill then).
+// blk (only where row_blocked holds): the result goes there, in the
+// row-blocked layout, instead of back into spec.
 template <class R>
 hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g, const FftPlan& planM,
-                                 const C2<R>* tw, hipStream_t st, const uint8_t* negf = nullptr);
+                                 const C2<R>* tw, hipStream_t st, const uint8_t* negf = nullptr,
+                                 C2<R>* blk = nullptr);
+// Whether the inverse column pass for M can hand the inverse row pass its
+// result in the row-blocked layout (the compiled sizes of both passes).
+template <class R>
+bool row_blocked(int M, const LaunchGeom& g);
 // Whether the paired inverse column pass for M leaves out negligible modes
 // cheaply (a compiled tile shape whose rows meet one or two class indices
 // per column), so that the solve need not store their zeros.

@@ -106,7 +106,7 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
                                  neg_two_pi2_sigma2_over_M2, scale, threadIdx.x);
 }
 
-template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED>
+template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED, bool BLK = false>
 __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                           int M_, int nslices, int slices_per_group, int rows_, int xcd_pair, int N,
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
-    row_inv_tile<R, DST, EPT, TWF, MS, PAIRED>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N,
+    row_inv_tile<R, DST, EPT, TWF, MS, PAIRED, BLK>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N,
                                                out_scale, planH, tw, buf, threadIdx.x,
                                                MS ? buf + row_buf_elems(M, rows) : nullptr);
 }
@@ -131,10 +131,12 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
 // Paired inverse column pass: one tile of column pairs per workgroup.
 // TWO: each workgroup transforms slices 2s and 2s + 1 of its pair block (grid
 // N/2 x pair blocks), loading the flags and twiddles once for both.
-template <class R, int EPT, int MS, bool TWO = false>
+// BLK: the result goes to blk in the row-blocked layout.
+template <class R, int EPT, int MS, bool TWO = false, bool BLK = false>
 __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spec, int M_, int pcols_, FftPlan planM,
                                                          const C2<R>* __restrict__ twg,
-                                                         const uint8_t* __restrict__ negf, int FS) {
+                                                         const uint8_t* __restrict__ negf, int FS,
+                                                         C2<R>* __restrict__ blk) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int nthr = MS ? GC.pcol_threads : (int)blockDim.x;
@@ -151,9 +153,9 @@ __global__ __launch_bounds__(1024) void k_col_inv_paired(C2<R>* __restrict__ spe
         tile2 = tile + tps;
     }
     // the tile fetches the twiddles while its flag loads are in flight
-    col_inv_paired_tile<R, EPT, MS, true>(spec, M, pcols_, nthr, tile, planM, tw, buf, threadIdx.x, nslices, negf,
-                                          FS, [&] { load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr); },
-                                          tile2);
+    auto pre = [&] { load_twiddles<R>(tw, twg, M >> 2, false, threadIdx.x, nthr); };
+    col_inv_paired_tile<R, EPT, MS, true, decltype(pre), BLK>(spec, M, pcols_, nthr, tile, planM, tw, buf, threadIdx.x,
+                                                              nslices, negf, FS, pre, tile2, blk);
 }
 
 // ---------------------------------------------------------------------------
@@ -693,8 +695,14 @@ bool col_inv_masks(int M, const LaunchGeom& g) {
 }
 
 template <class R>
+bool row_blocked(int M, const LaunchGeom& g) {
+    return kStatic<R> && col_inv_static<R>(M, g) != 0 && static_size<R>(M, g) == M && M % kRowBlk == 0;
+}
+
+template <class R>
 hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g, const FftPlan& planM,
-                                 const C2<R>* tw, hipStream_t st, const uint8_t* negf) {
+                                 const C2<R>* tw, hipStream_t st, const uint8_t* negf, C2<R>* blk) {
+    if (blk != nullptr && !row_blocked<R>(M, g)) return hipErrorInvalidValue;
     const int P = g.pcols / 2;
     const int npair = M / 4 + 1;
     const size_t lds = tw_bytes<R>(M, false) + (size_t)lds_padded_size(g.pcols * M) * sizeof(C2<R>);
@@ -704,17 +712,24 @@ hipError_t launch_col_inv_paired(C2<R>* spec, int M, int N, const LaunchGeom& g,
     // (compiled for M = 2048, whose tiles are single pairs)
     const bool two = negf != nullptr && ms == 2048 && col_inv_masks<R>(M, g) && npair % P == 0 && N % 2 == 0;
     const dim3 grid((unsigned)((two ? N / 2 : N) * ((npair + P - 1) / P)));
-#define SE2N_PCOL(E, MSV) \
-    hipLaunchKernelGGL((k_col_inv_paired<R, E, MSV>), grid, dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw, \
-                       negf, flag_stride(M))
-    if (two && ms == 2048) hipLaunchKernelGGL((k_col_inv_paired<R, 8, kStatic<R> ? 2048 : 0, true>), grid,
-                                             dim3(g.pcol_threads), lds, st, spec, M, g.pcols, planM, tw, negf,
-                                             flag_stride(M));
-    else if (ms == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0);
-    else if (ms == 1024) SE2N_PCOL(8, kStatic<R> ? 1024 : 0);
-    else if (ms == 512) SE2N_PCOL(8, kStatic<R> ? 512 : 0);
-    else if (g.pcol_ept == 8) SE2N_PCOL(8, 0);
-    else SE2N_PCOL(16, 0);
+#define SE2N_PCOL(E, MSV, TWOV, BLKV)                                                                      \
+    hipLaunchKernelGGL((k_col_inv_paired<R, E, MSV, TWOV, BLKV>), grid, dim3(g.pcol_threads), lds, st, spec, M, \
+                       g.pcols, planM, tw, negf, flag_stride(M), blk)
+    if constexpr (kStatic<R>) {
+        if (blk != nullptr) {
+            if (two) SE2N_PCOL(8, 2048, true, true);
+            else if (ms == 2048) SE2N_PCOL(8, 2048, false, true);
+            else if (ms == 1024) SE2N_PCOL(8, 1024, false, true);
+            else SE2N_PCOL(8, 512, false, true);
+            return hipGetLastError();
+        }
+    }
+    if (two && ms == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0, true, false);
+    else if (ms == 2048) SE2N_PCOL(8, kStatic<R> ? 2048 : 0, false, false);
+    else if (ms == 1024) SE2N_PCOL(8, kStatic<R> ? 1024 : 0, false, false);
+    else if (ms == 512) SE2N_PCOL(8, kStatic<R> ? 512 : 0, false, false);
+    else if (g.pcol_ept == 8) SE2N_PCOL(8, 0, false, false);
+    else SE2N_PCOL(16, 0, false, false);
 #undef SE2N_PCOL
     return hipGetLastError();
 }
@@ -723,7 +738,8 @@ template <class R>
 hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U* enc, uint8_t* rmap,
                           int M, int nslices, int N, R out_scale, const LaunchGeom& g,
                           int slices_per_group, const FftPlan& planH, const C2<R>* tw, hipStream_t st,
-                          bool paired) {
+                          bool paired, bool blocked) {
+    if (blocked && !(paired && dst != DST_ORIENT && row_blocked<R>(M, g))) return hipErrorInvalidValue;
     const int groups = (nslices + slices_per_group - 1) / slices_per_group;
     dim3 grid((M / g.rows) * groups);
     // the kernels compiled for a fixed M run their stages between two row buffers
@@ -740,6 +756,29 @@ hipError_t launch_row_inv(int dst, const C2<R>* spec, R* out, typename Enc<R>::U
                                enc, rmap, M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale, planH,  \
                                tw);                                                                            \
     } while (0)
+#define SE2N_ROWINV_BLK(D, MSV)                                                                                 \
+    hipLaunchKernelGGL((k_row_inv<R, D, kRowEpt<MSV>, kRowTwf<MSV>, MSV, true, true>), grid, dim3(g.row_threads), lds, \
+                       st, spec, out, enc, rmap, M, nslices, slices_per_group, g.rows, g.xcd_pair, N, out_scale,       \
+                       planH, tw)
+    if constexpr (kStatic<R>) {
+        if (blocked) {
+            if (dst == DST_MAX) {
+                if (M == 2048) SE2N_ROWINV_BLK(DST_MAX, 2048);
+                else if (M == 1024) SE2N_ROWINV_BLK(DST_MAX, 1024);
+                else SE2N_ROWINV_BLK(DST_MAX, 512);
+            } else if (dst == DST_SUM) {
+                if (M == 2048) SE2N_ROWINV_BLK(DST_SUM, 2048);
+                else if (M == 1024) SE2N_ROWINV_BLK(DST_SUM, 1024);
+                else SE2N_ROWINV_BLK(DST_SUM, 512);
+            } else {
+                if (M == 2048) SE2N_ROWINV_BLK(DST_VOLUME, 2048);
+                else if (M == 1024) SE2N_ROWINV_BLK(DST_VOLUME, 1024);
+                else SE2N_ROWINV_BLK(DST_VOLUME, 512);
+            }
+            return hipGetLastError();
+        }
+    }
+#undef SE2N_ROWINV_BLK
 #define SE2N_ROWINV_E(D)                                                    \
     if (static_size<R>(M, g) == 2048) SE2N_ROWINV(D, kRowEpt<2048>, kRowTwf<2048>, kStatic<R> ? 2048 : 0);        \
     else if (static_size<R>(M, g) == 1024) SE2N_ROWINV(D, kRowEpt<1024>, kRowTwf<1024>, kStatic<R> ? 1024 : 0);   \
@@ -822,9 +861,10 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
                                              const C2<R>*, double, hipStream_t);                       \
     template hipError_t launch_row_inv<R>(int, const C2<R>*, R*, typename Enc<R>::U*, uint8_t*, int,   \
                                           int, int, R, const LaunchGeom&, int, const FftPlan&,         \
-                                          const C2<R>*, hipStream_t, bool);                            \
+                                          const C2<R>*, hipStream_t, bool, bool);                            \
     template hipError_t launch_col_inv_paired<R>(C2<R>*, int, int, const LaunchGeom&, const FftPlan&,  \
-                                                 const C2<R>*, hipStream_t, const uint8_t*);           \
+                                                 const C2<R>*, hipStream_t, const uint8_t*, C2<R>*);   \
+    template bool row_blocked<R>(int, const LaunchGeom&);                                              \
     template bool col_inv_masks<R>(int, const LaunchGeom&);                                            \
     template hipError_t launch_fill_enc<R>(typename Enc<R>::U*, long, hipStream_t);                    \
     template hipError_t launch_decode_enc<R>(const typename Enc<R>::U*, R*, long, hipStream_t);        \

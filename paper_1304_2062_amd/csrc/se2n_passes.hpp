@@ -18,6 +18,15 @@
 
 namespace se2n {
 
+// Maximum of two values.  FP32 takes the IEEE maximum (one instruction; a
+// NaN propagates); fmax would first quieten its loop-carried operand on
+// every call.
+template <class R>
+__device__ __forceinline__ R vmax(R a, R b) {
+    if constexpr (sizeof(R) == 4) return __builtin_elementwise_maximum(a, b);
+    else return fmax(a, b);
+}
+
 // (q, r) = divmod(tid + i*nthr, d) without a per-element division when nthr
 // is a multiple of d or d of nthr (uniform branches); inv_d = 1/d in float.
 __device__ __forceinline__ void split_index(int tid, int i, int nthr, int d, float inv_d, int& q, int& r) {
@@ -143,31 +152,70 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
             __syncthreads();
             fft_lds<R, false, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
         }
-        // unpack the real transform and write (r, kx, y0..y0+rows) segments
-        const int nout = rows * K;
+        // Unpack the real transform and write (r, kx, y0..y0+rows) segments.
+        // One unit (row, k), k = 0 .. H/2, gives two outputs from a = Z[k] and
+        // b = Z[(H - k) mod H] and one twiddle (w_M^{H-k} = -conj w_M^k):
+        //   s = a + conj b,  u = w_M^k (a - conj b) / 2,
+        //   X[k] = s/2 - i u,  X[H - k] = conj(s/2 + i u)
+        // (k = 0 gives X[0] and X[H]; k = H/2 gives X[H/2] once).  Thread t
+        // takes row t mod rows, so 8 lanes write one 64-byte segment.
         C2<R>* out = spec + (size_t)s * K * M + y0;
+        const int H2 = H >> 1;
         const int rshift = __ffs(rows) - 1;  // rows is a power of two
-        auto unpack = [&](int e) {
-            const int kx = e >> rshift;
-            const int row = e & (rows - 1);
-            const C2<R> z1 = res[lds_pad(row * S + (kx == H ? 0 : kx))];
-            const C2<R> z2 = res[lds_pad(row * S + (kx == 0 ? 0 : H - kx))];
-            const C2<R> ev = cmk<R>(R(0.5) * (z1.x + z2.x), R(0.5) * (z1.y - z2.y));
-            // (z1 - conj z2)/(2i)
-            const C2<R> d = cmk<R>(z1.x - z2.x, z1.y + z2.y);
-            const C2<R> od = cmk<R>(R(0.5) * d.y, -R(0.5) * d.x);
-            out[(size_t)kx * M + row] = cadd<R>(ev, cmul<R>(tw_get<R, TWF>(tw, kx, M4), od));
+        auto pair_out = [&](C2<R> a, C2<R> b, C2<R> w, C2<R>& xk, C2<R>& xh) {
+            const R sx = a.x + b.x, sy = a.y - b.y;
+            const R dx = R(0.5) * (a.x - b.x), dy = R(0.5) * (a.y + b.y);
+            const R ux = w.x * dx - w.y * dy, uy = w.x * dy + w.y * dx;
+            xk = cmk<R>(R(0.5) * sx + uy, R(0.5) * sy - ux);
+            xh = cmk<R>(R(0.5) * sx - uy, R(-0.5) * sy - ux);
         };
-        if constexpr (MS != 0) {
-            // compiled size: a constant count, unrolled so that the LDS reads
-            // of several outputs are in flight together
-            constexpr int NOUT = GC.rows * (MS / 2 + 1);
-            constexpr int FULLIT = NOUT / GC.row_threads;
-#pragma unroll 4
-            for (int it = 0; it < FULLIT; ++it) unpack(tid + it * GC.row_threads);
-            if (tid + FULLIT * GC.row_threads < NOUT) unpack(tid + FULLIT * GC.row_threads);
+        // twiddles w_M^k, k <= M/4, are in the quarter table as well
+        constexpr int KSTEP = MS != 0 ? GC.row_threads / GC.rows : 1;
+        constexpr bool LINU = MS != 0 && GC.row_threads % GC.rows == 0 && KSTEP % kLdsPadPeriod == 0 &&
+                              KSTEP % (1 << SE2N_TW_PAD_SHIFT) == 0;
+        if constexpr (LINU) {
+            // unit it of thread t is (row, k0 + it KSTEP): every LDS position
+            // is the first one plus a constant (KSTEP is a multiple of both
+            // padding periods), and so is every output line
+            constexpr int NU = GC.rows * (MS / 4 + 1);
+            constexpr int FULLIT = NU / GC.row_threads;
+            constexpr int LSTEP = KSTEP + KSTEP / kLdsPadPeriod;
+            constexpr int TSTEP = KSTEP + (KSTEP >> SE2N_TW_PAD_SHIFT);
+            const int row = tid & (GC.rows - 1);
+            const int k0 = tid >> rshift;
+            const C2<R>* pa = res + lds_pad(row * S + k0);
+            const C2<R>* pb = res + lds_pad(row * S + H - k0);
+            const C2<R>* pb0 = k0 == 0 ? pa : pb;  // Z[H] is Z[0]
+            const C2<R>* pw = tw + tw_pos(k0);
+            C2<R>* ok = out + (size_t)k0 * MS + row;
+            C2<R>* oh = out + (size_t)(H - k0) * MS + row;
+            constexpr long LB = (long)KSTEP * MS;  // elements between a thread's output lines
+#pragma unroll
+            for (int it = 0; it < FULLIT; ++it) {
+                C2<R> xk, xh;
+                pair_out(pa[it * LSTEP], it == 0 ? pb0[0] : pb[-it * LSTEP], pw[it * TSTEP], xk, xh);
+                ok[it * LB] = xk;
+                oh[-it * LB] = xh;
+            }
+            if (tid + FULLIT * GC.row_threads < NU) {
+                // k = k0 + FULLIT KSTEP <= H/2; the unit k = H/2 writes X[H/2] once
+                const int k = k0 + FULLIT * KSTEP;
+                C2<R> xk, xh;
+                pair_out(pa[FULLIT * LSTEP], FULLIT == 0 ? pb0[0] : pb[-FULLIT * LSTEP], pw[FULLIT * TSTEP], xk, xh);
+                ok[FULLIT * LB] = xk;
+                if (k != H2) oh[-FULLIT * LB] = xh;
+            }
         } else {
-            for (int e = tid; e < nout; e += nthr) unpack(e);
+            for (int e = tid; e < rows * (H2 + 1); e += nthr) {
+                const int k = e >> rshift;
+                const int row = e & (rows - 1);
+                const C2<R> a = res[lds_pad(row * S + k)];
+                const C2<R> b = res[lds_pad(row * S + (k == 0 ? 0 : H - k))];
+                C2<R> xk, xh;
+                pair_out(a, b, tw[tw_pos(k)], xk, xh);
+                out[(size_t)k * M + row] = xk;
+                if (k != H2) out[(size_t)(H - k) * M + row] = xh;
+            }
         }
         if (pp) {
             // the next first stage fills the buffer nobody reads any more
@@ -346,12 +394,16 @@ __device__ __forceinline__ int fold_class(int k, int M) {
 // tile2 >= 0 (full fast-path tiles only, same pair block as `tile`): the
 // workgroup also transforms that tile, reusing the flags and twiddles and
 // holding its input in registers while the first tile is transformed.
-template <class R, int EPT, int MS, bool HINTS = false, class Pre = NoPre>
+//
+// BLK: the result goes to `blk` (same slice stride as spec) in the
+// row-blocked layout (row_blk_index) instead of back into the tile's columns.
+template <class R, int EPT, int MS, bool HINTS = false, class Pre = NoPre, bool BLK = false>
 __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, int M_, int pcols_, int nthr_,
                                                     int tile, const FftPlan& planM, const C2<R>* tw, C2<R>* buf,
                                                     int tid, int nslices = 0,
                                                     const uint8_t* __restrict__ negf = nullptr, int FS = 0,
-                                                    Pre pre = Pre{}, int tile2 = -1) {
+                                                    Pre pre = Pre{}, int tile2 = -1,
+                                                    C2<R>* __restrict__ blk = nullptr) {
     constexpr GeomCore GC = geom_core<R>(MS ? MS : 16);
     const int M = MS ? MS : M_;
     const int pc = MS ? GC.pcols : pcols_;
@@ -368,6 +420,12 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
     C2<R>* base = spec + (size_t)r * K * M;
     const int r2 = tile2 >= 0 ? tile2 / tps : r;
     C2<R>* const base2 = spec + (size_t)r2 * K * M;
+    // where output (column k, row y) of the current tile goes
+    C2<R>* obase = BLK ? blk + (size_t)r * K * M : base;
+    auto dst = [&](int k, int y) {
+        if constexpr (BLK) return obase + row_blk_index(k, y, H);
+        else return obase + (size_t)k * M + y;
+    };
     const float inv_M = 1.0f / (float)M;
     const int nel = 2 * np * M;
     // LDS column q < np holds column k = p0 + q, column np + q its partner
@@ -433,12 +491,12 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
                     const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
                     const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
                     const C2<R> ta = cmul<R>(wk[q], da);
-                    st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
+                    st(dst(k, y), cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
                     if (k != 0 && kk != k) {
                         const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
                         const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
                         const C2<R> tb = cmul<R>(wkk[q], db);
-                        st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
+                        st(dst(kk, y), cmk<R>(sb.x - tb.y, sb.y + tb.x));
                     }
                 }
                 return;
@@ -454,12 +512,12 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             const C2<R> sa = cmk<R>(a.x + b.x, a.y - b.y);  // a + conj b
             const C2<R> da = cmk<R>(a.x - b.x, a.y + b.y);  // a - conj b
             const C2<R> ta = cmul<R>(cconj<R>(tw_get<R, false>(tw, k, M4)), da);
-            st(base + (size_t)k * M + y, cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
+            st(dst(k, y), cmk<R>(sa.x - ta.y, sa.y + ta.x));  // sa + i ta
             if (k != 0 && kk != k) {
                 const C2<R> sb = cmk<R>(b.x + a.x, b.y - a.y);
                 const C2<R> db = cmk<R>(b.x - a.x, b.y + a.y);
                 const C2<R> tb = cmul<R>(cconj<R>(tw_get<R, false>(tw, kk, M4)), db);
-                st(base + (size_t)kk * M + y, cmk<R>(sb.x - tb.y, sb.y + tb.x));
+                st(dst(kk, y), cmk<R>(sb.x - tb.y, sb.y + tb.x));
             }
         }
     };
@@ -516,6 +574,7 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
                 __syncthreads();  // every thread is done with the first tile's LDS
                 to_lds(v2);
                 base = base2;
+                obase = BLK ? blk + (size_t)r2 * K * M : base2;
                 nts = HINTS && 2 * r2 < nslices;
                 finish();
             }
@@ -548,6 +607,7 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
     if (tile2 >= 0) {  // the same pair block in another slice
         __syncthreads();
         base = base2;
+        obase = BLK ? blk + (size_t)r2 * K * M : base2;
         nts = HINTS && 2 * r2 < nslices;
         load_generic();
         finish();
@@ -609,7 +669,7 @@ __device__ __forceinline__ void col_orient_tile(C2<R>* __restrict__ spec, int M,
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED = false>
+template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED = false, bool BLK = false>
 __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* __restrict__ out,
                                              typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                                              int M_, int rows_, int nthr_, int rb, int s_begin, int s_end, int N,
@@ -654,6 +714,8 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     // thread's first-stage butterfly, rows fastest across lanes so that 8
     // lanes read one 64-byte (slice, column) segment.
     constexpr bool DIRECT = MS != 0 && PAIRED;
+    // the row-blocked input is read by the direct first stage only
+    static_assert(!BLK || DIRECT, "row-blocked input needs the compiled paired pass");
     if constexpr (DIRECT)
         static_assert(static_in_slots(MS / 2, GC.rows, GC.row_threads) <= MAXL, "one register per input");
 #define SE2N_FETCH(SL)                                                                                  \
@@ -662,7 +724,8 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
             _Pragma("unroll") for (int i = 0; i < static_in_slots(MS / 2, GC.rows, GC.row_threads); ++i) { \
                 int t_, n_;                                                                            \
                 if (static_in_pos<MS / 2, GC.rows, GC.row_threads, true>(tid, i, t_, n_))              \
-                    pre[i] = spec[(size_t)(SL) * K * M + (size_t)n_ * M + y0 + t_];                    \
+                    pre[i] = spec[(size_t)(SL) * K * M +                                               \
+                                  (BLK ? row_blk_index(n_, y0 + t_, H) : (long)n_ * M + y0 + t_)];     \
             }                                                                                          \
         } else {                                                                                       \
             const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;            \
@@ -675,6 +738,22 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const bool pp = DIRECT && buf2 != nullptr;
     C2<R>* bx = buf;
     C2<R>* by = buf2;
+    // consume output element i (row, pixel pair n) of slice s
+    auto take = [&](int s, int i, int row, int n, C2<R> z) {
+        if (DST == DST_VOLUME) {
+            *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
+                cmk<R>(z.x * out_scale, z.y * out_scale);
+        } else if (DST == DST_MAX) {
+            acc[i].x = vmax<R>(acc[i].x, z.x);
+            acc[i].y = vmax<R>(acc[i].y, z.y);
+        } else if (DST == DST_SUM) {
+            acc[i].x += z.x;
+            acc[i].y += z.y;
+        } else {  // DST_ORIENT
+            if (s == 0) acc[i] = z;
+            else acc2[i] = z;
+        }
+    };
     // Slices are taken from the last to the first: the pass before this one
     // wrote the high slices last, so they are the ones still held by the
     // memory-side cache when this pass starts.
@@ -715,39 +794,23 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
         __syncthreads();
         }
       }
-        // consume output element i (row, pixel pair n) of this slice
-        auto take = [&](int i, int row, int n, C2<R> z) {
-            if (DST == DST_VOLUME) {
-                *reinterpret_cast<C2<R>*>(out + ((size_t)s * M + y0 + row) * M + 2 * n) =
-                    cmk<R>(z.x * out_scale, z.y * out_scale);
-            } else if (DST == DST_MAX) {
-                acc[i].x = fmax(acc[i].x, z.x);
-                acc[i].y = fmax(acc[i].y, z.y);
-            } else if (DST == DST_SUM) {
-                acc[i].x += z.x;
-                acc[i].y += z.y;
-            } else {  // DST_ORIENT
-                if (s == 0) acc[i] = z;
-                else acc2[i] = z;
-            }
-        };
         if constexpr (DIRECT) {
             // stages 2.. with the last stage's outputs going to the accumulators
             constexpr int R0 = static_radix(MS / 2, 0);
             if (pp) {
                 C2<R>* last = fft_static_out_pp<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
-                    bx, by, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+                    bx, by, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(s, slot, t, n, z); });
                 // the last stage may still be reading `last`: the next first stage fills the other one
                 by = last;
                 bx = (last == buf) ? buf2 : buf;
             } else {
                 fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
-                    buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+                    buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(s, slot, t, n, z); });
             }
         } else if constexpr (MS != 0) {
             // the last stage's outputs go straight to the accumulators
             fft_static_out<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
-                buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(slot, t, n, z); });
+                buf, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(s, slot, t, n, z); });
         } else {
             fft_lds<R, true, EPT, TWF>(buf, planH, rows, S, tw, M4, tid, nthr);
 #pragma unroll
@@ -756,7 +819,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
                 if (e < nel) {
                     int row, n;
                     split_index(tid, i, nthr, H, inv_H, row, n);
-                    take(i, row, n, buf[lds_pad(row * S + n)]);
+                    take(s, i, row, n, buf[lds_pad(row * S + n)]);
                 }
             }
             __syncthreads();

@@ -278,9 +278,14 @@ struct se2n_plan_s {
     size_t cplx_size() const { return 2 * real_size(); }
     int K() const { return M / 2 + 1; }
     size_t spec_bytes() const { return align256((size_t)N * K() * M * cplx_size()); }
+    // second spectrum: the inverse column pass's result in the row-blocked
+    // layout, where the compiled passes support it (row_blocked)
+    bool blk_ok = false;
+    size_t blk_bytes() const { return blk_ok ? spec_bytes() : 0; }
     size_t enc_bytes() const { return align256((size_t)M * M * real_size()); }
     size_t rmap_bytes() const { return align256((size_t)M * M); }
-    size_t workspace() const { return spec_bytes() + enc_bytes() + rmap_bytes(); }
+    size_t workspace() const { return spec_bytes() + blk_bytes() + enc_bytes() + rmap_bytes(); }
+    size_t workspace_unblocked() const { return spec_bytes() + enc_bytes() + rmap_bytes(); }
     // restoration: the above, the real volume, h, h_ref and the join map
     size_t vol_bytes() const { return align256((size_t)N * M * M * real_size()); }
     size_t restore_workspace() const {
@@ -501,32 +506,40 @@ bool use_iterated(se2n_plan p, double T, double beta, int n_steps, se2n_scheme s
 }
 
 template <class R>
-int spectral_middle_iter(se2n_plan p, C2<R>* spec, double T, double beta, int n_steps, hipStream_t st) {
+int spectral_middle_iter(se2n_plan p, C2<R>* spec, C2<R>* blk, double T, double beta, int n_steps, hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
     const long ncols = (long)p->N * p->K();
     SE2N_TIMED(p, "col_fft_fwd", st, launch_col_fft<R>(false, spec, ncols, p->M, p->geom, p->planM, tw, st, nullptr),
                "forward column FFT");
     SE2N_TIMED(p, "solve_iter", st, launch_solve_iter<R>(spec, p->M, p->N, beta, T, n_steps, st),
                "iterated per-mode Crank-Nicolson");
-    SE2N_TIMED(p, "col_fft_inv", st, launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st, nullptr),
+    SE2N_TIMED(p, "col_fft_inv", st,
+               launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st, nullptr, blk),
                "inverse column FFT");
     return SE2N_OK;
 }
 
+// Workspace: the half spectrum, the row-blocked copy the inverse column pass
+// writes for the inverse row pass (blk_ok plans; left out of a workspace of
+// workspace_unblocked() bytes), the max-combining buffer and the map.
 template <class R>
 struct Ws {
     C2<R>* spec;
+    C2<R>* blk;  // null: the inverse passes work in place on spec
     typename Enc<R>::U* enc;
     uint8_t* rmap;
+    const C2<R>* rows() const { return blk ? blk : spec; }  // what the inverse row pass reads
 };
 
 template <class R>
-Ws<R> split_workspace(se2n_plan p, void* ws) {
+Ws<R> split_workspace(se2n_plan p, void* ws, bool use_blk = true) {
     char* b = (char*)ws;
     Ws<R> w;
     w.spec = (C2<R>*)b;
-    w.enc = (typename Enc<R>::U*)(b + p->spec_bytes());
-    w.rmap = (uint8_t*)(b + p->spec_bytes() + p->enc_bytes());
+    const size_t bb = use_blk ? p->blk_bytes() : 0;
+    w.blk = bb ? (C2<R>*)(b + p->spec_bytes()) : nullptr;
+    w.enc = (typename Enc<R>::U*)(b + p->spec_bytes() + bb);
+    w.rmap = (uint8_t*)(b + p->spec_bytes() + bb + p->enc_bytes());
     return w;
 }
 
@@ -571,14 +584,15 @@ int orient_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, uint
     return SE2N_OK;
 }
 
-// spec holds the forward half spectrum of all slices; propagate it in place.
+// spec holds the forward half spectrum of all slices; propagate it (in place,
+// or into blk in the row-blocked layout when blk is set).
 // The forward column pass does not store the modes of negligible classes;
 // the solve writes their zeros unless the inverse column pass takes them as
 // zero without reading them.  The inverse column pass runs on column pairs
 // and leaves the pairing step of the real inverse row transform done (the
 // row pass is then `paired`).
 template <class R>
-int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
+int spectral_middle(se2n_plan p, C2<R>* spec, C2<R>* blk, const void* P, hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
     const long ncols = (long)p->N * p->K();
     const uint8_t* negf = table_flags(P, p->M, p->N, (int)sizeof(R));
@@ -589,13 +603,14 @@ int spectral_middle(se2n_plan p, C2<R>* spec, const void* P, hipStream_t st) {
                "forward column FFT");
     SE2N_TIMED(p, "solve", st, launch_solve<R>(spec, (const R*)P, p->M, p->N, st, !masked), "per-mode solve");
     SE2N_TIMED(p, "col_fft_inv", st,
-               launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st, masked ? negf : nullptr),
+               launch_col_inv_paired<R>(spec, p->M, p->N, p->geom, p->planM, tw, st, masked ? negf : nullptr, blk),
                "inverse column FFT");
     return SE2N_OK;
 }
 
+// spec: the paired spectrum, row-blocked if `blocked`.
 template <class R>
-int project_spec(se2n_plan p, const C2<R>* spec, typename Enc<R>::U* enc, se2n_proj mode, R* out,
+int project_spec(se2n_plan p, const C2<R>* spec, bool blocked, typename Enc<R>::U* enc, se2n_proj mode, R* out,
                  hipStream_t st) {
     const C2<R>* tw = (const C2<R>*)p->tw;
     const int M = p->M, N = p->N;
@@ -603,21 +618,21 @@ int project_spec(se2n_plan p, const C2<R>* spec, typename Enc<R>::U* enc, se2n_p
     if (mode == SE2N_PROJ_MEAN) {
         SE2N_TIMED(p, "row_inv_mean", st,
                    launch_row_inv<R>(DST_SUM, spec, out, nullptr, nullptr, M, N, N, R(1) / (R)N, p->geom, N,
-                                     p->planH, tw, st, true),
+                                     p->planH, tw, st, true, blocked),
                    "inverse row pass (mean)");
         return SE2N_OK;
     }
     if (p->geom.inv_slices >= N) {
         SE2N_TIMED(p, "row_inv_max", st,
                    launch_row_inv<R>(DST_MAX, spec, out, nullptr, nullptr, M, N, N, R(1), p->geom, N, p->planH,
-                                     tw, st, true),
+                                     tw, st, true, blocked),
                    "inverse row pass (max)");
         return SE2N_OK;
     }
     SE2N_TIMED(p, "fill_max", st, launch_fill_enc<R>(enc, MM, st), "clear max buffer");
     SE2N_TIMED(p, "row_inv_max", st,
                launch_row_inv<R>(DST_MAX, spec, nullptr, enc, nullptr, M, N, N, R(1), p->geom,
-                                 p->geom.inv_slices, p->planH, tw, st, true),
+                                 p->geom.inv_slices, p->planH, tw, st, true, blocked),
                "inverse row pass (max)");
     SE2N_TIMED(p, "decode_max", st, launch_decode_enc<R>(enc, out, MM, st), "decode max buffer");
     return SE2N_OK;
@@ -626,13 +641,13 @@ int project_spec(se2n_plan p, const C2<R>* spec, typename Enc<R>::U* enc, se2n_p
 template <class R>
 int inpaint_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, double T, double beta,
                  int n_steps, se2n_scheme scheme, se2n_proj mode, const uint8_t* rmap_in, uint8_t* rmap_out,
-                 R* out, void* workspace, hipStream_t st, const void* P = nullptr) {
+                 R* out, void* workspace, hipStream_t st, const void* P = nullptr, bool use_blk = true) {
     int rc = SE2N_OK;
     const bool iter = !P && use_iterated(p, T, beta, n_steps, scheme);
     if (!P && !iter) rc = get_propagators(p, T, beta, n_steps, scheme, st, &P);
     if (rc) return rc;
     p->last_schedule = iter ? SE2N_SCHEDULE_ITERATED : SE2N_SCHEDULE_PROPAGATOR;
-    Ws<R> w = split_workspace<R>(p, workspace);
+    Ws<R> w = split_workspace<R>(p, workspace, use_blk);
     const uint8_t* rmap = rmap_in;
     if (!rmap_in) {
         uint8_t* dst = rmap_out ? rmap_out : w.rmap;
@@ -647,9 +662,10 @@ int inpaint_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, dou
     SE2N_TIMED(p, "lift_row_fwd", st,
                launch_row_fwd<R>(SRC_LIFT, f, mask, rmap, nullptr, w.spec, p->M, p->N, p->geom, p->planH, tw, st),
                "lift + row FFT");
-    rc = iter ? spectral_middle_iter<R>(p, w.spec, T, beta, n_steps, st) : spectral_middle<R>(p, w.spec, P, st);
+    rc = iter ? spectral_middle_iter<R>(p, w.spec, w.blk, T, beta, n_steps, st)
+              : spectral_middle<R>(p, w.spec, w.blk, P, st);
     if (rc) return rc;
-    return project_spec<R>(p, w.spec, w.enc, mode, out, st);
+    return project_spec<R>(p, w.rows(), w.blk != nullptr, w.enc, mode, out, st);
 }
 
 template <class R>
@@ -666,11 +682,12 @@ int diffuse_impl(se2n_plan p, R* psi, double T, double beta, int n_steps, se2n_s
                launch_row_fwd<R>(SRC_VOLUME, nullptr, nullptr, nullptr, psi, w.spec, p->M, p->N, p->geom,
                                  p->planH, tw, st),
                "row FFT");
-    rc = iter ? spectral_middle_iter<R>(p, w.spec, T, beta, n_steps, st) : spectral_middle<R>(p, w.spec, P, st);
+    rc = iter ? spectral_middle_iter<R>(p, w.spec, w.blk, T, beta, n_steps, st)
+              : spectral_middle<R>(p, w.spec, w.blk, P, st);
     if (rc) return rc;
     SE2N_TIMED(p, "row_inv_volume", st,
-               launch_row_inv<R>(DST_VOLUME, w.spec, psi, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
-                                 p->geom.inv_slices, p->planH, tw, st, true),
+               launch_row_inv<R>(DST_VOLUME, w.rows(), psi, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
+                                 p->geom.inv_slices, p->planH, tw, st, true, w.blk != nullptr),
                "inverse row FFT");
     return SE2N_OK;
 }
@@ -712,8 +729,8 @@ int restore_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, dou
     for (int i = 0; i < n_int; ++i) {
         if (i > 0) {
             SE2N_TIMED(p, "row_inv_volume", st,
-                       launch_row_inv<R>(DST_VOLUME, w.spec, vol, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
-                                         p->geom.inv_slices, p->planH, tw, st, true),
+                       launch_row_inv<R>(DST_VOLUME, w.rows(), vol, nullptr, nullptr, p->M, p->N, p->N, R(1), p->geom,
+                                         p->geom.inv_slices, p->planH, tw, st, true, w.blk != nullptr),
                        "inverse row FFT");
             if (dynamic)
                 SE2N_TIMED(p, "dr_step", st, launch_dr_step<R>(vol, h, join, href, eps, i, p->M, p->N, st),
@@ -725,10 +742,10 @@ int restore_impl(se2n_plan p, const R* f, const uint8_t* mask, double sigma, dou
                                          p->planH, tw, st),
                        "row FFT");
         }
-        rc = spectral_middle<R>(p, w.spec, P, st);
+        rc = spectral_middle<R>(p, w.spec, w.blk, P, st);
         if (rc) return rc;
     }
-    rc = project_spec<R>(p, w.spec, w.enc, mode, out, st);
+    rc = project_spec<R>(p, w.rows(), w.blk != nullptr, w.enc, mode, out, st);
     if (rc) return rc;
     if (join_out) {
         if (dynamic)
@@ -809,6 +826,8 @@ int se2n_plan_create(se2n_plan* out, int M, int N, se2n_dtype dtype) {
         p->geom = make_geom<float>(M, N, num_cu);
         rc = check_geom<float>(p->geom, M);
         if (!rc) rc = make_twiddles<float>(p);
+        // SE2N_NO_ROW_BLOCKS: the inverse passes stay in place (measurement)
+        p->blk_ok = row_blocked<float>(M, p->geom) && std::getenv("SE2N_NO_ROW_BLOCKS") == nullptr;
     } else {
         p->geom = make_geom<double>(M, N, num_cu);
         rc = check_geom<double>(p->geom, M);
@@ -1008,9 +1027,11 @@ int se2n_inpaint_noalloc(se2n_plan p, const void* f, const uint8_t* mask, double
     if (mode != SE2N_PROJ_MAX && mode != SE2N_PROJ_MEAN) return fail(SE2N_EINVAL, "unknown projection %d", (int)mode);
     rc = check_diffusion_params(T, beta, n_steps, scheme);
     if (rc) return rc;
-    if (p->workspace() > (size_t)SE2N_NOALLOC_MAX_BYTES)
+    // the row-blocked copy of the spectrum is used when it fits as well
+    const bool use_blk = p->workspace() <= (size_t)SE2N_NOALLOC_MAX_BYTES;
+    if (p->workspace_unblocked() > (size_t)SE2N_NOALLOC_MAX_BYTES)
         return fail(SE2N_EINVAL, "M=%d, N=%d needs %zu bytes of workspace, above the %zu-byte static scratch", p->M,
-                    p->N, p->workspace(), (size_t)SE2N_NOALLOC_MAX_BYTES);
+                    p->N, p->workspace_unblocked(), (size_t)SE2N_NOALLOC_MAX_BYTES);
     int dev = -1;
     SE2N_HIP(hipGetDevice(&dev), "hipGetDevice");
     if (dev != p->device) return fail(SE2N_ESTATE, "the plan belongs to device %d, device %d is current", p->device, dev);
@@ -1037,10 +1058,10 @@ int se2n_inpaint_noalloc(se2n_plan p, const void* f, const uint8_t* mask, double
     p->prof_hold = true;  // timing events would be created on demand
     if (p->dt == SE2N_F32)
         rc = inpaint_impl<float>(p, (const float*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in, rmap_out,
-                                 (float*)out, ws, st, P);
+                                 (float*)out, ws, st, P, use_blk);
     else
         rc = inpaint_impl<double>(p, (const double*)f, mask, sigma, T, beta, n_steps, scheme, mode, rmap_in,
-                                  rmap_out, (double*)out, ws, st, P);
+                                  rmap_out, (double*)out, ws, st, P, use_blk);
     p->prof_hold = false;
     return rc;
 }
