@@ -155,11 +155,20 @@ __host__ __device__ constexpr int xcd_contiguous(int i, int n) {
     return xcd < rem ? xcd * (per + 1) + slot : rem * (per + 1) + (xcd - rem) * per + slot;
 }
 
-// Propagator table P[lx][ly][element], lx, ly in [0, M/4].  Class (lx, ly)
-// holds the packed upper triangles of its periodic and antiperiodic blocks,
-// (N/2)(N/2 + 1) reals, padded to whole 128-byte lines: the classes a solve
-// workgroup stages form one contiguous run, and a negligible class that is
-// skipped shares no line with a live one.
+// Propagator table: one slot per frequency class (lx, ly), lx, ly in
+// [0, M/4], holding the packed upper triangles of its periodic and
+// antiperiodic blocks, (N/2)(N/2 + 1) reals, padded to whole 128-byte lines
+// (a negligible class that is skipped shares no line with a live one).
+//
+// When 4 | N the classes (lx, ly) and (ly, lx) share a slot: swapping s_kx
+// and s_ky in the potential (cos e_r s_kx + sin e_r s_ky)^2 is the
+// reflection e_r -> pi/2 - e_r of the orientations, r -> N/4 - r (mod N),
+// under which the cyclic Laplacian is invariant, so
+//     P(lx, ly)[r][c] = P(ly, lx)[N/4 - r][N/4 - c]
+// (a quarter turn of the frequency, as in the rotation theorem of the
+// almost-periodic view, up to the mirror s_ky -> -s_ky).  Only lx <= ly is
+// stored, row lx of the upper triangle holding ly = lx .. M/4 contiguously;
+// otherwise the slots are P[lx][ly], row-major.
 // Reals per class: both N/2 x N/2 blocks (even N), or the whole N x N
 // propagator (odd N, where the potential's period N/2 is no symmetry).
 __host__ __device__ constexpr int table_class_entries(int N) {
@@ -183,16 +192,50 @@ __host__ __device__ constexpr bool col_skip_shape(int MS, int NT) {
     return MS != 0 && NT <= MS && MS % NT == 0 && ((MS / 2) % NT == 0 || NT % (MS / 2) == 0);
 }
 
-// The flags of a table at P (the bytes after its propagators).
-__host__ __device__ inline const uint8_t* table_flags(const void* P, int M, int N, int rsize) {
+// Class slots: shared by (lx, ly) and (ly, lx) when 4 | N (above).
+__host__ __device__ constexpr bool table_sym(int N) { return N % 4 == 0; }
+__host__ __device__ constexpr size_t table_slots(int M, int N) {
     const size_t Q = (size_t)(M / 4 + 1);
-    return reinterpret_cast<const uint8_t*>(P) + Q * Q * (size_t)table_class_stride(N, rsize) * (size_t)rsize;
+    return table_sym(N) ? Q * (Q + 1) / 2 : Q * Q;
+}
+// first slot of row a of the upper triangle (classes (a, b), b >= a)
+__host__ __device__ constexpr size_t table_row_start(int a, int Q) { return (size_t)a * Q - (size_t)a * (a - 1) / 2; }
+// slot of class (lx, ly); with 4 | N the class is read through the
+// reflection exactly when lx > ly (table_transposed)
+__host__ __device__ constexpr size_t table_slot(int lx, int ly, int Q, int N) {
+    if (!table_sym(N)) return (size_t)lx * Q + ly;
+    const int a = lx < ly ? lx : ly, b = lx < ly ? ly : lx;
+    return table_row_start(a, Q) + (size_t)(b - a);
+}
+__host__ __device__ constexpr bool table_transposed(int lx, int ly, int N) { return table_sym(N) && lx > ly; }
+// the class stored in slot s (lx <= ly when 4 | N)
+__host__ __device__ inline void table_slot_class(size_t s, int Q, int N, int& lx, int& ly) {
+    if (!table_sym(N)) {
+        lx = (int)(s / Q);
+        ly = (int)(s - (size_t)lx * Q);
+        return;
+    }
+    // row a: table_row_start(a) <= s < table_row_start(a + 1), from the root
+    // of a (2Q + 1 - a) / 2 = s, then corrected for rounding
+    const double b = 2.0 * Q + 1.0;
+    int a = (int)((b - sqrt(b * b - 8.0 * (double)s)) * 0.5);
+    if (a < 0) a = 0;
+    while (a + 1 < Q && table_row_start(a + 1, Q) <= s) ++a;
+    while (a > 0 && table_row_start(a, Q) > s) --a;
+    lx = a;
+    ly = a + (int)(s - table_row_start(a, Q));
+}
+
+// The flags of a table at P (the bytes after its propagators): one byte per
+// class, both orders of a shared slot.
+__host__ __device__ inline const uint8_t* table_flags(const void* P, int M, int N, int rsize) {
+    return reinterpret_cast<const uint8_t*>(P) + table_slots(M, N) * (size_t)table_class_stride(N, rsize) * (size_t)rsize;
 }
 
 // Bytes of a propagator table with its flags (and 64 bytes of slack).
 __host__ __device__ constexpr size_t table_bytes(int M, int N, int rsize) {
     const size_t Q = (size_t)(M / 4 + 1);
-    return Q * Q * (size_t)table_class_stride(N, rsize) * (size_t)rsize + Q * (size_t)flag_stride(M) + 64;
+    return table_slots(M, N) * (size_t)table_class_stride(N, rsize) * (size_t)rsize + Q * (size_t)flag_stride(M) + 64;
 }
 
 // LDS layout of the propagators a solve workgroup stages: class c at c * S,

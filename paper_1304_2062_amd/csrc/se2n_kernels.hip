@@ -221,6 +221,21 @@ __device__ void lds_copy(const double* A, double* B, int n, int tid) {
     __syncthreads();
 }
 
+// Negligible-class flag of a slot's class, under both orders when the slot
+// is shared (the column passes look flags up by (lx, ly) as they come), and
+// the padding of the flag rows the slot ends (by the thread group of one
+// workgroup; tid < 64).
+template <class R>
+__device__ void store_class_flags(R* Ptab, int M, int N, int Q, int FS, int lx, int ly, bool negligible, int tid) {
+    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + table_slots(M, N) * (size_t)table_class_stride(N, (int)sizeof(R)));
+    if (tid == 0) {
+        flags[(size_t)lx * FS + ly] = negligible ? 1 : 0;
+        if (table_sym(N)) flags[(size_t)ly * FS + lx] = negligible ? 1 : 0;
+    }
+    if (ly == Q - 1)  // row padding (every row lx has the slot (lx, Q - 1))
+        for (int j = Q + tid; j < FS; j += 64) flags[(size_t)lx * FS + j] = 0;
+}
+
 template <class R>
 __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, int N, int Q, int FS,
                                                    double beta, double T, int nsteps, int scheme,
@@ -241,8 +256,8 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     double* pot = Ts + hh;
     double* A = scheme == 0 ? Ts : W;  // generator block
     const int tid = threadIdx.x;
-    const int lx = blockIdx.x / Q;
-    const int ly = blockIdx.x - lx * Q;
+    int lx, ly;  // the class of this workgroup's slot
+    table_slot_class(blockIdx.x, Q, N, lx, ly);
     const double two_pi = 6.283185307179586476925;
     const double sx = sin(two_pi * lx / M);
     const double sy = sin(two_pi * ly / M);
@@ -358,7 +373,7 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
             }
         }
         // packed upper triangle, symmetrised, scaled, stored as R
-        R* dst = Ptab + ((size_t)lx * Q + ly) * CS;
+        R* dst = Ptab + (size_t)blockIdx.x * CS;
         for (int idx = tid; idx < hh; idx += 64) {
             const int i = idx / h;
             const int j = idx - i * h;
@@ -375,12 +390,9 @@ __global__ __launch_bounds__(64) void k_precompute(R* __restrict__ Ptab, int M, 
     // entry of both blocks is below 2^-30 (FP32) or 2^-60 (FP64); the solve
     // then writes zeros for the class's modes without reading them
     for (int off = 32; off >= 1; off >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
-    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * Q * CS);
-    if (tid == 0) flags[(size_t)lx * FS + ly] = !keep_all && pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
-    if (ly == Q - 1)  // row padding
-        for (int j = ly + 1 + tid; j < FS; j += 64) flags[(size_t)lx * FS + j] = 0;
+    store_class_flags<R>(Ptab, M, N, Q, FS, lx, ly, !keep_all && pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60), tid);
     // the class's line padding
-    for (int e = E + tid; e < CS; e += 64) Ptab[((size_t)lx * Q + ly) * CS + e] = R(0);
+    for (int e = E + tid; e < CS; e += 64) Ptab[(size_t)blockIdx.x * CS + e] = R(0);
 }
 
 // ---------------------------------------------------------------------------
@@ -434,8 +446,8 @@ __global__ __launch_bounds__(64) void k_precompute_mfma(R* __restrict__ Ptab, in
     __shared__ double spot[16];
     const int l = threadIdx.x;
     const int h = N / 2;
-    const int lx = blockIdx.x / Q;
-    const int ly = blockIdx.x - lx * Q;
+    int lx, ly;  // the class of this workgroup's slot
+    table_slot_class(blockIdx.x, Q, N, lx, ly);
     const double two_pi = 6.283185307179586476925;
     const double sx = sin(two_pi * lx / M);
     const double sy = sin(two_pi * ly / M);
@@ -556,7 +568,7 @@ __global__ __launch_bounds__(64) void k_precompute_mfma(R* __restrict__ Ptab, in
     // packed upper triangles of both blocks, symmetrised, scaled, stored as R
     const int Eh = h * (h + 1) / 2;
     const int CS = table_class_stride(N, (int)sizeof(R));
-    R* dst = Ptab + ((size_t)lx * Q + ly) * CS;
+    R* dst = Ptab + (size_t)blockIdx.x * CS;
     double pmax = 0.0;
     for (int e = l; e < 2 * h * h; e += 64) {
         const int b = e / (h * h), r = e - b * h * h, i = r / h, j = r - (r / h) * h;
@@ -568,10 +580,7 @@ __global__ __launch_bounds__(64) void k_precompute_mfma(R* __restrict__ Ptab, in
         }
     }
     for (int off = 32; off >= 1; off >>= 1) pmax = fmax(pmax, __shfl_xor(pmax, off, 64));
-    uint8_t* flags = reinterpret_cast<uint8_t*>(Ptab + (size_t)Q * Q * CS);
-    if (l == 0) flags[(size_t)lx * FS + ly] = !keep_all && pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60) ? 1 : 0;
-    if (ly == Q - 1)
-        for (int j = ly + 1 + l; j < FS; j += 64) flags[(size_t)lx * FS + j] = 0;
+    store_class_flags<R>(Ptab, M, N, Q, FS, lx, ly, !keep_all && pmax < (sizeof(R) == 4 ? 0x1p-30 : 0x1p-60), l);
     for (int e = 2 * Eh + l; e < CS; e += 64) dst[e] = R(0);
 }
 
@@ -833,6 +842,7 @@ template <class R>
 hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int nsteps, int scheme,
                              hipStream_t st, bool keep_all) {
     const int Q = M / 4 + 1;
+    const size_t slots = table_slots(M, N);  // one workgroup per stored class
     const int h = (N & 1) ? N : N / 2;
     const size_t lds = (size_t)(4 * h * h + h) * sizeof(double);
     // the inverse FFT's 1/M^2, and for even N the 1/2 of the p/q recombination
@@ -841,11 +851,11 @@ hipError_t launch_precompute(R* Ptab, int M, int N, double beta, double T, int n
     // pay off there: N = 32 at 2048^2, 400 steps: 8.6 -> 2 ms; N = 16 is
     // faster on the scalar path); SE2N_SCALAR_PRECOMPUTE forces the scalar one
     if (!(N & 1) && h > 8 && h <= 16 && std::getenv("SE2N_SCALAR_PRECOMPUTE") == nullptr) {
-        hipLaunchKernelGGL((k_precompute_mfma<R>), dim3((unsigned)(Q * Q)), dim3(64), 0, st, Ptab, M, N, Q,
+        hipLaunchKernelGGL((k_precompute_mfma<R>), dim3((unsigned)slots), dim3(64), 0, st, Ptab, M, N, Q,
                            flag_stride(M), beta, T, nsteps, scheme, scale, keep_all ? 1 : 0);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)(Q * Q)), dim3(64), lds, st, Ptab, M, N, Q,
+    hipLaunchKernelGGL((k_precompute<R>), dim3((unsigned)slots), dim3(64), lds, st, Ptab, M, N, Q,
                        flag_stride(M), beta,
                        T, nsteps, scheme, scale, keep_all ? 1 : 0);
     return hipGetLastError();

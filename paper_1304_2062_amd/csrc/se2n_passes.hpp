@@ -391,9 +391,10 @@ __device__ __forceinline__ int fold_class(int k, int M) {
 // of negligible classes are taken as zero and not read: the solve then need
 // not store them, and lines that hold no live mode are never fetched.
 //
-// tile2 >= 0 (full fast-path tiles only, same pair block as `tile`): the
-// workgroup also transforms that tile, reusing the flags and twiddles and
-// holding its input in registers while the first tile is transformed.
+// tile2 >= 0 (same pair block as `tile`; the caller requests it only where
+// every tile takes the flag-reading fast path): the workgroup also
+// transforms that tile, reusing the flags and twiddles and holding its input
+// in registers while the first tile is transformed.
 //
 // BLK: the result goes to `blk` (same slice stride as spec) in the
 // row-blocked layout (row_blk_index) instead of back into the tile's columns.
@@ -601,17 +602,10 @@ __device__ __forceinline__ void col_inv_paired_tile(C2<R>* __restrict__ spec, in
             }
         }
     };
+    // (a second tile is only ever requested for full fast-path tiles, above)
     pre();
     load_generic();
     finish();
-    if (tile2 >= 0) {  // the same pair block in another slice
-        __syncthreads();
-        base = base2;
-        obase = BLK ? blk + (size_t)r2 * K * M : base2;
-        nts = HINTS && 2 * r2 < nslices;
-        load_generic();
-        finish();
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -906,6 +900,8 @@ __device__ __forceinline__ double swap_pair(double v) {
 
 // zfill: store the zeros of negligible classes (off when the inverse column
 // pass takes them as zero without reading them).
+// With 4 | N the classes with lx > ly of the block use the slot of (ly, lx),
+// read through its reflection (table_slot).
 template <class R, int N, int CLS>
 __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __restrict__ P, int M, int Q,
                                            int FS, int lx, int ly0, R* Ps, int tid, bool zfill = true) {
@@ -929,7 +925,7 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
     uint64_t negm;
     {
         const uint8_t* __restrict__ flags =
-            reinterpret_cast<const uint8_t*>(P + (size_t)Q * Q * CS) + (size_t)lx * FS + ly0;
+            reinterpret_cast<const uint8_t*>(P + table_slots(M, N) * CS) + (size_t)lx * FS + ly0;
         const int l = tid & 63;
         negm = __ballot(l >= ncls || flags[l] != 0);
     }
@@ -948,7 +944,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         constexpr int CH = CLS * CPC;
         constexpr int NST = (CH + NT - 1) / NT;
         constexpr int BATCH = NST < 8 ? NST : 8;  // loads in flight per thread
-        const R* __restrict__ src = P + ((size_t)lx * Q + ly0) * CS;
+        // the block's slots: one contiguous run, except where classes share
+        // the slots of (ly, lx) (one slot per class, in rows ly < lx of the
+        // triangle)
         for (int k0 = 0; k0 < NST; k0 += BATCH) {
             vec_t v[BATCH];
 #pragma unroll
@@ -958,8 +956,11 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
                 // non-temporal: each propagator is read once per call, and
                 // keeping the table out of the caches leaves them to the
                 // spectrum, which the next pass reads again
-                if (i < CH && !((negm >> (i / CPC)) & 1))
-                    v[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(src + (size_t)i * VEC));
+                if (i < CH && !((negm >> (i / CPC)) & 1)) {
+                    const int c = i / CPC;
+                    const R* a = P + table_slot(lx, ly0 + c, Q, N) * CS + (size_t)(i - c * CPC) * VEC;
+                    v[k] = __builtin_nontemporal_load(reinterpret_cast<const vec_t*>(a));
+                }
             }
 #pragma unroll
             for (int k = 0; k < BATCH; ++k) {
@@ -980,13 +981,14 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
     const int odd = tid & 1;
     // A wavefront holds 32 pairs; with CLS >= 32 they all belong to one member,
     // so the member, its column kx and its orientation mirroring are uniform
-    // across the wavefront and the plane addresses live in scalar registers.
+    // across the wavefront (the slot reflection, per class, is not).
     constexpr bool UNIFORM = CLS >= 32;
     // The mode of lane pair `pair`: its class c, row ky and column, whether it
-    // exists (live), is read, and is mirrored in orientation (perm).
+    // exists (live), is read, is mirrored in orientation (perm) and shares
+    // the slot of its transposed class (tr).
     struct Mode {
         int c, ky;
-        bool live, read, perm;
+        bool live, read, perm, tr;
         C2<R>* colbase;
     };
     auto mode_of = [&](int pair) {
@@ -1008,8 +1010,18 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
         md.ky = live ? ky : 0;  // harmless in-range address; nothing is stored
         // s_ky < 0 exactly for the live members b = 2, 3 (ky in (M/2, M))
         md.perm = b >= 2;
+        // a class sharing the slot of (ly, lx) is read through its reflection
+        md.tr = table_transposed(lx, ly, N);
         md.colbase = spec + (size_t)kx * M;
         return md;
+    };
+    // Orientation plane of logical index r: the mirror r -> -r for s_ky < 0,
+    // and for a class read through its slot's reflection (tr) that
+    // reflection composed with it, r -> N/4 - r, or r -> r - N/4 under the
+    // mirror.
+    auto plane_of = [&](bool perm, bool tr, int r) {
+        if (table_sym(N) && tr) return perm ? (r + 3 * (N / 4)) % N : (N / 4 + N - r) % N;
+        return perm ? (r == 0 ? 0 : N - r) : r;
     };
     // this lane's half of the orientation vector (lanes of dead or negligible
     // modes read nothing and hold zeros)
@@ -1017,9 +1029,9 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
 #pragma unroll
         for (int j = 0; j < h; ++j) {
             const int r0 = j, r1 = j + h;
-            const int a0 = md.perm ? (r0 == 0 ? 0 : N - r0) : r0;
-            const int a1 = md.perm ? N - r1 : r1;
-            const C2<R>* pl0 = md.colbase + (size_t)a0 * plane;  // wave-uniform with UNIFORM
+            const int a0 = plane_of(md.perm, md.tr, r0);
+            const int a1 = plane_of(md.perm, md.tr, r1);
+            const C2<R>* pl0 = md.colbase + (size_t)a0 * plane;
             const C2<R>* pl1 = md.colbase + (size_t)a1 * plane;
             C2<R> v = cmk<R>(R(0), R(0));
             if (md.read) v = odd ? pl1[md.ky] : pl0[md.ky];
@@ -1069,8 +1081,8 @@ __device__ __forceinline__ void solve_tile(C2<R>* __restrict__ spec, const R* __
 #pragma unroll
             for (int j = 0; j < h; ++j) {
                 const int r0 = j, r1 = j + h;
-                const int a0 = md.perm ? (r0 == 0 ? 0 : N - r0) : r0;
-                const int a1 = md.perm ? N - r1 : r1;
+                const int a0 = plane_of(md.perm, md.tr, r0);
+                const int a1 = plane_of(md.perm, md.tr, r1);
                 C2<R>* pl = md.colbase + (size_t)(odd ? a1 : a0) * plane;
                 pl[md.ky] = y[j];
             }

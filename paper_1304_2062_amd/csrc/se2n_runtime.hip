@@ -482,7 +482,7 @@ double est_iterated_ms(int M, int N, int n) {
 }
 double est_precompute_ms(int M, int N, int n) {
     const double h = N / 2.0;
-    const double classes = (double)(M / 4 + 1) * (M / 4 + 1);
+    const double classes = (double)table_slots(M, N);  // one build per stored class
     const double products = (std::log2((double)n) + 3.0) / 11.6;
     if (h > 8 && h <= 16) return 1.0e-5 * classes * products;
     return 3.3e-5 * classes * (h * h * h / 4096.0) * products;

@@ -73,7 +73,8 @@ __global__ __launch_bounds__(512) void k_solve_odd(C2<R>* __restrict__ spec, con
     const int ky = b == 0 ? ly : (b == 1 ? H - ly : (b == 2 ? H + ly : M - ly));
     const size_t plane = (size_t)(H + 1) * M;
     C2<R>* col = spec + (size_t)kx * M + (live ? ky : 0);
-    const uint8_t* flags = reinterpret_cast<const uint8_t*>(P + (size_t)Q * Q * table_class_stride(N, sizeof(R)));
+    // (odd N: no shared slots, slot lx Q + ly)
+    const uint8_t* flags = reinterpret_cast<const uint8_t*>(P + table_slots(M, N) * table_class_stride(N, sizeof(R)));
     if (flags[(size_t)lx * FS + ly]) {
         if (live && zfill) col[(size_t)r * plane] = cmk<R>(R(0), R(0));
         return;
@@ -81,7 +82,7 @@ __global__ __launch_bounds__(512) void k_solve_odd(C2<R>* __restrict__ spec, con
     if (live) xs[m * N + r] = col[(size_t)r * plane];
     __syncthreads();
     if (!live) return;
-    const R* Pc = P + ((size_t)lx * Q + ly) * table_class_stride(N, sizeof(R));
+    const R* Pc = P + table_slot(lx, ly, Q, N) * table_class_stride(N, sizeof(R));
     const bool perm = b >= 2;
     const int rr = perm ? (N - r) % N : r;
     C2<R> acc = cmk<R>(R(0), R(0));
