@@ -95,3 +95,36 @@ def test_semi_discrete_tends_to_the_continuum_at_second_order():
         errs.append(np.abs(semi - TH.theta_continuum(lam, mu, alpha, g, T, e)).max())
     ratios = [errs[i] / errs[i + 1] for i in range(3)]
     assert all(3.6 < r < 4.4 for r in ratios), (errs, ratios)
+
+
+@pytest.mark.parametrize("N", [8, 12, 32])
+def test_swapped_frequency_is_the_reflected_orientation(N):
+    """Swapping kx and ky is the reflection e_r -> pi/2 - e_r of the
+    orientations, r -> N/4 - r (mod N), when 4 | N: started from the reflected
+    vector, the mode (l, k) evolves into the reflected evolution of (k, l).
+    (One propagator thus serves both frequency classes.)  Checked on the
+    oracle's Crank-Nicolson steps and exact exponential, mirrored frequencies
+    (ky > M/2) included.  For N = 2 mod 4 no orientation index is N/4 and the
+    relation has no grid form (next test)."""
+    M, beta, T = 64, 1.3, 0.5
+    rng = np.random.default_rng(N)
+    refl = (N // 4 - np.arange(N)) % N
+    for k, l in ((3, 11), (1, 30), (7, 64 - 5), (0, 9)):
+        a0 = rng.normal(size=N) + 1j * rng.normal(size=N)
+        for evolve in (lambda X, kk, ll: O.diffuse_modes_cn(X, M, [kk], [ll], beta, T, 40),
+                       lambda X, kk, ll: O.diffuse_modes_exact(X, M, [kk], [ll], beta, T)):
+            A = evolve(a0[None, :], k, l)[0]
+            B = evolve(a0[refl][None, :], l, k)[0]
+            np.testing.assert_allclose(B, A[refl], rtol=0, atol=1e-12 * np.abs(A).max())
+
+
+def test_swapped_frequency_has_no_reflection_when_4_does_not_divide_N():
+    M, N, beta, T = 64, 10, 1.3, 0.5
+    a0 = np.random.default_rng(1).normal(size=N).astype(complex)
+    A = O.diffuse_modes_exact(a0[None, :], M, [3], [11], beta, T)[0]
+    B = O.diffuse_modes_exact(a0[None, :], M, [11], [3], beta, T)[0]
+    # the potentials of the two classes are not orientation permutations of each other
+    pa = np.sort(O.mode_potential(M, N, np.array([3]), np.array([11])).ravel())
+    pb = np.sort(O.mode_potential(M, N, np.array([11]), np.array([3])).ravel())
+    assert np.abs(pa - pb).max() > 1e-3
+    assert np.abs(A - B).max() > 1e-6
