@@ -13,7 +13,12 @@ of the semi-discrete model; FP64 plans, se2n_diffuse on plane-wave volumes).
 * Sec. "The weighting of the metric": with beta_N = alpha (N / 2 pi)^2 the
   semi-discrete system tends to the continuous-angle equation
   (contdif-weight) as N grows, at second order in 1/N.
-The references come from oracle/theory_oracle.py (pinned by closed forms).
+* The semi-discrete heat kernel two ways (equations (Discrker) and (new2),
+  identical by the appendix's proof): on the grid, the diffusion of a unit
+  mass equals the trace form over the rotation orbits that the orientations
+  and the square grid share.
+The references come from oracle/theory_oracle.py (pinned by closed forms and
+by the plain oracle diffusion).
 """
 import numpy as np
 import pytest
@@ -95,3 +100,42 @@ def test_semi_discrete_tends_to_the_continuous_angle_limit():
     print(f"  errors {errs}, ratios {ratios}", flush=True)
     assert all(3.5 < r < 4.5 for r in ratios)
     assert errs[-1] < 2e-3
+
+
+@pytest.mark.parametrize("M,N,dtype,scheme,n", [(64, 16, torch.float64, "exact", 1), (48, 30, torch.float64, "cn", 25),
+                                                (512, 32, torch.float32, "cn", 40)])
+def test_gpu_heat_kernel_is_the_trace_form(M, N, dtype, scheme, n):
+    """(Discrker) = (new2) on the grid, through the library: the GPU's
+    diffusion of a unit mass at pixel (0, 0), orientation 0 (the grid form
+    of (new2)) against the trace form over rotation orbits of the theory
+    oracle (quarter turns for N = 16 and 32, the half turn for N = 30).
+    FP64 everywhere at small sides; FP32 at 512^2 (the compiled passes with
+    the row-blocked layout) on 256 sampled pixels of every eighth
+    orientation, to the FP32 tolerance."""
+    beta, T = 1.2, 0.3
+    print(f"theory: heat kernel {M}^2 N={N} {dtype} {scheme}", flush=True)
+    psi = torch.zeros((N, M, M), dtype=dtype, device=DEV)
+    psi[0, 0, 0] = 1.0
+    plan = se2n.Plan(M, N, dtype)
+    plan.diffuse(psi, T, beta, n, scheme)
+    torch.cuda.synchronize()
+    got = psi.cpu().numpy()
+    plan.close()
+    # errors are measured against the largest value of the whole kernel
+    # (orientation 0 near the source): the rounding of the transforms is
+    # relative to it, not to the far orientations' much smaller values
+    if M <= 64:
+        want = TH.heat_kernel_trace_form(M, N, beta, T, list(range(N)), scheme, n)
+        assert np.abs(want.imag).max() < 1e-13 * np.abs(want.real).max()
+        np.testing.assert_allclose(got, want.real, rtol=0, atol=1e-12 * np.abs(want.real).max())
+        return
+    rng = np.random.default_rng(4)
+    ys = np.concatenate([np.arange(8), rng.integers(0, M, 248)])  # near the source and elsewhere
+    xs = np.concatenate([np.arange(8), rng.integers(0, M, 248)])
+    rs = list(range(0, N, 8))
+    want = TH.heat_kernel_trace_form(M, N, beta, T, rs, scheme, n, pixels=(ys, xs)).real
+    scale = np.abs(want).max()
+    for i, r in enumerate(rs):
+        err = np.abs(got[r][ys, xs] - want[i]).max() / scale
+        print(f"  r={r}: max error {err:.2e} of the kernel's largest sampled value", flush=True)
+        assert err < 2e-5

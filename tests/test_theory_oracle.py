@@ -128,3 +128,57 @@ def test_swapped_frequency_has_no_reflection_when_4_does_not_divide_N():
     pb = np.sort(O.mode_potential(M, N, np.array([11]), np.array([3])).ravel())
     assert np.abs(pa - pb).max() > 1e-3
     assert np.abs(A - B).max() > 1e-6
+
+
+@pytest.mark.parametrize("M,N,scheme", [(16, 8, "exact"), (24, 12, "cn"), (16, 10, "exact"), (12, 7, "cn")])
+def test_trace_form_of_the_heat_kernel_is_the_inverse_fft(M, N, scheme):
+    """(Discrker) against (new2) on the grid: the trace form over rotation
+    orbits (quarter turns for 4 | N, the half turn for N = 2 mod 4, nothing
+    for odd N) equals the plain diffusion of a unit mass at pixel (0, 0),
+    orientation 0, to rounding -- and is real."""
+    beta, T, n = 1.7, 0.35, 12
+    psi = np.zeros((N, M, M))
+    psi[0, 0, 0] = 1.0
+    ref = O.diffuse(psi, T, beta, n, scheme)
+    for r in (0, 1, N // 2, N - 1):
+        got = TH.heat_kernel_trace_form(M, N, beta, T, r, scheme, n)
+        assert np.abs(got.imag).max() < 1e-14
+        np.testing.assert_allclose(got.real, ref[r], rtol=0, atol=1e-14)
+
+
+def test_trace_form_needs_the_rotation_of_the_orientations():
+    """Pairing each orbit's rotated pixels with the unshifted entry P[r, 0]
+    (dropping the shift S^n of the proof) gives a different field: the pin
+    above would catch a wrong orientation index in the trace form."""
+    M, N, beta, T, r = 16, 8, 1.7, 0.35, 1
+    psi = np.zeros((N, M, M))
+    psi[0, 0, 0] = 1.0
+    ref = O.diffuse(psi, T, beta, 0, "exact")[r]
+    good = TH.heat_kernel_trace_form(M, N, beta, T, r).real
+    np.testing.assert_allclose(good, ref, atol=1e-14)
+    # the same orbit representatives and weights, no orientation shift
+    g, seen, reps, w = 4, np.zeros((M, M), bool), [], []
+    for k in range(M):
+        for l in range(M):
+            if seen[k, l]:
+                continue
+            orb, a, b = {(k, l)}, k, l
+            for _ in range(g - 1):
+                a, b = (-b) % M, a % M
+                orb.add((a, b))
+            for (a, b) in orb:
+                seen[a, b] = True
+            reps.append((k, l))
+            w.append(len(orb) / g)
+    ks, ls = np.array(reps).T
+    X = np.zeros((ks.size, N))
+    X[:, 0] = 1.0
+    coef = np.array(w) * O.diffuse_modes_exact(X, M, ks, ls, beta, T)[:, r]
+    ys, xs = np.mgrid[0:M, 0:M]
+    wrong = np.zeros((M, M), dtype=complex)
+    xq, yq = xs, ys
+    for _ in range(g):
+        wrong += np.tensordot(coef, np.exp(2j * np.pi * (ks[:, None, None] * xq + ls[:, None, None] * yq) / M), 1)
+        xq, yq = (-yq) % M, xq % M
+    wrong = wrong.real / (M * M)
+    assert np.abs(wrong - ref).max() > 1e-3 * np.abs(ref).max()
