@@ -557,13 +557,101 @@ __device__ __forceinline__ void fft_stage_static_out(C2<R>* buf, const C2<R>* tw
 }
 
 // ---------------------------------------------------------------------------
+// Twiddles kept in registers.  In a fixed-size transform a thread runs the
+// same butterflies, hence needs the same twiddles, for every batch it
+// transforms; a pass that walks many batches with fixed threads (the row
+// passes walk the orientation slices) reads the base powers w^e, w^{2e}
+// (and w^{4e} for radix 8) of stages 1 .. SLIM - 1 from the LDS table once
+// and forms the other powers as apply_twiddles does, with the same values
+// and products (bit-identical results).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int static_nstages(int L) {
+    int s = 0;
+    while (static_radix(L, s) != 0) ++s;
+    return s;
+}
+__host__ __device__ constexpr int static_ns(int L, int S) {
+    int ns = 1;
+    for (int s = 0; s < S; ++s) ns *= static_radix(L, s);
+    return ns;
+}
+
+struct NoTw {
+    static constexpr int SLIM = 0;
+};
+
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int NTHR, int M, int SLIM_>
+struct StageTw {
+    static constexpr int SLIM = SLIM_;
+    static constexpr int MB = 4;  // butterflies of a thread in one stage, at most
+    C2<R> w[SLIM > 1 ? SLIM : 1][MB][3];
+    template <int S>
+    __device__ __forceinline__ void load_from(const C2<R>* twq, int tid) {
+        if constexpr (S < SLIM && static_radix(L, S) != 0) {
+            constexpr int RADIX = static_radix(L, S);
+            constexpr int NS = static_ns(L, S);
+            constexpr int NB = L / RADIX;
+            constexpr int TOTAL = NB * NBATCH;
+            constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
+            static_assert(MAXB <= MB, "butterflies per thread and stage");
+            constexpr int TWSTEP = M / (NS * RADIX);
+            auto rd = [&](int m) {
+                C2<R> v = tw_get<R, TWFULL>(twq, m, M / 4);
+                if (INV) v.y = -v.y;
+                return v;
+            };
+#pragma unroll
+            for (int i = 0; i < MAXB; ++i) {
+                const int bf = tid + i * NTHR;
+                const int j = bf - (bf / NB) * NB;
+                const int e = (j - (j / NS) * NS) * TWSTEP;  // k TWSTEP, k = j mod NS
+                w[S][i][0] = rd(e);
+                if constexpr (RADIX >= 3) w[S][i][1] = rd(2 * e);
+                if constexpr (RADIX == 8) w[S][i][2] = rd(4 * e);
+            }
+            load_from<S + 1>(twq, tid);
+        }
+    }
+    // every thread of the workgroup, after the table is in LDS
+    __device__ __forceinline__ void load(const C2<R>* twq, int tid) { load_from<1>(twq, tid); }
+};
+
+// apply_twiddles with the base powers wb (already conjugated for the inverse)
+template <class R, int RADIX>
+__device__ __forceinline__ void apply_twiddles_base(C2<R>* v, const C2<R>* wb) {
+    if constexpr (RADIX == 2) {
+        v[1] = cmul<R>(v[1], wb[0]);
+    } else if constexpr (RADIX == 3) {
+        v[1] = cmul<R>(v[1], wb[0]);
+        v[2] = cmul<R>(v[2], wb[1]);
+    } else if constexpr (RADIX == 4) {
+        const C2<R> w1 = wb[0], w2 = wb[1];
+        v[1] = cmul<R>(v[1], w1);
+        v[2] = cmul<R>(v[2], w2);
+        v[3] = cmul<R>(v[3], cmul<R>(w1, w2));
+    } else {
+        const C2<R> w1 = wb[0], w2 = wb[1], w4 = wb[2];
+        const C2<R> w3 = cmul<R>(w1, w2);
+        v[1] = cmul<R>(v[1], w1);
+        v[2] = cmul<R>(v[2], w2);
+        v[3] = cmul<R>(v[3], w3);
+        v[4] = cmul<R>(v[4], w4);
+        v[5] = cmul<R>(v[5], cmul<R>(w1, w4));
+        v[6] = cmul<R>(v[6], cmul<R>(w2, w4));
+        v[7] = cmul<R>(v[7], cmul<R>(w3, w4));
+    }
+}
+
+// ---------------------------------------------------------------------------
 // The same fixed-size stages between two LDS buffers.  A stage reads `a` and
 // writes `b`, so no thread can overwrite what another still has to read:
 // one barrier per stage instead of two, and each thread computes a butterfly
 // as soon as its own loads arrive.
 // ---------------------------------------------------------------------------
-template <class R, int RADIX, bool INV, bool TWFULL, int L, int NS, int NBATCH, int BSTRIDE, int NTHR, int M>
-__device__ __forceinline__ void fft_stage_pp(const C2<R>* a, C2<R>* b, const C2<R>* twq, int tid) {
+// Stage S (twiddles from tc for S < TC::SLIM, else from the LDS table).
+template <class R, int RADIX, bool INV, bool TWFULL, int L, int NS, int NBATCH, int BSTRIDE, int NTHR, int M, int S,
+          class TC>
+__device__ __forceinline__ void fft_stage_pp(const C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, const TC& tc) {
     constexpr int NB = L / RADIX;
     constexpr int TOTAL = NB * NBATCH;
     constexpr int MAXB = (TOTAL + NTHR - 1) / NTHR;
@@ -587,7 +675,11 @@ __device__ __forceinline__ void fft_stage_pp(const C2<R>* a, C2<R>* b, const C2<
 #pragma unroll
                 for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
             }
-            if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, k * TWSTEP, M4);
+            if constexpr (S < TC::SLIM) {
+                if (NS > 1) apply_twiddles_base<R, RADIX>(v, tc.w[S][i]);
+            } else {
+                if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, k * TWSTEP, M4);
+            }
             dft<R, RADIX, INV>(v);
             const int ob = t * BSTRIDE + q * NS * RADIX + k;
             if constexpr (pad_linear_write(NS, RADIX, BSTRIDE)) {
@@ -605,32 +697,36 @@ __device__ __forceinline__ void fft_stage_pp(const C2<R>* a, C2<R>* b, const C2<
 
 // Stages S.. of the transform, the first reading `a`; returns the buffer
 // that holds the result.
-template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S, int NS>
-__device__ __forceinline__ C2<R>* fft_static_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid) {
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S, int NS,
+          class TC = NoTw>
+__device__ __forceinline__ C2<R>* fft_static_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, const TC& tc = TC{}) {
     constexpr int RADIX = static_radix(L, S);
     if constexpr (RADIX == 0) {
         return a;
     } else {
-        fft_stage_pp<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(a, b, twq, tid);
-        return fft_static_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(b, a, twq, tid);
+        fft_stage_pp<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M, S>(a, b, twq, tid, tc);
+        return fft_static_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(b, a, twq, tid, tc);
     }
 }
 
 // fft_static_in on two buffers: the first stage's inputs come from g(slot)
 // and go to `a`; returns the buffer holding the result.  The caller
 // guarantees that no thread still reads `a`.
-template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, class G>
-__device__ __forceinline__ C2<R>* fft_static_in_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, G&& g) {
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, class G, class TC = NoTw>
+__device__ __forceinline__ C2<R>* fft_static_in_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, G&& g,
+                                                   const TC& tc = TC{}) {
     fft_static_first<R, INV, L, NBATCH, BSTRIDE, NTHR, false>(a, tid, g);
-    return fft_static_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, 1, static_radix(L, 0)>(a, b, twq, tid);
+    return fft_static_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, 1, static_radix(L, 0)>(a, b, twq, tid, tc);
 }
 
 // fft_static_out on two buffers, from stage S reading `a`: the last stage
 // hands its outputs to f and is followed by no barrier.  Returns the buffer
 // the last stage read, which threads may still be reading on return; the
 // other one is free.
-template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S, int NS, class F>
-__device__ __forceinline__ C2<R>* fft_static_out_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, F&& f) {
+template <class R, bool INV, bool TWFULL, int L, int NBATCH, int BSTRIDE, int NTHR, int M, int S, int NS, class F,
+          class TC = NoTw>
+__device__ __forceinline__ C2<R>* fft_static_out_pp(C2<R>* a, C2<R>* b, const C2<R>* twq, int tid, F&& f,
+                                                    const TC& tc = TC{}) {
     constexpr int RADIX = static_radix(L, S);
     if constexpr (static_radix(L, S + 1) == 0) {
         constexpr int NB = L / RADIX;
@@ -655,7 +751,11 @@ __device__ __forceinline__ C2<R>* fft_static_out_pp(C2<R>* a, C2<R>* b, const C2
 #pragma unroll
                     for (int r = 0; r < RADIX; ++r) v[r] = a[lds_pad(ib + r * NB)];
                 }
-                if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, j * TWSTEP, M4);
+                if constexpr (S < TC::SLIM) {
+                    if (NS > 1) apply_twiddles_base<R, RADIX>(v, tc.w[S][i]);
+                } else {
+                    if (NS > 1) apply_twiddles<R, RADIX, INV, TWFULL>(v, twq, j * TWSTEP, M4);
+                }
                 dft<R, RADIX, INV>(v);
 #pragma unroll
                 for (int r = 0; r < RADIX; ++r) f(i * RADIX + r, t, j + r * NS, v[r]);
@@ -663,8 +763,8 @@ __device__ __forceinline__ C2<R>* fft_static_out_pp(C2<R>* a, C2<R>* b, const C2
         }
         return a;
     } else {
-        fft_stage_pp<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M>(a, b, twq, tid);
-        return fft_static_out_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(b, a, twq, tid, f);
+        fft_stage_pp<R, RADIX, INV, TWFULL, L, NS, NBATCH, BSTRIDE, NTHR, M, S>(a, b, twq, tid, tc);
+        return fft_static_out_pp<R, INV, TWFULL, L, NBATCH, BSTRIDE, NTHR, M, S + 1, NS * RADIX>(b, a, twq, tid, f, tc);
     }
 }
 

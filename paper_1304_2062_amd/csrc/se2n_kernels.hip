@@ -69,7 +69,7 @@ __global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
-    row_fwd_tile<R, SRC, EPT, TWF, MS>(f, mask, rmap, vol, spec, M, rows, nthr, rb, s_begin, s_end, planH, tw,
+    row_fwd_tile<R, SRC, EPT, TWF, MS, true>(f, mask, rmap, vol, spec, M, rows, nthr, rb, s_begin, s_end, planH, tw,
                                        buf, threadIdx.x, MS ? buf + row_buf_elems(M, rows) : nullptr);
 }
 
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec
     const int s_begin = grp * slices_per_group;
     const int s_end = min(nslices, s_begin + slices_per_group);
     load_twiddles<R>(tw, twg, M >> 2, TWF, threadIdx.x, nthr);
-    row_inv_tile<R, DST, EPT, TWF, MS, PAIRED, BLK>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N,
+    row_inv_tile<R, DST, EPT, TWF, MS, PAIRED, BLK, true>(spec, out, enc, rmap, M, rows, nthr, rb, s_begin, s_end, N,
                                                out_scale, planH, tw, buf, threadIdx.x,
                                                MS ? buf + row_buf_elems(M, rows) : nullptr);
 }

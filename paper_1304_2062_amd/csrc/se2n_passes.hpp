@@ -54,7 +54,9 @@ __device__ __forceinline__ void split_index(int tid, int i, int nthr, int d, flo
 // z[n] = x[2n] + i x[2n+1]:  with Z = FFT_H(z), H = M/2,
 //   X[k] = (Z[k] + conj Z[H-k])/2 + w_M^k (Z[k] - conj Z[H-k])/(2i),  k = 0..H.
 // MS != 0: compiled for M = MS with the geometry geom_core<R>(MS).
-template <class R, int SRC, int EPT, bool TWF, int MS>
+// TWC: the fixed-size two-buffer stages keep their twiddles in registers
+// (StageTw), read once per tile (the caller has put the table in LDS).
+template <class R, int SRC, int EPT, bool TWF, int MS, bool TWC = false>
 __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint8_t* __restrict__ mask,
                                              const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
                                              C2<R>* __restrict__ spec, int M_, int rows_, int nthr_, int rb,
@@ -118,6 +120,13 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
     const bool pp = MS != 0 && buf2 != nullptr;
     C2<R>* bx = buf;
     C2<R>* by = buf2;
+    using TwC = StageTw<R, false, TWF, MS ? MS / 2 : 8, GC.rows, GC.row_threads, MS ? MS : 16,
+                        MS != 0 && TWC ? static_nstages(MS ? MS / 2 : 8) : 1>;
+    TwC twc;
+    if constexpr (MS != 0 && TWC) {
+        __syncthreads();  // the twiddle table is in LDS
+        twc.load(tw, tid);
+    }
     for (int s = s_begin; s < s_end; ++s) {
         // input element i of this slice (zero where unused)
         auto input = [&](int i) {
@@ -138,9 +147,14 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
         };
         C2<R>* res = buf;
         if constexpr (MS != 0) {
-            if (pp)
-                res = fft_static_in_pp<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(bx, by, tw, tid,
-                                                                                                      input);
+            if (pp) {
+                if constexpr (TWC)
+                    res = fft_static_in_pp<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
+                        bx, by, tw, tid, input, twc);
+                else
+                    res = fft_static_in_pp<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(
+                        bx, by, tw, tid, input);
+            }
             else
                 fft_static_in<R, false, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS>(buf, tw, tid, input);
         } else {
@@ -663,7 +677,8 @@ __device__ __forceinline__ void col_orient_tile(C2<R>* __restrict__ spec, int M,
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED = false, bool BLK = false>
+// TWC: as for row_fwd_tile, for the stages before the last (registers).
+template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED = false, bool BLK = false, bool TWC = false>
 __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* __restrict__ out,
                                              typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                                              int M_, int rows_, int nthr_, int rb, int s_begin, int s_end, int N,
@@ -732,6 +747,15 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const bool pp = DIRECT && buf2 != nullptr;
     C2<R>* bx = buf;
     C2<R>* by = buf2;
+    // (not for the orientation pass: two slices only, and no registers to spare)
+    constexpr bool CACHE = DIRECT && TWC && DST != DST_ORIENT;
+    using TwC = StageTw<R, true, TWF, MS ? MS / 2 : 8, GC.rows, GC.row_threads, MS ? MS : 16,
+                        CACHE ? static_nstages(MS ? MS / 2 : 8) - 1 : 1>;
+    TwC twc;
+    if constexpr (CACHE) {
+        __syncthreads();  // the twiddle table is in LDS
+        twc.load(tw, tid);
+    }
     // consume output element i (row, pixel pair n) of slice s
     auto take = [&](int s, int i, int row, int n, C2<R> z) {
         if (DST == DST_VOLUME) {
@@ -793,7 +817,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
             constexpr int R0 = static_radix(MS / 2, 0);
             if (pp) {
                 C2<R>* last = fft_static_out_pp<R, true, TWF, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, MS, 1, R0>(
-                    bx, by, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(s, slot, t, n, z); });
+                    bx, by, tw, tid, [&](int slot, int t, int n, C2<R> z) { take(s, slot, t, n, z); }, twc);
                 // the last stage may still be reading `last`: the next first stage fills the other one
                 by = last;
                 bx = (last == buf) ? buf2 : buf;
