@@ -677,7 +677,7 @@ __device__ __forceinline__ void col_orient_tile(C2<R>* __restrict__ spec, int M,
 // With Z[k] = (X[k] + conj X[H-k]) + i w_M^{-k} (X[k] - conj X[H-k]), k < H,
 // the unnormalised inverse FFT_H of Z is M (x[2n] + i x[2n+1]).
 // ---------------------------------------------------------------------------
-// TWC: as for row_fwd_tile, for the stages before the last (registers).
+// TWC: as for row_fwd_tile (twiddles of every stage in registers).
 template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED = false, bool BLK = false, bool TWC = false>
 __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* __restrict__ out,
                                              typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
@@ -750,7 +750,7 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     // (not for the orientation pass: two slices only, and no registers to spare)
     constexpr bool CACHE = DIRECT && TWC && DST != DST_ORIENT;
     using TwC = StageTw<R, true, TWF, MS ? MS / 2 : 8, GC.rows, GC.row_threads, MS ? MS : 16,
-                        CACHE ? static_nstages(MS ? MS / 2 : 8) - 1 : 1>;
+                        CACHE ? static_nstages(MS ? MS / 2 : 8) : 1>;
     TwC twc;
     if constexpr (CACHE) {
         __syncthreads();  // the twiddle table is in LDS
