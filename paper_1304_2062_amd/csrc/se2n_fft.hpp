@@ -12,11 +12,24 @@
 #include <hip/hip_runtime.h>
 
 #include <type_traits>
+#include <utility>
 
 namespace se2n {
 
 template <class R>
 using C2 = typename std::conditional<std::is_same<R, float>::value, float2, double2>::type;
+
+// f(0), f(1), ..., f(N - 1) with compile-time indices, so that a register
+// array indexed by them never needs memory (an unroll pragma leaves that to
+// the optimiser).
+template <class F, int... I>
+__device__ __forceinline__ void static_for_impl(F&& f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, class F>
+__device__ __forceinline__ void static_for(F&& f) {
+    static_for_impl(f, std::make_integer_sequence<int, N>{});
+}
 
 template <class R>
 __device__ __forceinline__ C2<R> cmk(R x, R y) {

@@ -95,6 +95,8 @@ __host__ __device__ constexpr void fft_threads_of(int elems, int& threads, int& 
     }
 }
 
+constexpr int kRowThreadsF64 = 512;  // threads of an FP64 row-pass workgroup, at most
+
 template <class R>
 __host__ __device__ constexpr GeomCore geom_core(int M) {
     GeomCore g{};
@@ -112,7 +114,10 @@ __host__ __device__ constexpr GeomCore geom_core(int M) {
 #ifndef SE2N_ROW_MAX_THREADS
 #define SE2N_ROW_MAX_THREADS 1024
 #endif
-    if (g.row_threads > SE2N_ROW_MAX_THREADS && g.row_ept == 8) {  // 16 elements per thread, half the threads
+    // FP64 row workgroups stay at 512 threads (their kernels are bounded
+    // to 512 threads and get 256 registers per thread)
+    const int max_threads = sizeof(R) == 8 ? kRowThreadsF64 : SE2N_ROW_MAX_THREADS;
+    if (g.row_threads > max_threads && g.row_ept == 8) {  // 16 elements per thread, half the threads
         g.row_ept = 16;
         g.row_threads = (rows * H + 15) / 16;
     }

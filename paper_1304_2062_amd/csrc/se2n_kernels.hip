@@ -53,7 +53,7 @@ __device__ __forceinline__ void row_block_of(int nrb, int ngroups, bool pair, in
 // Row passes: grid (M/rows row blocks) x (slice groups) on a 1-D grid;
 // block: nthr threads; LDS: twiddles + rows x (H+2) (padded).
 template <class R, int SRC, int EPT, bool TWF, int MS>
-__global__ __launch_bounds__(1024) void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
+__global__ __launch_bounds__(sizeof(R) == 8 ? kRowThreadsF64 : 1024) void k_row_fwd(const R* __restrict__ f, const uint8_t* __restrict__ mask,
                           const uint8_t* __restrict__ rmap, const R* __restrict__ vol,
                           C2<R>* __restrict__ spec, int M_, int nslices, int slices_per_group,
                           int rows_, int xcd_pair, FftPlan planH, const C2<R>* __restrict__ twg) {
@@ -107,7 +107,7 @@ __global__ void k_col_orient(C2<R>* __restrict__ spec, int M, int cols_per_block
 }
 
 template <class R, int DST, int EPT, bool TWF, int MS, bool PAIRED, bool BLK = false>
-__global__ __launch_bounds__(1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
+__global__ __launch_bounds__(sizeof(R) == 8 ? kRowThreadsF64 : 1024) void k_row_inv(const C2<R>* __restrict__ spec, R* __restrict__ out,
                           typename Enc<R>::U* __restrict__ enc, uint8_t* __restrict__ rmap,
                           int M_, int nslices, int slices_per_group, int rows_, int xcd_pair, int N,
                           R out_scale, FftPlan planH, const C2<R>* __restrict__ twg) {

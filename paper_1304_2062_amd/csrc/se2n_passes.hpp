@@ -717,7 +717,12 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     const int kx_t = tid >> rshift;
     const int kstep = nthr >> rshift;
     const int KL = PAIRED ? H : K;       // columns the transform reads
-    C2<R> pre[MAXL];
+    // held as native two-element vectors: an array of the C2 class type is
+    // kept in memory by the FP64 build (scratch), a vector array is not
+    typedef R pv_t __attribute__((ext_vector_type(2)));
+    pv_t pre[MAXL];
+    auto pv = [](C2<R> z) { pv_t v; v.x = z.x; v.y = z.y; return v; };
+    auto cv = [](pv_t v) { return cmk<R>(v.x, v.y); };
     // Fixed-size paired transforms take the first stage's inputs straight
     // from the prefetch registers: slot i holds (row t, column n) of the
     // thread's first-stage butterfly, rows fastest across lanes so that 8
@@ -733,13 +738,14 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
             _Pragma("unroll") for (int i = 0; i < static_in_slots(MS / 2, GC.rows, GC.row_threads); ++i) { \
                 int t_, n_;                                                                            \
                 if (static_in_pos<MS / 2, GC.rows, GC.row_threads, true>(tid, i, t_, n_))              \
-                    pre[i] = spec[(size_t)(SL) * K * M +                                               \
-                                  (BLK ? row_blk_index(n_, y0 + t_, H) : (long)n_ * M + y0 + t_)];     \
+                    pre[i] = pv(spec[(size_t)(SL) * K * M +                                            \
+                                     (BLK ? row_blk_index(n_, y0 + t_, H) : (long)n_ * M + y0 + t_)]); \
             }                                                                                          \
         } else {                                                                                       \
             const C2<R>* in_ = spec + (size_t)(SL) * K * M + (size_t)kx_t * M + y0 + row_t;            \
-            _Pragma("unroll") for (int i = 0; i < MAXL; ++i) if (kx_t + i * kstep < KL) pre[i] =        \
-                in_[(size_t)(i * kstep) * M];                                                          \
+            static_for<MAXL>([&](auto I) {                                                             \
+                if (kx_t + I * kstep < KL) pre[I] = pv(in_[(size_t)(I * kstep) * M]);                  \
+            });                                                                                        \
         }                                                                                              \
     } while (0)
     // Fixed-size paired transforms with a second buffer (buf2) run their
@@ -779,14 +785,13 @@ __device__ __forceinline__ void row_inv_tile(const C2<R>* __restrict__ spec, R* 
     for (int s = s_end - 1; s >= s_begin; --s) {
       if constexpr (DIRECT) {
         fft_static_first<R, true, MS / 2, GC.rows, MS / 2 + 2, GC.row_threads, true>(
-            pp ? bx : buf, tid, [&](int i) { return pre[i]; });
+            pp ? bx : buf, tid, [&](int i) { return cv(pre[i]); });
         if (s > s_begin) SE2N_FETCH(s - 1);
       } else {
-#pragma unroll
-        for (int i = 0; i < MAXL; ++i) {
-            const int kx = kx_t + i * kstep;
-            if (kx < KL) buf[lds_pad(row_t * S + kx)] = pre[i];
-        }
+        static_for<MAXL>([&](auto I) {
+            const int kx = kx_t + I * kstep;
+            if (kx < KL) buf[lds_pad(row_t * S + kx)] = cv(pre[I]);
+        });
         __syncthreads();
         if (s > s_begin) SE2N_FETCH(s - 1);
         if constexpr (!PAIRED) {
