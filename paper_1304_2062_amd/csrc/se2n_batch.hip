@@ -34,6 +34,10 @@ static_assert(row_nt<1024>() <= BT && row_nt<768>() <= BT && row_nt<192>() <= BT
 
 using C = C2<float>;
 
+// Rows per row tile of a compiled side (where its second row buffer starts).
+template <int MS>
+constexpr int kBatchRows = geom_core<float>(MS ? MS : 16).rows;
+
 // The thread index, hidden from loop-invariant code motion: the tile bodies
 // derive many per-thread addresses from it, and hoisting them out of the
 // tile loop would keep all of them live across it.
@@ -85,9 +89,9 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         C* buf = tw + tw_elems(M, true);
         __syncthreads();
         ensure_twiddles<true>(tw, uni(d.tw), M, cur, row_nt<MS>());
-        row_fwd_tile<float, SRC, 8, true, MS>(uni(d.f), uni(d.mask), SRC == SRC_LIFT ? uni(d.rmap) : nullptr, nullptr,
-                                              uni(d.spec), M, uni(d.rows), BT, tl.y, tl.z, tl.w, d.planH, tw, buf,
-                                              opaque_tid());
+        row_fwd_tile<float, SRC, 8, true, MS, kBatchTwoBuf<MS>>(
+            uni(d.f), uni(d.mask), SRC == SRC_LIFT ? uni(d.rmap) : nullptr, nullptr, uni(d.spec), M, uni(d.rows), BT,
+            tl.y, tl.z, tl.w, d.planH, tw, buf, opaque_tid(), kBatchTwoBuf<MS> ? buf + row_buf_elems(M, kBatchRows<MS>) : nullptr);
     }
 }
 
@@ -187,9 +191,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         ensure_twiddles<true>(tw, uni(d.tw), M, cur, row_nt<MS>());
         unsigned* enc = (DST == DST_MAX && uni(d.groups) > 1) ? uni(d.enc) : nullptr;
         const float sc = DST == DST_SUM ? 1.0f / (float)N : 1.0f;
-        row_inv_tile<float, DST, 8, true, MS, PAIRED>(uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
-                                              DST == DST_ORIENT ? uni(d.rmap) : nullptr, M, uni(d.rows), BT, tl.y,
-                                              tl.z, tl.w, N, sc, d.planH, tw, buf, opaque_tid());
+        constexpr bool TWO = kBatchTwoBuf<MS> && PAIRED;
+        row_inv_tile<float, DST, 8, true, MS, PAIRED, false, TWO>(
+            uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc, DST == DST_ORIENT ? uni(d.rmap) : nullptr, M,
+            uni(d.rows), BT, tl.y, tl.z, tl.w, N, sc, d.planH, tw, buf, opaque_tid(),
+            TWO ? buf + row_buf_elems(M, kBatchRows<MS>) : nullptr);
     }
 }
 

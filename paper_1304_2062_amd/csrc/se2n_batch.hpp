@@ -61,6 +61,13 @@ inline int batch_class(int M) {
         if (kBatchSides[c] == M) return c;
     return 0;
 }
+// Sides whose batched row passes run their stages between two row buffers
+// with the stage twiddles in registers (the single-image kernels' form); their
+// row passes take a second row buffer of LDS.  The other classes keep one
+// buffer: with the tile loop's state the second one makes them spill.
+template <int MS>
+constexpr bool kBatchTwoBuf = MS == 512 || MS == 1024;
+inline bool batch_two_buf(int M) { return M == 512 || M == 1024; }
 
 // Launch one pass (size class `cls`, solve instance N): `grid` workgroups
 // walk tiles[0..ntiles) with stride grid.

@@ -564,12 +564,17 @@ int build_schedule(BatchPlan& bp) {
             const GeomCore g = geom_core<float>(M);
             size_t need = 0;
             switch (p.kind) {
+                case BK_ORIENT_INV:
+                    need = (size_t)(tw_elems(M, true) + lds_padded_size(g.rows * (H + 2))) * sizeof(C2<float>);
+                    break;
                 case BK_ORIENT_ROW:
                 case BK_LIFT_ROW:
-                case BK_ORIENT_INV:
                 case BK_ROW_INV_MAX:
                 case BK_ROW_INV_MEAN:
-                    need = (size_t)(tw_elems(M, true) + lds_padded_size(g.rows * (H + 2))) * sizeof(C2<float>);
+                    // two row buffers where the compiled stages run between them
+                    need = batch_two_buf(M)
+                               ? (size_t)(tw_elems(M, true) + 2 * row_buf_elems(M, g.rows)) * sizeof(C2<float>)
+                               : (size_t)(tw_elems(M, true) + lds_padded_size(g.rows * (H + 2))) * sizeof(C2<float>);
                     break;
                 case BK_COL_FWD:
                     need = (size_t)(tw_elems(M, false) + lds_padded_size(g.cols * M)) * sizeof(C2<float>);
