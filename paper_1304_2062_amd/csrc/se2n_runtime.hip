@@ -13,6 +13,7 @@
 #include <map>
 #include <mutex>
 #include <string>
+#include <thread>
 #include <tuple>
 #include <type_traits>
 #include <vector>
@@ -144,21 +145,39 @@ int orient_stencil_taps(int M, double sigma, OrientTaps* taps) {
         c[k] = std::cos(two_pi * k / M);
         s[k] = std::sin(two_pi * k / M);
     }
-    for (int x = 0; x <= M / 2; ++x) {
-        double sg = 0.0, sd = 0.0;
-        int idx = 0;  // k x mod M
-        for (int k = 0; k < M; ++k) {
-            sg += G[k] * c[idx];
-            sd += s[k] * G[k] * s[idx];
-            idx += x;
-            if (idx >= M) idx -= M;
+    // the M/2 + 1 sums are independent: large sides split them over a few
+    // host threads (each sum is the same sequence of operations, so the taps
+    // do not depend on the split)
+    auto sums = [&](int x0, int x1) {
+        for (int x = x0; x < x1; ++x) {
+            double sg = 0.0, sd = 0.0;
+            int idx = 0;  // k x mod M
+            for (int k = 0; k < M; ++k) {
+                sg += G[k] * c[idx];
+                sd += s[k] * G[k] * s[idx];
+                idx += x;
+                if (idx >= M) idx -= M;
+            }
+            g[x] = sg / M;
+            d[x] = -std::sqrt((double)M) / M * sd;
+            if (x > 0 && x < M - x) {
+                g[M - x] = g[x];
+                d[M - x] = -d[x];
+            }
         }
-        g[x] = sg / M;
-        d[x] = -std::sqrt((double)M) / M * sd;
-        if (x > 0 && x < M - x) {
-            g[M - x] = g[x];
-            d[M - x] = -d[x];
+    };
+    const int nx = M / 2 + 1;
+    const unsigned hw = std::thread::hardware_concurrency();
+    const int nt = M < 512 ? 1 : (int)std::min<unsigned>(8u, hw ? hw : 1u);
+    if (nt <= 1) {
+        sums(0, nx);
+    } else {
+        std::vector<std::thread> pool;
+        for (int t = 0; t < nt; ++t) {
+            const int x0 = (int)((long)nx * t / nt), x1 = (int)((long)nx * (t + 1) / nt);
+            pool.emplace_back(sums, x0, x1);
         }
+        for (auto& th : pool) th.join();
     }
     // absolute mass at circular distance r, then the smallest radius whose
     // dropped tail is below 2^-26 of the kernel's absolute sum
