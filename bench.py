@@ -129,10 +129,15 @@ def measured_traffic(kernel: str):
         rec = json.load(fh)
     if rec.get("source_hash") != kernel_source_hash():
         return None
+    # several instances can match the prefix (the warm-up plan's, for another
+    # side or N, run once): take the one the profiled run dispatched most
+    best = None
     for k, v in rec["kernels"].items():
         if k.startswith(ROCPROF_NAME[kernel]):
-            return v["fetch_bytes"] + v["write_bytes"]
-    return None
+            key = (v.get("dispatches", 0), v["fetch_bytes"] + v["write_bytes"])
+            if best is None or key > best[0]:
+                best = (key, v)
+    return None if best is None else best[1]["fetch_bytes"] + best[1]["write_bytes"]
 
 
 def cpu_model() -> str:
@@ -642,10 +647,13 @@ def main() -> int:
     rmap = torch.empty((M, M), dtype=torch.uint8, device=dev)
     plan = se2n.Plan(M, N, torch.float32)
     plan.workspace()
-    # load the library's code objects once (a small plan's propagators), so
-    # that the cold call below measures what a new (T, beta, n) costs
-    warm = se2n.Plan(64, N, torch.float32)
-    warm.precompute(T, beta, n)
+    # load the library's code objects once (a whole inpaint of a small plan,
+    # which launches a kernel from every module of the path), so that the
+    # cold call below measures what a new (T, beta, n) costs; its N and sigma
+    # differ from the workload's, so none of its kernels shares a name with
+    # the timed ones (profiles average per kernel name)
+    warm = se2n.Plan(64, 16, torch.float32)
+    warm.inpaint(f[:64, :64].contiguous(), mask[:64, :64].contiguous(), T, beta, n, sigma=1.0)
     torch.cuda.synchronize()
     warm.close()
 

@@ -87,3 +87,26 @@ def test_skipping_solve_and_inverse_bytes(M, N):
     # skipping removes exactly the writes of the negligible modes
     neg_modes = N * (bench.live_modes(M, none) - bench.live_modes(M, flags)) * 8
     assert bench.solve_bytes(M, N, flags, 4, False) - bench.solve_bytes(M, N, flags, 4, True) == neg_modes
+
+
+def test_measured_traffic_takes_the_workload_instance(tmp_path, monkeypatch):
+    """The counter record lists every instance that matches a pass's name
+    prefix (the warm-up plan's run once); the lookup takes the one the
+    profiled run dispatched most, and nothing once the sources changed."""
+    import json
+
+    from paper_1304_2062_amd.profile_summary import kernel_source_hash
+
+    rec = {"source_hash": kernel_source_hash(), "kernels": {
+        "k_col_inv_paired<float,8,0,false,false>": {"fetch_bytes": 7.0e5, "write_bytes": 5.0e5, "dispatches": 1},
+        "k_col_inv_paired<float,8,2048,true,true>": {"fetch_bytes": 3.24e8, "write_bytes": 5.37e8, "dispatches": 12},
+    }}
+    (tmp_path / "profiles").mkdir()
+    path = tmp_path / "profiles" / "traffic_inpaint_2048_N32.json"
+    path.write_text(json.dumps(rec))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    assert bench.measured_traffic("col_fft_inv") == pytest.approx(8.61e8)
+    assert bench.measured_traffic("solve") is None
+    rec["source_hash"] = "0" * 16
+    path.write_text(json.dumps(rec))
+    assert bench.measured_traffic("col_fft_inv") is None
