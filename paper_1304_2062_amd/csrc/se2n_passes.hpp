@@ -171,8 +171,10 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
         // b = Z[(H - k) mod H] and one twiddle (w_M^{H-k} = -conj w_M^k):
         //   s = a + conj b,  u = w_M^k (a - conj b) / 2,
         //   X[k] = s/2 - i u,  X[H - k] = conj(s/2 + i u)
-        // (k = 0 gives X[0] and X[H]; k = H/2 gives X[H/2] once).  Thread t
-        // takes row t mod rows, so 8 lanes write one 64-byte segment.
+        // (k = 0 gives X[0] and X[H]; k = H/2 gives X[H/2] once).  On the
+        // compiled sides a lane takes two adjacent rows of a column, so four
+        // lanes write one 64-byte segment; the generic loop takes unit e as
+        // (row e mod rows, k = e / rows).
         C2<R>* out = spec + (size_t)s * K * M + y0;
         const int H2 = H >> 1;
         const int rshift = __ffs(rows) - 1;  // rows is a power of two
@@ -187,37 +189,49 @@ __device__ __forceinline__ void row_fwd_tile(const R* __restrict__ f, const uint
         constexpr int KSTEP = MS != 0 ? GC.row_threads / GC.rows : 1;
         constexpr bool LINU = MS != 0 && GC.row_threads % GC.rows == 0 && KSTEP % kLdsPadPeriod == 0 &&
                               KSTEP % (1 << SE2N_TW_PAD_SHIFT) == 0;
-        if constexpr (LINU) {
-            // unit it of thread t is (row, k0 + it KSTEP): every LDS position
-            // is the first one plus a constant (KSTEP is a multiple of both
-            // padding periods), and so is every output line
-            constexpr int NU = GC.rows * (MS / 4 + 1);
+        // row pairs: a lane takes rows 2p and 2p + 1 of its columns, whose
+        // outputs are adjacent, so it writes them with one 16-byte store
+        // and reads one twiddle for both
+        constexpr int NRP = MS != 0 ? GC.rows / 2 : 1;
+        constexpr int KSTEP2 = MS != 0 ? GC.row_threads / NRP : 1;
+        constexpr bool PAIRS = LINU && sizeof(R) == 4 && GC.rows % 2 == 0 &&
+                               GC.row_threads % NRP == 0 && KSTEP2 % kLdsPadPeriod == 0 &&
+                               KSTEP2 % (1 << SE2N_TW_PAD_SHIFT) == 0;
+        if constexpr (PAIRS) {
+            typedef R v4_t __attribute__((ext_vector_type(4)));
+            constexpr int NU = NRP * (MS / 4 + 1);
             constexpr int FULLIT = NU / GC.row_threads;
-            constexpr int LSTEP = KSTEP + KSTEP / kLdsPadPeriod;
-            constexpr int TSTEP = KSTEP + (KSTEP >> SE2N_TW_PAD_SHIFT);
-            const int row = tid & (GC.rows - 1);
-            const int k0 = tid >> rshift;
-            const C2<R>* pa = res + lds_pad(row * S + k0);
-            const C2<R>* pb = res + lds_pad(row * S + H - k0);
-            const C2<R>* pb0 = k0 == 0 ? pa : pb;  // Z[H] is Z[0]
+            constexpr int LSTEP = KSTEP2 + KSTEP2 / kLdsPadPeriod;
+            constexpr int TSTEP = KSTEP2 + (KSTEP2 >> SE2N_TW_PAD_SHIFT);
+            const int rp = tid & (NRP - 1);
+            const int k0 = tid / NRP;
+            const int r0 = 2 * rp;
+            const C2<R>* pa0 = res + lds_pad(r0 * S + k0);
+            const C2<R>* pa1 = res + lds_pad((r0 + 1) * S + k0);
+            const C2<R>* pb0 = res + lds_pad(r0 * S + H - k0);
+            const C2<R>* pb1 = res + lds_pad((r0 + 1) * S + H - k0);
+            const C2<R>* pz0 = k0 == 0 ? pa0 : pb0;  // Z[H] is Z[0]
+            const C2<R>* pz1 = k0 == 0 ? pa1 : pb1;
             const C2<R>* pw = tw + tw_pos(k0);
-            C2<R>* ok = out + (size_t)k0 * MS + row;
-            C2<R>* oh = out + (size_t)(H - k0) * MS + row;
-            constexpr long LB = (long)KSTEP * MS;  // elements between a thread's output lines
+            v4_t* ok = reinterpret_cast<v4_t*>(out + (size_t)k0 * MS + r0);
+            v4_t* oh = reinterpret_cast<v4_t*>(out + (size_t)(H - k0) * MS + r0);
+            constexpr long LB = (long)KSTEP2 * MS / 2;  // 16-byte units between a thread's output lines
+            auto unit = [&](int it, bool both) {
+                const C2<R> w = pw[it * TSTEP];
+                C2<R> xk0, xh0, xk1, xh1;
+                pair_out(pa0[it * LSTEP], it == 0 ? pz0[0] : pb0[-it * LSTEP], w, xk0, xh0);
+                pair_out(pa1[it * LSTEP], it == 0 ? pz1[0] : pb1[-it * LSTEP], w, xk1, xh1);
+                v4_t a, b;
+                a.x = xk0.x; a.y = xk0.y; a.z = xk1.x; a.w = xk1.y;
+                b.x = xh0.x; b.y = xh0.y; b.z = xh1.x; b.w = xh1.y;
+                ok[it * LB] = a;
+                if (both) oh[-it * LB] = b;
+            };
 #pragma unroll
-            for (int it = 0; it < FULLIT; ++it) {
-                C2<R> xk, xh;
-                pair_out(pa[it * LSTEP], it == 0 ? pb0[0] : pb[-it * LSTEP], pw[it * TSTEP], xk, xh);
-                ok[it * LB] = xk;
-                oh[-it * LB] = xh;
-            }
+            for (int it = 0; it < FULLIT; ++it) unit(it, true);
             if (tid + FULLIT * GC.row_threads < NU) {
-                // k = k0 + FULLIT KSTEP <= H/2; the unit k = H/2 writes X[H/2] once
-                const int k = k0 + FULLIT * KSTEP;
-                C2<R> xk, xh;
-                pair_out(pa[FULLIT * LSTEP], FULLIT == 0 ? pb0[0] : pb[-FULLIT * LSTEP], pw[FULLIT * TSTEP], xk, xh);
-                ok[FULLIT * LB] = xk;
-                if (k != H2) oh[-FULLIT * LB] = xh;
+                // k = k0 + FULLIT KSTEP2 <= H/2; the unit k = H/2 writes X[H/2] once
+                unit(FULLIT, k0 + FULLIT * KSTEP2 != H2);
             }
         } else {
             for (int e = tid; e < rows * (H2 + 1); e += nthr) {
