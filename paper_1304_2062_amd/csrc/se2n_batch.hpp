@@ -20,6 +20,8 @@ struct BItem {
     uint8_t* rmap;     // orientation map (caller's rmap_out or workspace)
     float* out;
     C2<float>* spec;   // half-spectrum volume [N][M/2+1][M] (workspace)
+    C2<float>* blk;    // row-blocked second volume between the inverse passes
+                       // (sides with batch_two_buf, else null; workspace)
     unsigned* enc;     // max-combining buffer [M][M] (workspace)
     const float* P;    // propagator table of (M, N, T, beta, n, scheme)
     const C2<float>* tw;  // quarter-wave twiddles of M
@@ -68,6 +70,10 @@ inline int batch_class(int M) {
 template <int MS>
 constexpr bool kBatchTwoBuf = MS == 512 || MS == 1024;
 inline bool batch_two_buf(int M) { return M == 512 || M == 1024; }
+// The same sides run their inverse passes through a row-blocked second
+// volume (as the single-image path does): the inverse column pass writes it,
+// the inverse row pass reads it in 64-byte pieces of consecutive lines.
+static_assert(512 % kRowBlk == 0 && 1024 % kRowBlk == 0, "row blocks of the two-buffer sides");
 
 // Launch one pass (size class `cls`, solve instance N): `grid` workgroups
 // walk tiles[0..ntiles) with stride grid.

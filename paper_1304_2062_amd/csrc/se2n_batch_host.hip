@@ -116,7 +116,7 @@ const se2n_tune kDefaultTune = {2, 0, 1, 0};
 // Workspace layout and tiles (host only)
 // ---------------------------------------------------------------------------
 struct Layout {
-    std::vector<size_t> spec, enc, rmap;
+    std::vector<size_t> spec, blk, enc, rmap;  // blk: SIZE_MAX where the side has none
     size_t bytes = 0;
 };
 
@@ -125,8 +125,15 @@ Layout layout_of(const std::vector<Shape>& sh) {
     size_t off = 0;
     for (const Shape& x : sh) {
         const size_t M = (size_t)x.M, K = M / 2 + 1;
+        const size_t vol = align256((size_t)x.N * K * M * sizeof(C2<float>));
         L.spec.push_back(off);
-        off += align256((size_t)x.N * K * M * sizeof(C2<float>));
+        off += vol;
+        if (batch_two_buf(x.M)) {
+            L.blk.push_back(off);
+            off += vol;
+        } else {
+            L.blk.push_back(SIZE_MAX);
+        }
         L.enc.push_back(off);
         off += align256(M * M * sizeof(unsigned));
         L.rmap.push_back(off);
@@ -725,6 +732,7 @@ int upload_items(BatchPlan& bp, const se2n_item* items, void* ws, hipStream_t st
         n.out = it.out;
         n.rmap = it.rmap_out ? it.rmap_out : (uint8_t*)(base + bp.layout.rmap[i]);
         n.spec = (C2<float>*)(base + bp.layout.spec[i]);
+        n.blk = bp.layout.blk[i] == SIZE_MAX ? nullptr : (C2<float>*)(base + bp.layout.blk[i]);
         n.enc = (unsigned*)(base + bp.layout.enc[i]);
         n.groups = groups_of(bp.shapes[i], bp.tune);
         if (std::memcmp(&n, &b, sizeof(BItem)) != 0) {
