@@ -349,7 +349,7 @@ typedef struct {
 } se2n_tune;
 
 /* Device workspace bytes se2n_inpaint_batched needs for these items: per
- * item the half-spectrum volume (two for sides 512 and 1024, whose inverse
+ * item the half-spectrum volume (two for sides 512, 768 and 1024, whose inverse
  * passes go through a row-blocked copy), a max-combining buffer and an
  * orientation map.  Returns 0 if an item is invalid (see se2n_last_error). */
 size_t se2n_batch_workspace_bytes(const se2n_item *items, int count);

@@ -132,11 +132,11 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         C* buf = tw + tw_elems(M, false);
         __syncthreads();
         ensure_twiddles<false>(tw, uni(d.tw), M, cur, pcol_nt<MS>());
-        // the two-buffer sides write the row-blocked volume blk
-        col_inv_paired_tile<float, 8, MS, false, NoPre, kBatchTwoBuf<MS>>(
+        // the blocked sides write the row-blocked volume blk
+        col_inv_paired_tile<float, 8, MS, false, NoPre, kBatchBlocked<MS>>(
             uni(d.spec), M, uni(d.pcols), BT, tl.y, d.planM, tw, buf, opaque_tid(), 0,
             uni(d.imask) ? table_flags(uni(d.P), M, uni(d.N), 4) : nullptr, uni(d.FS), NoPre{}, -1,
-            kBatchTwoBuf<MS> ? uni(d.blk) : nullptr);
+            kBatchBlocked<MS> ? uni(d.blk) : nullptr);
     }
 }
 
@@ -194,9 +194,10 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         unsigned* enc = (DST == DST_MAX && uni(d.groups) > 1) ? uni(d.enc) : nullptr;
         const float sc = DST == DST_SUM ? 1.0f / (float)N : 1.0f;
         constexpr bool TWO = kBatchTwoBuf<MS> && PAIRED;
-        // the paired passes of the two-buffer sides read the row-blocked volume
-        row_inv_tile<float, DST, 8, true, MS, PAIRED, TWO, TWO>(
-            TWO ? uni(d.blk) : uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
+        constexpr bool BLK = kBatchBlocked<MS> && PAIRED;
+        // the paired passes of the blocked sides read the row-blocked volume
+        row_inv_tile<float, DST, 8, true, MS, PAIRED, BLK, TWO>(
+            BLK ? uni(d.blk) : uni(d.spec), DST == DST_ORIENT ? nullptr : uni(d.out), enc,
             DST == DST_ORIENT ? uni(d.rmap) : nullptr, M,
             uni(d.rows), BT, tl.y, tl.z, tl.w, N, sc, d.planH, tw, buf, opaque_tid(),
             TWO ? buf + row_buf_elems(M, kBatchRows<MS>) : nullptr);

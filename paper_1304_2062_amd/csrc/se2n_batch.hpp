@@ -70,10 +70,13 @@ inline int batch_class(int M) {
 template <int MS>
 constexpr bool kBatchTwoBuf = MS == 512 || MS == 1024;
 inline bool batch_two_buf(int M) { return M == 512 || M == 1024; }
-// The same sides run their inverse passes through a row-blocked second
-// volume (as the single-image path does): the inverse column pass writes it,
-// the inverse row pass reads it in 64-byte pieces of consecutive lines.
-static_assert(512 % kRowBlk == 0 && 1024 % kRowBlk == 0, "row blocks of the two-buffer sides");
+// Sides whose inverse passes go through a row-blocked second volume (as the
+// single-image path does): the inverse column pass writes it, the inverse
+// row pass reads it in 64-byte pieces of consecutive lines.
+template <int MS>
+constexpr bool kBatchBlocked = MS == 512 || MS == 768 || MS == 1024;
+inline bool batch_blocked(int M) { return M == 512 || M == 768 || M == 1024; }
+static_assert(512 % kRowBlk == 0 && 768 % kRowBlk == 0 && 1024 % kRowBlk == 0, "row blocks of the blocked sides");
 
 // Launch one pass (size class `cls`, solve instance N): `grid` workgroups
 // walk tiles[0..ntiles) with stride grid.

@@ -128,7 +128,7 @@ Layout layout_of(const std::vector<Shape>& sh) {
         const size_t vol = align256((size_t)x.N * K * M * sizeof(C2<float>));
         L.spec.push_back(off);
         off += vol;
-        if (batch_two_buf(x.M)) {
+        if (batch_blocked(x.M)) {
             L.blk.push_back(off);
             off += vol;
         } else {

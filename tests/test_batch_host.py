@@ -225,8 +225,8 @@ def test_workspace_bytes_is_the_sum_of_per_item_buffers(lib):
 
     def a256(x):
         return (x + 255) // 256 * 256
-    # sides 512 and 1024 hold a second, row-blocked spectrum for their inverse passes
-    want = sum((2 if M in (512, 1024) else 1) * a256(N * (M // 2 + 1) * M * 8) + a256(M * M * 4) + a256(M * M)
+    # sides 512, 768 and 1024 hold a second, row-blocked spectrum for their inverse passes
+    want = sum((2 if M in (512, 768, 1024) else 1) * a256(N * (M // 2 + 1) * M * 8) + a256(M * M * 4) + a256(M * M)
                for M, N, _ in SPECS)
     assert b == want
 
