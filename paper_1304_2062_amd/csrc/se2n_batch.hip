@@ -89,7 +89,9 @@ __global__ __launch_bounds__(BT) __attribute__((amdgpu_waves_per_eu(4))) void kb
         C* buf = tw + tw_elems(M, true);
         __syncthreads();
         ensure_twiddles<true>(tw, uni(d.tw), M, cur, row_nt<MS>());
-        row_fwd_tile<float, SRC, 8, true, MS, kBatchTwoBuf<MS>>(
+        // (the 512 class keeps its twiddles in LDS: with the tile loop's
+        // state, the register copy makes it spill)
+        row_fwd_tile<float, SRC, 8, true, MS, kBatchTwoBuf<MS> && MS != 512>(
             uni(d.f), uni(d.mask), SRC == SRC_LIFT ? uni(d.rmap) : nullptr, nullptr, uni(d.spec), M, uni(d.rows), BT,
             tl.y, tl.z, tl.w, d.planH, tw, buf, opaque_tid(), kBatchTwoBuf<MS> ? buf + row_buf_elems(M, kBatchRows<MS>) : nullptr);
     }
